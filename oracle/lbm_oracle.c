@@ -1,0 +1,478 @@
+/*
+ * lbm_oracle.c -- plain, slow FP64 reference of the SC-LBM hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * load this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header or table with the
+ * GPU library.
+ *
+ * What it computes (arXiv 2508.18202, Sec. 2.2 "Deterministic lattice
+ * Boltzmann method"):
+ *   - D3Q19 velocity set (Fig. 1), c_s^2 = 1/3;
+ *   - the lattice Boltzmann update of Eq. (deterministicLBE) with the
+ *     non-equilibrium part left unprojected (BGK), second-order equilibrium
+ *     (the truncation of the Hermite equilibrium of Sec. 2.2 at n = 2);
+ *   - effective relaxation time of Eq. (tauEff) with the Smagorinsky-Lilly
+ *     eddy viscosity of Eq. (turbVisc), |S| evaluated from the local
+ *     non-equilibrium stress;
+ *   - bounce-back walls/ground, a local velocity (moving-wall bounce-back)
+ *     inflow, a zero-gradient outflow and a free-slip sky (Sec. 2.2 boundary
+ *     list), plus periodic faces;
+ *   - the discrete adjoint of one step (not in the paper; used for the
+ *     inflow-parameter gradients).
+ *
+ * Storage: full populations f_i (not shifted), layout [q][z][y][x], x fastest.
+ * Every step is a two-lattice pull: f_out(x, i) = rule(x, i) applied to the
+ * post-collision populations of f_in.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NQ 19
+
+enum { F_WALL = 0, F_INLET = 1, F_OUTLET = 2, F_FREESLIP = 3, F_PERIODIC = 4 };
+enum { M_BGK = 0, M_SMAG = 1 };
+enum { IN_UNIFORM = 0, IN_LOGLAW = 1 };
+
+typedef struct {
+    int nx, ny, nz;
+    int face[6];                 /* -x, +x, -y, +y, -z, +z */
+    const unsigned char *solid;  /* nx*ny*nz, 1 = solid */
+    int model;
+    double tau0, cs;
+    int inflow;
+    double theta[3];             /* uniform: (U, phi, -); log-law: (u*, phi, z0) */
+    int ramp;                    /* inflow ramp length in steps (0 = none) */
+    double force[3];             /* uniform body force (Guo); zero in the workloads */
+} orc_case;
+
+/* D3Q19 velocities in the canonical order: rest, 6 faces (+x,-x,+y,-y,+z,-z),
+ * then the 12 edges (+x+y, -x-y, +x-y, -x+y, +x+z, -x-z, +x-z, -x+z,
+ * +y+z, -y-z, +y-z, -y+z).  Fig. 1 shows the set; the order is ours. */
+static const int C[NQ][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+};
+
+/* Weight from the energy shell |c|^2 = 0, 1, 2 (Fig. 1 caption). */
+static double weight(int i)
+{
+    int c2 = C[i][0] * C[i][0] + C[i][1] * C[i][1] + C[i][2] * C[i][2];
+    return c2 == 0 ? 1.0 / 3.0 : (c2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+/* Index of the velocity (a, b, c), found by search. */
+static int find_vel(int a, int b, int c)
+{
+    for (int j = 0; j < NQ; ++j)
+        if (C[j][0] == a && C[j][1] == b && C[j][2] == c) return j;
+    return -1;
+}
+
+static int opposite(int i) { return find_vel(-C[i][0], -C[i][1], -C[i][2]); }
+static int zflip(int i) { return find_vel(C[i][0], C[i][1], -C[i][2]); }
+
+static long cell_index(const orc_case *k, int x, int y, int z)
+{
+    return ((long)z * k->ny + y) * k->nx + x;
+}
+
+static long ncells(const orc_case *k) { return (long)k->nx * k->ny * k->nz; }
+
+static int wrap(int v, int n) { return ((v % n) + n) % n; }
+
+void orc_lattice(int *c_out, double *w_out, int *opp_out)
+{
+    for (int i = 0; i < NQ; ++i) {
+        for (int a = 0; a < 3; ++a) c_out[3 * i + a] = C[i][a];
+        w_out[i] = weight(i);
+        opp_out[i] = opposite(i);
+    }
+}
+
+/* Second-order equilibrium, f_i^eq = w_i rho (1 + c.u/cs2 + (c.u)^2/(2 cs4) - u.u/(2 cs2)). */
+void orc_equilibrium(double rho, const double *u, double *feq)
+{
+    const double cs2 = 1.0 / 3.0;
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < NQ; ++i) {
+        double cu = C[i][0] * u[0] + C[i][1] * u[1] + C[i][2] * u[2];
+        feq[i] = weight(i) * rho *
+                 (1.0 + cu / cs2 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+    }
+}
+
+/* rho = sum f, rho u = sum c f (+ F/2 with a body force, Guo et al. 2002). */
+static void moments(const orc_case *k, const double *f, double *rho, double *u)
+{
+    double r = 0.0, m[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < NQ; ++i) {
+        r += f[i];
+        for (int a = 0; a < 3; ++a) m[a] += C[i][a] * f[i];
+    }
+    *rho = r;
+    for (int a = 0; a < 3; ++a) u[a] = (m[a] + 0.5 * k->force[a]) / r;
+}
+
+/* Smagorinsky effective relaxation time.  With nu_t = (Cs dx)^2 |S|,
+ * |S| = sqrt(2 S:S) and S = -Pi_neq / (2 rho cs2 tau_eff) (dt = dx = 1),
+ * Eq. (tauEff) becomes tau^2 - tau0 tau - 9 Cs^2 Q / (sqrt(2) rho) = 0 with
+ * Q = sqrt(Pi_neq : Pi_neq); the positive root is returned. */
+double orc_tau_eff(double tau0, double cs, double rho, double q)
+{
+    return 0.5 * (tau0 + sqrt(tau0 * tau0 + 18.0 * sqrt(2.0) * cs * cs * q / rho));
+}
+
+/* Q = sqrt(Pi:Pi) of the non-equilibrium second moment. */
+static double neq_norm(const double *f, const double *feq, double pi[3][3])
+{
+    double s = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double p = 0.0;
+            for (int i = 0; i < NQ; ++i) p += C[i][a] * C[i][b] * (f[i] - feq[i]);
+            pi[a][b] = p;
+            s += p * p;
+        }
+    return sqrt(s);
+}
+
+/* Local collision of one fluid cell: f* = f - (1/tau_eff)(f - f_eq) [+ Guo force term]. */
+void orc_collide_cell(const orc_case *k, const double *f, double *fstar)
+{
+    double rho, u[3], feq[NQ], pi[3][3];
+    moments(k, f, &rho, u);
+    orc_equilibrium(rho, u, feq);
+    double tau = k->tau0;
+    if (k->model == M_SMAG) tau = orc_tau_eff(k->tau0, k->cs, rho, neq_norm(f, feq, pi));
+    double om = 1.0 / tau;
+    for (int i = 0; i < NQ; ++i) {
+        double fi = 0.0;
+        if (k->force[0] != 0.0 || k->force[1] != 0.0 || k->force[2] != 0.0) {
+            double cu = C[i][0] * u[0] + C[i][1] * u[1] + C[i][2] * u[2];
+            for (int a = 0; a < 3; ++a)
+                fi += (3.0 * (C[i][a] - u[a]) + 9.0 * cu * C[i][a]) * k->force[a];
+            fi *= (1.0 - 0.5 * om) * weight(i);
+        }
+        fstar[i] = f[i] - om * (f[i] - feq[i]) + fi;
+    }
+}
+
+/* Inflow ramp r(n) = (1 - cos(pi n / T_r)) / 2 for n < T_r, else 1. */
+static double ramp_factor(const orc_case *k, long n)
+{
+    if (k->ramp <= 0 || n >= k->ramp) return 1.0;
+    return 0.5 * (1.0 - cos(M_PI * (double)n / (double)k->ramp));
+}
+
+/* Inflow velocity and its derivatives w.r.t. theta at height index z (cell
+ * centre z + 1/2 above the half-way ground).  Log-law: U(z) = (u_star / 0.41) ln(z/z0),
+ * direction (cos phi, sin phi, 0).  dudth[3][3]: d u_a / d theta_k. */
+static void inflow(const orc_case *k, int z, double u[3], double dudth[3][3])
+{
+    double phi = k->theta[1];
+    double U, dU[3] = {0.0, 0.0, 0.0};
+    if (k->inflow == IN_UNIFORM) {
+        U = k->theta[0];
+        dU[0] = 1.0;
+    } else {
+        double us = k->theta[0], z0 = k->theta[2], h = z + 0.5;
+        U = us / 0.41 * log(h / z0);
+        dU[0] = log(h / z0) / 0.41;
+        dU[2] = -us / (0.41 * z0);
+    }
+    double dir[3] = {cos(phi), sin(phi), 0.0};
+    double ddir[3] = {-sin(phi), cos(phi), 0.0};
+    for (int a = 0; a < 3; ++a) {
+        u[a] = U * dir[a];
+        for (int t = 0; t < 3; ++t) dudth[a][t] = dU[t] * dir[a];
+        dudth[a][1] = U * ddir[a];
+    }
+}
+
+void orc_inflow_velocity(const orc_case *k, int z, long n, double *u)
+{
+    double d[3][3];
+    inflow(k, z, u, d);
+    double r = ramp_factor(k, n);
+    for (int a = 0; a < 3; ++a) u[a] *= r;
+}
+
+enum { R_STREAM = 0, R_BOUNCE = 1, R_INLET = 2, R_FREESLIP = 3, R_OUTLET = 4, R_REST = 5 };
+
+/* Pull rule of destination link (x, i): returns the rule kind and writes the
+ * source cell and the post-collision population index that f_out(x, i) is
+ * taken from.  Rules, first match wins, with s = x - c_i (periodic axes
+ * wrapped):
+ *   R1 s is solid, or s leaves the box through a WALL face: bounce-back,
+ *      source (x, opp(i));
+ *   R2 s.x < 0 through the INLET face: moving-wall bounce-back, source
+ *      (x, opp(i)) plus 6 w_i rho_w c_i.u_in with rho_w = 1;
+ *   R3 s.z >= nz through the FREESLIP sky: specular reflection, source
+ *      (x - c_ix, y - c_iy, nz-1) with c_z flipped, a source at x = nx clamped
+ *      to nx-1;
+ *   R4 s.x >= nx through the OUTLET face: zero gradient, source (nx-1, s.y, s.z),
+ *      same population;
+ *   R5 otherwise plain streaming from (s, i).
+ */
+static int pull_rule(const orc_case *k, int x, int y, int z, int i,
+                     int *sx_o, int *sy_o, int *sz_o, int *pop_o)
+{
+    if (i == 0) { *sx_o = x; *sy_o = y; *sz_o = z; *pop_o = 0; return R_REST; }
+    int sx = x - C[i][0], sy = y - C[i][1], sz = z - C[i][2];
+    if (k->face[0] == F_PERIODIC) sx = wrap(sx, k->nx);
+    if (k->face[2] == F_PERIODIC) sy = wrap(sy, k->ny);
+    if (k->face[4] == F_PERIODIC) sz = wrap(sz, k->nz);
+    int inside = sx >= 0 && sx < k->nx && sy >= 0 && sy < k->ny && sz >= 0 && sz < k->nz;
+    int wall_exit = (sx < 0 && k->face[0] == F_WALL) || (sx >= k->nx && k->face[1] == F_WALL) ||
+                    (sy < 0 && k->face[2] == F_WALL) || (sy >= k->ny && k->face[3] == F_WALL) ||
+                    (sz < 0 && k->face[4] == F_WALL) || (sz >= k->nz && k->face[5] == F_WALL);
+    if ((inside && k->solid[cell_index(k, sx, sy, sz)]) || wall_exit) {
+        *sx_o = x; *sy_o = y; *sz_o = z; *pop_o = opposite(i);
+        return R_BOUNCE;
+    }
+    if (sx < 0 && k->face[0] == F_INLET) {
+        *sx_o = x; *sy_o = y; *sz_o = z; *pop_o = opposite(i);
+        return R_INLET;
+    }
+    if (sz >= k->nz && k->face[5] == F_FREESLIP) {
+        int px = sx;  /* x - c_ix, already wrapped when x is periodic */
+        if (px >= k->nx && k->face[1] == F_OUTLET) px = k->nx - 1;
+        *sx_o = px; *sy_o = sy; *sz_o = k->nz - 1; *pop_o = zflip(i);
+        return R_FREESLIP;
+    }
+    if (sx >= k->nx && k->face[1] == F_OUTLET) {
+        *sx_o = k->nx - 1; *sy_o = sy; *sz_o = sz; *pop_o = i;
+        return R_OUTLET;
+    }
+    *sx_o = sx; *sy_o = sy; *sz_o = sz; *pop_o = i;
+    return R_STREAM;
+}
+
+/* Validity of a case: face combinations and the cells the rules read. */
+int orc_check_case(const orc_case *k)
+{
+    if (k->nx < 1 || k->ny < 1 || k->nz < 1) return 1;
+    int ok0 = k->face[0] == F_WALL || k->face[0] == F_INLET || k->face[0] == F_PERIODIC;
+    int ok1 = k->face[1] == F_WALL || k->face[1] == F_OUTLET || k->face[1] == F_PERIODIC;
+    int ok5 = k->face[5] == F_WALL || k->face[5] == F_FREESLIP || k->face[5] == F_PERIODIC;
+    int oky = (k->face[2] == F_WALL || k->face[2] == F_PERIODIC) &&
+              (k->face[3] == F_WALL || k->face[3] == F_PERIODIC);
+    int ok4 = k->face[4] == F_WALL || k->face[4] == F_PERIODIC;
+    if (!(ok0 && ok1 && ok5 && oky && ok4)) return 2;
+    for (int a = 0; a < 3; ++a)
+        if ((k->face[2 * a] == F_PERIODIC) != (k->face[2 * a + 1] == F_PERIODIC)) return 3;
+    if (k->tau0 <= 0.5) return 4;
+    /* the free-slip and outflow rules read top-layer / last-column cells */
+    for (int z = 0; z < k->nz; ++z)
+        for (int y = 0; y < k->ny; ++y)
+            for (int x = 0; x < k->nx; ++x) {
+                if (!k->solid[cell_index(k, x, y, z)]) continue;
+                if (k->face[5] == F_FREESLIP && z == k->nz - 1) return 5;
+                if (k->face[1] == F_OUTLET && x == k->nx - 1) return 6;
+            }
+    return 0;
+}
+
+void orc_init(const orc_case *k, double *f)
+{
+    long n = ncells(k);
+    for (int i = 0; i < NQ; ++i)
+        for (long c = 0; c < n; ++c) f[i * n + c] = weight(i);
+}
+
+/* rho, u (layout [3][cells]) of every cell; solid cells report rho = 1, u = 0. */
+void orc_macros(const orc_case *k, const double *f, double *rho, double *u)
+{
+    long n = ncells(k);
+    for (long c = 0; c < n; ++c) {
+        if (k->solid[c]) {
+            rho[c] = 1.0; u[c] = u[n + c] = u[2 * n + c] = 0.0;
+            continue;
+        }
+        double fl[NQ], r, v[3];
+        for (int i = 0; i < NQ; ++i) fl[i] = f[i * n + c];
+        moments(k, fl, &r, v);
+        rho[c] = r;
+        for (int a = 0; a < 3; ++a) u[a * n + c] = v[a];
+    }
+}
+
+/* One time step n -> n+1 (two lattices): collide every fluid cell, then pull. */
+void orc_step(const orc_case *k, long step, const double *fin, double *fout)
+{
+    long n = ncells(k);
+    double *fs = (double *)malloc(sizeof(double) * NQ * n);
+    double r = ramp_factor(k, step);
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < n; ++c) {
+        double fl[NQ], fsl[NQ];
+        if (k->solid[c]) {
+            for (int i = 0; i < NQ; ++i) fs[i * n + c] = weight(i);
+            continue;
+        }
+        for (int i = 0; i < NQ; ++i) fl[i] = fin[i * n + c];
+        orc_collide_cell(k, fl, fsl);
+        for (int i = 0; i < NQ; ++i) fs[i * n + c] = fsl[i];
+    }
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < k->nz; ++z)
+        for (int y = 0; y < k->ny; ++y)
+            for (int x = 0; x < k->nx; ++x) {
+                long c = cell_index(k, x, y, z);
+                if (k->solid[c]) {
+                    for (int i = 0; i < NQ; ++i) fout[i * n + c] = weight(i);
+                    continue;
+                }
+                for (int i = 0; i < NQ; ++i) {
+                    int sx, sy, sz, p;
+                    int rule = pull_rule(k, x, y, z, i, &sx, &sy, &sz, &p);
+                    double v = fs[p * n + cell_index(k, sx, sy, sz)];
+                    if (rule == R_INLET) {
+                        double uin[3], d[3][3];
+                        inflow(k, z, uin, d);
+                        double cu = C[i][0] * uin[0] + C[i][1] * uin[1] + C[i][2] * uin[2];
+                        v += 6.0 * weight(i) * 1.0 * cu * r;
+                    }
+                    fout[i * n + c] = v;
+                }
+            }
+    free(fs);
+}
+
+/* Rule of every link, for tests: rules[i*ncells + c] (-1 for solid cells). */
+void orc_link_rules(const orc_case *k, int *rules)
+{
+    long n = ncells(k);
+    for (int z = 0; z < k->nz; ++z)
+        for (int y = 0; y < k->ny; ++y)
+            for (int x = 0; x < k->nx; ++x) {
+                long c = cell_index(k, x, y, z);
+                for (int i = 0; i < NQ; ++i) {
+                    int sx, sy, sz, p;
+                    rules[i * n + c] = k->solid[c] ? -1 : pull_rule(k, x, y, z, i, &sx, &sy, &sz, &p);
+                }
+            }
+}
+
+/* Jacobian J[i][k] = d fstar_i / d f_k of the local collision (no body force),
+ * by the chain rule through rho, u, f_eq and (Smagorinsky) tau_eff. */
+static void collision_jacobian(const orc_case *k, const double *f, double J[NQ][NQ])
+{
+    double rho, u[3], feq[NQ], pi[3][3];
+    moments(k, f, &rho, u);
+    orc_equilibrium(rho, u, feq);
+    const double cs2 = 1.0 / 3.0;
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+
+    /* d rho / d f_k = 1 ; d u_a / d f_k = (c_ka - u_a) / rho */
+    double du[3][NQ];
+    for (int kk = 0; kk < NQ; ++kk)
+        for (int a = 0; a < 3; ++a) du[a][kk] = (C[kk][a] - u[a]) / rho;
+
+    /* d feq_i / d f_k */
+    double dfeq[NQ][NQ];
+    for (int i = 0; i < NQ; ++i) {
+        double cu = C[i][0] * u[0] + C[i][1] * u[1] + C[i][2] * u[2];
+        double drho = weight(i) * (1.0 + cu / cs2 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+        double dua[3];
+        for (int a = 0; a < 3; ++a)
+            dua[a] = weight(i) * rho * (C[i][a] / cs2 + cu * C[i][a] / (cs2 * cs2) - u[a] / cs2);
+        for (int kk = 0; kk < NQ; ++kk)
+            dfeq[i][kk] = drho + dua[0] * du[0][kk] + dua[1] * du[1][kk] + dua[2] * du[2][kk];
+    }
+
+    double tau = k->tau0;
+    double dom[NQ];
+    for (int kk = 0; kk < NQ; ++kk) dom[kk] = 0.0;
+    if (k->model == M_SMAG) {
+        double q = neq_norm(f, feq, pi);
+        tau = orc_tau_eff(k->tau0, k->cs, rho, q);
+        double K = 18.0 * sqrt(2.0) * k->cs * k->cs;
+        double root = sqrt(k->tau0 * k->tau0 + K * q / rho);
+        double dtau_dq = 0.25 * K / (rho * root);
+        double dtau_drho = -0.25 * K * q / (rho * rho * root);
+        for (int kk = 0; kk < NQ; ++kk) {
+            double dq = 0.0;
+            if (q > 0.0) {
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        double dpi = C[kk][a] * C[kk][b];
+                        for (int i = 0; i < NQ; ++i) dpi -= C[i][a] * C[i][b] * dfeq[i][kk];
+                        dq += pi[a][b] * dpi;
+                    }
+                dq /= q;
+            }
+            double dtau = dtau_dq * dq + dtau_drho * 1.0;
+            dom[kk] = -dtau / (tau * tau);
+        }
+    }
+    double om = 1.0 / tau;
+    for (int i = 0; i < NQ; ++i)
+        for (int kk = 0; kk < NQ; ++kk)
+            J[i][kk] = (i == kk ? 1.0 - om : 0.0) + om * dfeq[i][kk] - (f[i] - feq[i]) * dom[kk];
+}
+
+void orc_collision_jacobian(const orc_case *k, const double *f, double *J)
+{
+    double Jl[NQ][NQ];
+    collision_jacobian(k, f, Jl);
+    for (int i = 0; i < NQ; ++i)
+        for (int kk = 0; kk < NQ; ++kk) J[i * NQ + kk] = Jl[i][kk];
+}
+
+/* Discrete adjoint of step n -> n+1.
+ *   mu      = P^T lam_next           (scatter-add of every pull link to its source)
+ *   lam_n   = J(f_n)^T mu            (fluid cells; zero on solid cells)
+ *   grad_k += sum over inlet links (x,i) of lam_next(x,i) * d b_i / d theta_k,
+ * with b_i = 6 w_i rho_w c_i.u_in(z; theta) r(n).  lam_n receives no
+ * objective source here; callers add dj_n/df_n. */
+void orc_adjoint_step(const orc_case *k, long step, const double *f_n,
+                      const double *lam_next, double *lam_n, double *grad)
+{
+    long n = ncells(k);
+    double *mu = (double *)calloc((size_t)NQ * n, sizeof(double));
+    double r = ramp_factor(k, step);
+    double g[3] = {0.0, 0.0, 0.0};
+    for (int z = 0; z < k->nz; ++z)
+        for (int y = 0; y < k->ny; ++y)
+            for (int x = 0; x < k->nx; ++x) {
+                long c = cell_index(k, x, y, z);
+                if (k->solid[c]) continue;
+                for (int i = 0; i < NQ; ++i) {
+                    int sx, sy, sz, p;
+                    int rule = pull_rule(k, x, y, z, i, &sx, &sy, &sz, &p);
+                    double lam = lam_next[i * n + c];
+                    mu[p * n + cell_index(k, sx, sy, sz)] += lam;
+                    if (rule == R_INLET) {
+                        double uin[3], d[3][3];
+                        inflow(k, z, uin, d);
+                        for (int t = 0; t < 3; ++t) {
+                            double cd = C[i][0] * d[0][t] + C[i][1] * d[1][t] + C[i][2] * d[2][t];
+                            g[t] += lam * 6.0 * weight(i) * cd * r;
+                        }
+                    }
+                }
+            }
+    for (int t = 0; t < 3; ++t) grad[t] += g[t];
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < n; ++c) {
+        if (k->solid[c]) {
+            for (int i = 0; i < NQ; ++i) lam_n[i * n + c] = 0.0;
+            continue;
+        }
+        double fl[NQ], J[NQ][NQ];
+        for (int i = 0; i < NQ; ++i) fl[i] = f_n[i * n + c];
+        collision_jacobian(k, fl, J);
+        for (int kk = 0; kk < NQ; ++kk) {
+            double s = 0.0;
+            for (int i = 0; i < NQ; ++i) s += J[i][kk] * mu[i * n + c];
+            lam_n[kk * n + c] = s;
+        }
+    }
+    free(mu);
+}
