@@ -1,0 +1,238 @@
+/*
+ * lbm_sc.h -- C ABI of the MI355X (gfx950) stochastic-collocation lattice
+ * Boltzmann hot path.
+ *
+ * The method (arXiv 2508.18202):
+ *   Sec. 2.3 / 2.4 steps 2-3  collocation nodes Z^(j) and weights a_j
+ *                             (lbm_quadrature, lbm_node_params);
+ *   Sec. 2.2                  deterministic D3Q19 LBM per node: the update of
+ *                             Eq. (deterministicLBE) with the effective
+ *                             relaxation time of Eqs. (tauEff, turbVisc), the
+ *                             boundary kinds of the Sec. 2.2 list
+ *                             (lbm_init_geometry, lbm_collide_stream);
+ *   Sec. 2.4 step 6           QoI capture (time-averaged fields, probes);
+ *   Eq. (quad_moments)        mean and variance over the nodes (lbm_sc_moments);
+ *   (not in the paper)        discrete adjoint of the update for gradients of
+ *                             probe QoIs w.r.t. the inflow parameters
+ *                             (lbm_adjoint_step).
+ *
+ * Conventions shared by every call:
+ *   - Return value: LBM_OK (0) or a negative LBM_E_* code; lbm_last_error()
+ *     returns a thread-local message describing the last failure.
+ *   - Every pointer whose name ends in _dev is device memory of the current
+ *     HIP device; _host pointers are host memory.  The caller allocates and
+ *     frees all device buffers.  The library allocates device memory only
+ *     inside an lbm_plan (instance and tile tables, health words, captured
+ *     graphs) and frees it in lbm_plan_destroy.
+ *   - Calls taking a hipStream_t only enqueue work on that stream (they may
+ *     copy small host tables synchronously first); device faults surface on a
+ *     later call or on lbm_sync / lbm_check_health.
+ *   - Lattice: D3Q19 in the canonical order
+ *       0 (0,0,0); 1 (+x); 2 (-x); 3 (+y); 4 (-y); 5 (+z); 6 (-z);
+ *       7 (+x+y); 8 (-x-y); 9 (+x-y); 10 (-x+y); 11 (+x+z); 12 (-x-z);
+ *       13 (+x-z); 14 (-x+z); 15 (+y+z); 16 (-y-z); 17 (+y-z); 18 (-y+z),
+ *     lattice units (dx = dt = 1, c_s^2 = 1/3, rho_0 = 1).
+ *   - Cells are numbered x fastest: c = (z*ny + y)*nx + x.
+ *   - Populations are FP32 holding f_i - w_i, structure of arrays with a
+ *     padded plane stride (lbm_population_stride), streamed in place.
+ */
+#ifndef LBM_SC_H
+#define LBM_SC_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LBM_OK = 0,
+    LBM_E_INVALID = -1,      /* bad argument, shape, face combination or geometry */
+    LBM_E_HIP = -2,          /* a HIP runtime call failed (message has its string) */
+    LBM_E_UNSTABLE = -3,     /* an instance produced a non-finite or non-positive density */
+    LBM_E_UNSUPPORTED = -4   /* device is not gfx950, or a feature combination is not built */
+};
+
+/* Boundary kind of each box face, order -x, +x, -y, +y, -z, +z (Sec. 2.2
+ * boundary list; the box replaces the paper's cylinder, see the design notes).
+ *   WALL      half-way bounce-back (no-slip building walls and ground);
+ *   INLET     local velocity condition as moving-wall bounce-back with
+ *             rho_w = 1: f_i = f*_opp(i) + 6 w_i c_i.u_in (only on -x);
+ *   OUTLET    zero gradient of the post-collision populations (only on +x);
+ *   FREESLIP  specular reflection: zero normal velocity, zero normal gradient
+ *             of the tangential velocity (only on +z);
+ *   PERIODIC  wrap-around (both faces of an axis). */
+enum { LBM_WALL = 0, LBM_INLET = 1, LBM_OUTLET = 2, LBM_FREESLIP = 3, LBM_PERIODIC = 4 };
+
+/* Collision models: BGK (Eq. deterministicLBE with an unprojected
+ * non-equilibrium part) and BGK with the Smagorinsky-Lilly effective
+ * relaxation time (Eqs. tauEff, turbVisc; |S| from the local non-equilibrium
+ * stress). */
+enum { LBM_BGK = 0, LBM_SMAGORINSKY = 1 };
+
+/* Inflow profiles (Sec. 3, log-law wind profile): theta = (speed, phi, z0).
+ *   UNIFORM  u_in = speed (cos phi, sin phi, 0);
+ *   LOGLAW   u_in(z) = (speed / 0.41) ln((z + 1/2) / z0) (cos phi, sin phi, 0),
+ *            speed = friction velocity u*, z0 = roughness length in cells,
+ *            z the cell index above the half-way ground. */
+enum { LBM_INFLOW_UNIFORM = 0, LBM_INFLOW_LOGLAW = 1 };
+
+/* Collocation rules (Sec. 2.3, Eq. coef_discrete / quad_moments). */
+enum { LBM_QUAD_GAUSS_LEGENDRE = 0, LBM_QUAD_SMOLYAK_CC = 1 };
+
+typedef struct lbm_domain {
+    int32_t nx, ny, nz;
+    int32_t face[6];
+} lbm_domain;
+
+/* One deterministic run (one collocation node of one case). */
+typedef struct lbm_instance {
+    lbm_domain dom;
+    const void *geom_dev;    /* geometry buffer filled by lbm_init_geometry */
+    int32_t n_probes;        /* probe count given to lbm_init_geometry */
+    float *f_dev;            /* 19 * lbm_population_stride(dom) floats */
+    int32_t model;           /* LBM_BGK / LBM_SMAGORINSKY (uniform over a plan) */
+    float tau0;              /* molecular relaxation time, > 1/2 */
+    float cs;                /* Smagorinsky constant C_S */
+    int32_t inflow;          /* LBM_INFLOW_* */
+    float theta[3];          /* inflow parameters (speed, phi [rad], z0) */
+    int32_t ramp;            /* inflow ramp length T_r in steps: u_in is scaled by
+                                (1 - cos(pi n / T_r)) / 2 for n < T_r */
+    float *qoi_part_dev;     /* [ncells][4] FP32 partial sums of (ux, uy, uz, |u|) or NULL */
+    double *qoi_sum_dev;     /* [ncells][4] FP64 window sums, or NULL (both or neither) */
+    double *probe_sum_dev;   /* [n_probes] FP64 window sums of u_x at the probes, or NULL */
+} lbm_instance;
+
+typedef struct lbm_plan_opts {
+    int64_t avg_begin;       /* QoI window: states f^n with avg_begin < n <= avg_end */
+    int64_t avg_end;         /* avg_end <= avg_begin disables accumulation */
+    int32_t use_graph;       /* replay step pairs from captured HIP graphs where possible */
+    int32_t block;           /* cells per workgroup: 128, 256 or 512; 0 = default (256) */
+} lbm_plan_opts;
+
+typedef struct lbm_plan lbm_plan;
+
+/* ------------------------------------------------------------------ errors */
+const char *lbm_last_error(void);
+const char *lbm_version(void);
+
+/* ------------------------------------------------------- collocation (a1/a2)
+ * lbm_quadrature: nodes [n][dim] (row-major) and probability weights [n] of
+ *   LBM_QUAD_GAUSS_LEGENDRE (level = number of points, dim must be 1; xi ~ U(-1,1))
+ *   or LBM_QUAD_SMOLYAK_CC (level L >= 0, dim >= 1; nested Clenshaw-Curtis
+ *   rules with 1, 3, 5, 9, ... points, combination technique).
+ *   Returns the node count through *n_out.  With nodes_host == NULL only the
+ *   count is returned.  cap = capacity of the output arrays in nodes.
+ * lbm_node_params: theta = (base*(1 + rel*xi_1), radians(angle_deg*xi_2), z0)
+ *   -- the multiplicative speed perturbation and additive direction
+ *   perturbation of Sec. 3 with uniform xi (dim 1: no direction term). */
+int lbm_quadrature(int32_t kind, int32_t level, int32_t dim, double *nodes_host,
+                   double *weights_host, int32_t cap, int32_t *n_out);
+int lbm_node_params(const double *xi_host, int32_t dim, double base, double rel,
+                    double angle_deg, double z0, float theta_out[3]);
+
+/* ---------------------------------------------------------- geometry (a3)
+ * Sizes the caller must allocate: the geometry buffer in bytes and the
+ * population plane stride in floats (f_dev holds 19 planes).
+ * lbm_init_geometry validates the case, builds per-cell flags and solid-link
+ * masks on the device from solid_host ([nz][ny][nx] bytes, 1 = solid) and
+ * the sorted probe list (probe_host, n_probes distinct fluid cell indices, may
+ * be NULL when n_probes == 0), and sets f_dev to the rest equilibrium
+ * (f_i - w_i = 0).  Rejected (LBM_E_INVALID): face kinds outside the list
+ * above, unpaired periodic faces, solid cells in the top layer under a
+ * free-slip sky, solid cells in the last two x columns or an odd nx with an
+ * outlet, more than 2^31 - 1 cells. */
+int64_t lbm_geometry_bytes(const lbm_domain *dom, int32_t n_probes);
+int64_t lbm_population_stride(const lbm_domain *dom);
+int lbm_init_geometry(const lbm_domain *dom, const uint8_t *solid_host,
+                      const int32_t *probe_host, int32_t n_probes, void *geom_dev,
+                      float *f_dev, hipStream_t stream);
+
+/* ------------------------------------------------------ batched plan (a5)
+ * A plan binds a batch of instances (any sizes, one collision model) that
+ * advance together, one launch per time step over a flattened tile list.
+ * lbm_plan_create copies the instance table; device buffers stay owned by
+ * the caller and must outlive the plan.  The step counter starts at 0. */
+int lbm_plan_create(const lbm_instance *inst, int32_t n_inst, const lbm_plan_opts *opts,
+                    lbm_plan **plan_out);
+void lbm_plan_destroy(lbm_plan *plan);
+int64_t lbm_plan_step(const lbm_plan *plan);
+int lbm_plan_set_step(lbm_plan *plan, int64_t step);   /* even steps only (natural layout) */
+int lbm_plan_set_theta(lbm_plan *plan, int32_t inst, const float theta[3]);
+int lbm_plan_reset_qoi(lbm_plan *plan, hipStream_t stream);     /* zero QoI sums and health */
+int lbm_sync(lbm_plan *plan, hipStream_t stream);
+/* Synchronises stream; returns LBM_E_UNSTABLE and the first bad instance
+ * index through *bad_inst if any instance saw rho <= 0 or a non-finite rho. */
+int lbm_check_health(lbm_plan *plan, hipStream_t stream, int32_t *bad_inst);
+/* Pick the block size by timing step pairs on a copy of the batch state
+ * (state, step counter and QoI sums are restored).  Results are cached in
+ * the JSON file named by LBMSC_TUNE_CACHE (default ~/.cache/lbmsc_tune.json). */
+int lbm_plan_autotune(lbm_plan *plan, hipStream_t stream, int32_t *block_out);
+
+/* --------------------------------------------- collide and stream (a4/a6)
+ * Advance every instance of the plan by n_steps time steps of Eq.
+ * (deterministicLBE): per cell read 19 populations, form rho, u
+ * (+ Smagorinsky tau_eff), relax, and write the 19 populations to their
+ * streamed slots, boundary rules resolved per link.  The in-place AA pattern
+ * alternates an even step (own cell, swapped slots) and an odd step
+ * (gather from neighbours, scatter to neighbours).  QoIs of every state f^n
+ * in the plan's window are accumulated: qoi sums of (ux, uy, uz, |u|) and
+ * probe sums of u_x (solid cells contribute nothing). */
+int lbm_collide_stream(lbm_plan *plan, int32_t n_steps, hipStream_t stream);
+
+/* Same, and also record the state of every step n for the adjoint sweep:
+ * record_kind 1 saves (rho, u) as [slot][ncells][4] floats (BGK adjoint),
+ * record_kind 2 saves f - w as [slot][19][stride] floats (Smagorinsky
+ * adjoint); slot = n % n_slots; rec_dev[i] is instance i's buffer. */
+int lbm_collide_stream_record(lbm_plan *plan, int32_t n_steps, int32_t record_kind,
+                              float *const *rec_dev_host, int32_t n_slots, hipStream_t stream);
+
+/* u_x, u_y, u_z, |u| of the current state of instance i ([ncells][4] floats;
+ * solid cells 0), and the natural-layout populations f - w ([19][stride]). */
+int lbm_read_fields(lbm_plan *plan, int32_t inst, float *out_dev, hipStream_t stream);
+int lbm_read_populations(lbm_plan *plan, int32_t inst, float *out_dev, hipStream_t stream);
+/* Window averages: out[c][k] = qoi_sum[c][k] / count and probe_sum / count
+ * as floats (probe_out may be NULL). */
+int lbm_qoi_average(lbm_plan *plan, int32_t inst, float *out_dev, float *probe_out_dev,
+                    hipStream_t stream);
+
+/* ---------------------------------------------------------- moments (a7)
+ * Eq. (quad_moments) per element e < n_elems of the node-major input
+ * q_dev[n_nodes][n_elems] (FP32):
+ *   mean[e] = sum_j w_j q[j][e],  var[e] = sum_j w_j (q[j][e] - mean[e])^2,
+ * both accumulated in FP64 (two passes over the nodes held in registers for
+ * n_nodes <= 32, a shifted single pass otherwise).  Weights may be negative
+ * (Smolyak), so var may come out negative; the count of negative variances
+ * is added atomically to *n_negative_dev (device, caller-zeroed; may be NULL).
+ * Rejected: n_nodes < 1 or > 256, |sum w - 1| > 1e-12. */
+int lbm_sc_moments(const float *q_dev, const double *w_host, int32_t n_nodes, int64_t n_elems,
+                   double *mean_dev, double *var_dev, unsigned long long *n_negative_dev,
+                   hipStream_t stream);
+
+/* ---------------------------------------------------------- adjoint (a8)
+ * Discrete adjoint of one step n -> n+1 for every instance of the plan
+ * (not in the paper):
+ *   lam^n = (dC/df |f^n)^T P^T lam^{n+1} + dj_n/df^n,
+ *   dJdtheta[i][k] += sum over inlet links (x,q) of
+ *                     lam^{n+1}_q(x) * 6 w_q c_q . d u_in / d theta_k * r(n)   (FP64),
+ * with P the streaming/boundary map, C the local collision, and
+ * j_n = sum_p pw[p] * u_x(f^n, p) / count for n inside the QoI window
+ * (count = avg_end - avg_begin).  Buffers per instance (device pointers in
+ * host arrays of length n_inst): lam_in (lam^{n+1}) and lam_out (lam^n),
+ * [19][stride] floats; rec, the state recorded by
+ * lbm_collide_stream_record for step n (kind 1 for BGK, 2 for Smagorinsky,
+ * slot n % n_slots); pw, [n_probes] FP64 probe weights or NULL;
+ * dJdtheta_dev, [n_inst][3] FP64 accumulated in place. */
+int lbm_adjoint_step(lbm_plan *plan, int64_t step, float *const *lam_in_host,
+                     float *const *lam_out_host, float *const *rec_host, int32_t record_kind,
+                     int32_t n_slots, const double *const *pw_host, double *dJdtheta_dev,
+                     hipStream_t stream);
+/* lam^N = dj_N/df^N from the plan's current (even) state N; lam_out as above. */
+int lbm_adjoint_init(lbm_plan *plan, float *const *lam_out_host, const double *const *pw_host,
+                     hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_SC_H */

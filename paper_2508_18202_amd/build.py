@@ -1,0 +1,55 @@
+"""Build the gfx950 shared libraries of the package in-tree with hipcc.
+
+* ``liblbmsc.so``           -- the C-ABI library (kernels + host code);
+* ``liblbmsc_hostcheck.so`` -- host-only checks of the link rules (CPU tests).
+
+Run ``python -m paper_2508_18202_amd.build``; ``__graft_entry__.build()``
+calls :func:`build` as well.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(PKG, "liblbmsc.so")
+HOSTCHECK = os.path.join(PKG, "liblbmsc_hostcheck.so")
+
+ARCH = "gfx950"
+# packed FP32 instructions stay off (see the design notes)
+HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-munsafe-fp-atomics", "-Wno-unused-command-line-argument"]
+
+
+def _hipcc() -> str:
+    exe = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(exe):
+        raise RuntimeError("hipcc not found; the HIP library cannot be built")
+    return exe
+
+
+def _run(cmd):
+    print("+", " ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+
+
+def build(verbose: bool = True) -> None:
+    hipcc = _hipcc()
+    srcs = [os.path.join(CSRC, f) for f in ("kernels.hip", "lbm_sc.hip", "quadrature.cpp")]
+    tmp = LIB + ".tmp"
+    _run([hipcc, *HIP_FLAGS, "-shared", f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-o", tmp])
+    os.replace(tmp, LIB)
+    tmp = HOSTCHECK + ".tmp"
+    _run([hipcc, *HIP_FLAGS, "-shared", f"-I{CSRC}", os.path.join(CSRC, "hostcheck.hip"), "-o", tmp])
+    os.replace(tmp, HOSTCHECK)
+
+
+if __name__ == "__main__":
+    build()
+    sys.exit(0)

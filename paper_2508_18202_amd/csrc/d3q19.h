@@ -1,0 +1,50 @@
+// d3q19.h -- D3Q19 velocity set for the gfx950 kernels and the host checker.
+//
+// The velocity set of Fig. 1 (arXiv 2508.18202): one rest velocity, six face
+// neighbours, twelve edge neighbours; weights 1/3, 1/18, 1/36; c_s^2 = 1/3.
+// Canonical order: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 = edge pairs,
+// each odd index followed by its opposite.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define LBM_HD __host__ __device__ __forceinline__
+
+namespace lbmsc {
+
+constexpr int Q = 19;
+
+LBM_HD constexpr int cx(int i)
+{
+    constexpr int v[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    return v[i];
+}
+LBM_HD constexpr int cy(int i)
+{
+    constexpr int v[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    return v[i];
+}
+LBM_HD constexpr int cz(int i)
+{
+    constexpr int v[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    return v[i];
+}
+// opposite direction: pairs (1,2), (3,4), ..., (17,18)
+LBM_HD constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+// same velocity with c_z mirrored (specular reflection at a z = const plane)
+LBM_HD constexpr int zflip(int i)
+{
+    constexpr int v[Q] = {0, 1, 2, 3, 4, 6, 5, 7, 8, 9, 10, 13, 14, 11, 12, 17, 18, 15, 16};
+    return v[i];
+}
+LBM_HD constexpr float wgt(int i) { return i == 0 ? 1.0f / 3.0f : (i <= 6 ? 1.0f / 18.0f : 1.0f / 36.0f); }
+LBM_HD constexpr double wgt_d(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+// face kinds (ABI values)
+enum : int { FACE_WALL = 0, FACE_INLET = 1, FACE_OUTLET = 2, FACE_FREESLIP = 3, FACE_PERIODIC = 4 };
+
+// per-cell flag bits
+enum : uint8_t { FL_SOLID = 1, FL_NEAR = 2, FL_PROBE = 4, FL_INLET = 8 };
+
+}  // namespace lbmsc

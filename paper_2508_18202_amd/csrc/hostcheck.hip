@@ -1,0 +1,183 @@
+// hostcheck.hip -- host-only checks of the link rules used by the kernels.
+//
+// Built into a separate host library so that CPU tests can verify, without a
+// GPU, that the in-place update is well defined for a geometry and a
+// workgroup size:
+//   * push_dsts() is the exact inverse of pull_src(): every fluid destination
+//     link has exactly one source, and that source lists it;
+//   * in the odd (gather-then-scatter) step, every memory slot is written at
+//     most once, and every slot touched by more than one cell is touched only
+//     by cells of one workgroup, where a barrier orders the reads before the
+//     writes.
+// It also exposes the per-link rule kinds so they can be compared with an
+// independent implementation.
+#include <cstdint>
+#include <cstring>
+#include <unordered_map>
+#include <vector>
+
+#include "rules.h"
+
+using namespace lbmsc;
+
+namespace {
+
+struct Geo3 {
+    Box b;
+    const uint8_t *solid;
+    std::vector<uint8_t> fl;
+    std::vector<uint32_t> m;
+    int64_t n;
+    int64_t cell(int x, int y, int z) const { return ((int64_t)z * b.ny + y) * b.nx + x; }
+};
+
+void build(Geo3 &g, int nx, int ny, int nz, const int *face, const uint8_t *solid)
+{
+    g.b.nx = nx;
+    g.b.ny = ny;
+    g.b.nz = nz;
+    for (int k = 0; k < 6; ++k) g.b.face[k] = face[k];
+    g.solid = solid;
+    g.n = (int64_t)nx * ny * nz;
+    g.fl.assign(g.n, 0);
+    g.m.assign(g.n, 0);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int64_t c = g.cell(x, y, z);
+                cell_flags(g.b, solid, x, y, z, g.fl[c], g.m[c]);
+            }
+}
+
+}  // namespace
+
+extern "C" {
+
+// Rule kind of every link ([19][ncells], -1 for solid cells).
+void lbmhc_rules(int nx, int ny, int nz, const int *face, const uint8_t *solid, int *rules)
+{
+    Geo3 g;
+    build(g, nx, ny, nz, face, solid);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int64_t c = g.cell(x, y, z);
+                for (int i = 0; i < Q; ++i)
+                    rules[i * g.n + c] = (g.fl[c] & FL_SOLID) ? -1 : pull_src(g.b, x, y, z, i, g.m[c]).kind;
+            }
+}
+
+// Returns 0 when all properties hold, otherwise a code; stats[0..5] =
+// fluid links, links through a non-plain rule, values with two destinations,
+// shared slots, shared slots spanning two workgroups, slots written twice.
+int lbmhc_check(int nx, int ny, int nz, const int *face, const uint8_t *solid, int block, int64_t *stats)
+{
+    Geo3 g;
+    build(g, nx, ny, nz, face, solid);
+    for (int k = 0; k < 6; ++k) stats[k] = 0;
+    // 1. inverse property
+    std::vector<int8_t> hit((size_t)Q * g.n, 0);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int64_t c = g.cell(x, y, z);
+                if (g.fl[c] & FL_SOLID) continue;
+                for (int k = 1; k < Q; ++k) {
+                    Link d[2];
+                    const int nd = push_dsts(g.b, x, y, z, k, g.m[c], d[0], d[1]);
+                    if (nd == 2) ++stats[2];
+                    for (int j = 0; j < nd; ++j) {
+                        if (d[j].x < 0 || d[j].x >= nx || d[j].y < 0 || d[j].y >= ny || d[j].z < 0 || d[j].z >= nz)
+                            return 1;
+                        const int64_t dc = g.cell(d[j].x, d[j].y, d[j].z);
+                        if (g.fl[dc] & FL_SOLID) return 2;
+                        const Link s = pull_src(g.b, d[j].x, d[j].y, d[j].z, d[j].pop, g.m[dc]);
+                        if (s.x != x || s.y != y || s.z != z || s.pop != k || s.kind != d[j].kind) return 3;
+                        if (hit[(size_t)d[j].pop * g.n + dc]++) return 4;
+                    }
+                }
+            }
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int64_t c = g.cell(x, y, z);
+                if (g.fl[c] & FL_SOLID) continue;
+                for (int i = 1; i < Q; ++i) {
+                    ++stats[0];
+                    const Link s = pull_src(g.b, x, y, z, i, g.m[c]);
+                    if (s.kind != R_STREAM) ++stats[1];
+                    if (!hit[(size_t)i * g.n + c]) return 5;  // a link without a source
+                    const int64_t sc = g.cell(s.x, s.y, s.z);
+                    if (g.fl[sc] & FL_SOLID) return 6;
+                    // fast paths: a cell without FL_NEAR must stream plainly both ways
+                    if (!(g.fl[c] & FL_NEAR)) {
+                        if (s.kind != R_STREAM || s.x != x - cx(i) || s.y != y - cy(i) || s.z != z - cz(i)) return 7;
+                        Link d[2];
+                        if (push_dsts(g.b, x, y, z, i, g.m[c], d[0], d[1]) != 1 || d[0].kind != R_STREAM) return 8;
+                    }
+                }
+            }
+    // 2. odd-step slot ownership: cells touching each slot (read of swapped
+    // value or write of the next natural value)
+    std::unordered_map<int64_t, std::vector<int64_t>> touch;
+    std::unordered_map<int64_t, int> writes;
+    auto slot = [&](int pop, int64_t cell) { return (int64_t)pop * g.n + cell; };
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int64_t c = g.cell(x, y, z);
+                if (g.fl[c] & FL_SOLID) continue;
+                for (int i = 0; i < Q; ++i) {
+                    const Link s = pull_src(g.b, x, y, z, i, g.m[c]);
+                    touch[slot(opp(s.pop), g.cell(s.x, s.y, s.z))].push_back(c);
+                }
+                touch[slot(0, c)].push_back(c);
+                ++writes[slot(0, c)];
+                for (int k = 1; k < Q; ++k) {
+                    Link d[2];
+                    const int nd = push_dsts(g.b, x, y, z, k, g.m[c], d[0], d[1]);
+                    for (int j = 0; j < nd; ++j) {
+                        const int64_t s = slot(d[j].pop, g.cell(d[j].x, d[j].y, d[j].z));
+                        touch[s].push_back(c);
+                        if (++writes[s] > 1) ++stats[5];
+                    }
+                }
+            }
+    if (stats[5]) return 9;
+    for (auto &kv : touch) {
+        const std::vector<int64_t> &v = kv.second;
+        bool shared = false, cross = false;
+        for (int64_t c : v) {
+            if (c != v[0]) shared = true;
+            if (c / block != v[0] / block) cross = true;
+        }
+        if (shared) ++stats[3];
+        if (cross) ++stats[4];
+    }
+    if (stats[4]) return 10;
+    return 0;
+}
+
+// Fast division: checks v / d against fdiv for the given values.
+int lbmhc_fastdiv(uint32_t d, const uint32_t *v, int64_t n)
+{
+    const FastDiv f = make_fastdiv(d);
+    for (int64_t k = 0; k < n; ++k)
+        if (fdiv(v[k], f) != v[k] / d) return 1;
+    return 0;
+}
+
+// Velocity set as the kernels see it: c [19][3], w [19], opp [19], zflip [19].
+void lbmhc_lattice(int *c, float *w, int *o, int *zf)
+{
+    for (int i = 0; i < Q; ++i) {
+        c[3 * i] = cx(i);
+        c[3 * i + 1] = cy(i);
+        c[3 * i + 2] = cz(i);
+        w[i] = wgt(i);
+        o[i] = opp(i);
+        zf[i] = zflip(i);
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+// kernels.h -- device-side instance table and kernel launch entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rules.h"
+
+namespace lbmsc {
+
+// One instance (one collocation node of one case) as the kernels see it.
+struct Geo {
+    float *f;                  // populations f - w, [19][qs]
+    const uint8_t *flags;      // [ncells] FL_* bits
+    const uint32_t *smask;     // [ncells] bit i: neighbour x - c_i is solid
+    const int32_t *probes;     // [n_probes] sorted cell indices
+    float *qpart;              // [ncells][4] FP32 window partial sums or null
+    double *qsum;              // [ncells][4] FP64 window sums or null
+    double *psum;              // [n_probes] FP64 probe sums or null
+    int64_t qs;                // population plane stride in floats
+    int32_t ncells;
+    int32_t n_probes;
+    Box box;
+    int32_t offy, offz;        // linear offsets of +y and +z neighbours
+    FastDiv dx, dxy;           // division by nx and nx*ny
+    int32_t tile0;             // first tile of this instance in the flattened list
+    int32_t inflow;            // 0 uniform, 1 log-law
+    float tau0;
+    float kcs;                 // 18 sqrt(2) Cs^2
+    float speed, cphi, sphi, phi, z0;
+    int32_t ramp;
+    int32_t pad_;
+};
+
+// Launch arguments that change from step to step.
+struct StepArgs {
+    int64_t step;              // time index n of the state being collided
+    int32_t accumulate;        // add this state's QoIs to the window sums
+    int32_t record;            // 0 none, 1 (rho,u), 2 populations
+    float *const *rec;         // device array [n_inst] of record buffer bases
+    int64_t rec_slot;          // slot index n % n_slots
+};
+
+int launch_step(int block, int model, int parity, const Geo *geo, const int32_t *tile_inst,
+                int32_t n_tiles, const StepArgs &a, int32_t *health, hipStream_t s);
+int launch_init_geometry(const Box &b, const uint8_t *solid, uint8_t *flags, uint32_t *smask,
+                         const int32_t *probes, int32_t n_probes, hipStream_t s);
+int launch_capture(int tcells, int parity, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
+                   int64_t step, int32_t *health, hipStream_t s);
+int launch_flush(int tcells, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, hipStream_t s);
+int launch_fields(int parity, const Geo *geo, int32_t inst, const Geo &g, int64_t step,
+                  float *out, int32_t mode, hipStream_t s);
+int launch_average(const Geo &g, double inv_count, float *out, float *pout, hipStream_t s);
+int launch_zero_qoi(const Geo &g, hipStream_t s);
+int launch_moments(const float *q, const double *w, int32_t nq, int64_t n, double *mean,
+                   double *var, unsigned long long *nneg, hipStream_t s);
+
+struct AdjArgs {
+    int64_t step;
+    int32_t model;
+    int32_t record;            // 1 (rho,u) or 2 populations
+    int32_t in_window;         // the objective has a term at this step
+    double inv_count;          // 1 / (avg_end - avg_begin)
+    float *const *lam_in;      // device arrays [n_inst]
+    float *const *lam_out;
+    float *const *rec;         // device array [n_inst] of record buffer bases
+    int64_t rec_slot;          // slot index n % n_slots
+    const double *const *pw;   // [n_inst] probe weights (entries may be null)
+    double *grad;              // [n_inst][3]
+};
+
+int launch_adjoint(int block, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
+                   const AdjArgs &a, hipStream_t s);
+int launch_adjoint_init(int tcells, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
+                        const AdjArgs &a, hipStream_t s);
+
+}  // namespace lbmsc

@@ -1,0 +1,772 @@
+// kernels.hip -- gfx950 kernels of the SC-LBM hot path.
+//
+// In-place AA streaming on one FP32 population array per instance (values
+// f_i - w_i):
+//   even step n (state stored naturally: slot i of cell x holds f_i^n(x))
+//     each cell reads its own 19 slots, collides, and writes f*_i into its own
+//     slot opp(i);
+//   odd step n (slots hold the swapped post-collision values of step n-1)
+//     each cell gathers f_i^n(x) through the link rules of rules.h, collides,
+//     and scatters f*_i(x) to every destination link of the next state, which
+//     is then stored naturally again.
+// Both steps move 19 floats in and 19 floats out per fluid cell.  In the odd
+// step the outflow column reads values that its upstream neighbour in the
+// same x-row overwrites, so each workgroup finishes all gathers before any
+// scatter (one barrier); a workgroup is a run of consecutive cells of one
+// instance, which never separates cells nx-2 and nx-1 of a row when nx is even.
+//
+// Collision (Sec. 2.2, Eq. deterministicLBE with an unprojected
+// non-equilibrium part): f* = f - omega (f - f_eq), second-order
+// equilibrium; Smagorinsky omega = 1 / tau_eff with
+// tau_eff = (tau0 + sqrt(tau0^2 + 18 sqrt(2) Cs^2 Q / rho)) / 2,
+// Q = |Pi_neq| (Eqs. tauEff, turbVisc with |S| from the local
+// non-equilibrium stress).
+#include "kernels.h"
+
+namespace lbmsc {
+
+namespace {
+
+constexpr float KAPPA_INV = 1.0f / 0.41f;
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of tiles so neighbouring tiles share one L2.
+__device__ __forceinline__ int xcd_tile()
+{
+    const int G8 = gridDim.x >> 3;
+    const int p = blockIdx.x;
+    return (p & 7) * G8 + (p >> 3);
+}
+
+__device__ __forceinline__ float ramp_factor(const Geo &G, int64_t n)
+{
+    if (G.ramp <= 0 || n >= G.ramp) return 1.0f;
+    return 0.5f * (1.0f - cosf(3.14159265358979323846f * (float)n / (float)G.ramp));
+}
+
+__device__ __forceinline__ float inflow_speed(const Geo &G, int z)
+{
+    if (G.inflow == 0) return G.speed;
+    return G.speed * KAPPA_INV * logf(((float)z + 0.5f) / G.z0);
+}
+
+// 6 w_i c_i . u_in, the moving-wall momentum of link i.
+__device__ __forceinline__ float inlet_term(int i, float U, const Geo &G, float r)
+{
+    return 6.0f * wgt(i) * U * r * ((float)cx(i) * G.cphi + (float)cy(i) * G.sphi);
+}
+
+__device__ __forceinline__ int probe_index(const Geo &G, int32_t c)
+{
+    int lo = 0, hi = G.n_probes - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        int v = G.probes[mid];
+        if (v == c) return mid;
+        if (v < c) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ void coords(const Geo &G, uint32_t c, int &x, int &y, int &z)
+{
+    const uint32_t zz = fdiv(c, G.dxy);
+    const uint32_t rem = c - zz * (uint32_t)(G.box.nx * G.box.ny);
+    const uint32_t yy = fdiv(rem, G.dx);
+    x = (int)(rem - yy * (uint32_t)G.box.nx);
+    y = (int)yy;
+    z = (int)zz;
+}
+
+__device__ __forceinline__ uint32_t cell_of(const Geo &G, const Link &l)
+{
+    return ((uint32_t)l.z * (uint32_t)G.box.ny + (uint32_t)l.y) * (uint32_t)G.box.nx + (uint32_t)l.x;
+}
+
+__device__ __forceinline__ int32_t off_of(const Geo &G, int i)
+{
+    return cx(i) + cy(i) * G.offy + cz(i) * G.offz;
+}
+
+// Populations f^n(x) of a fluid cell in the current storage state.
+// parity 0: natural slots; parity 1: gathered from the swapped
+// post-collision values of step n-1 (inlet momentum uses r(n-1)).
+template <int PARITY>
+__device__ __forceinline__ void load_state(const Geo &G, uint32_t c, uint8_t fl, int x, int y, int z,
+                                           int64_t n, float g[Q])
+{
+    const float *__restrict__ f = G.f;
+    const uint32_t qs = (uint32_t)G.qs;
+    if (PARITY == 0) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) g[i] = f[i * qs + c];
+    } else if (!(fl & FL_NEAR)) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) g[i] = f[opp(i) * qs + (uint32_t)((int32_t)c - off_of(G, i))];
+    } else {
+        const uint32_t sm = G.smask[c];
+        const float U = (fl & FL_INLET) ? inflow_speed(G, z) : 0.0f;
+        const float r = ramp_factor(G, n - 1);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const Link s = pull_src(G.box, x, y, z, i, sm);
+            float v = f[opp(s.pop) * qs + cell_of(G, s)];
+            if (s.kind == R_INLET) v += inlet_term(i, U, G, r);
+            g[i] = v;
+        }
+    }
+}
+
+struct Macro {
+    float drho, rho, ux, uy, uz;
+};
+
+__device__ __forceinline__ Macro macro_of(const float g[Q])
+{
+    Macro m;
+    float d = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        d += g[i];
+        if (cx(i)) jx += cx(i) * g[i];
+        if (cy(i)) jy += cy(i) * g[i];
+        if (cz(i)) jz += cz(i) * g[i];
+    }
+    m.drho = d;
+    m.rho = 1.0f + d;
+    const float inv = 1.0f / m.rho;
+    m.ux = jx * inv;
+    m.uy = jy * inv;
+    m.uz = jz * inv;
+    return m;
+}
+
+// Non-equilibrium stress Pi = sum c c (f - f_eq) from the shifted populations:
+// sum c c g - (drho/3) I - rho u u.  Order: xx, yy, zz, xy, xz, yz.
+__device__ __forceinline__ void neq_stress(const float g[Q], const Macro &m, float P[6])
+{
+    float xx = 0.f, yy = 0.f, zz = 0.f, xy = 0.f, xz = 0.f, yz = 0.f;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        if (cx(i)) xx += g[i];
+        if (cy(i)) yy += g[i];
+        if (cz(i)) zz += g[i];
+        if (cx(i) && cy(i)) xy += cx(i) * cy(i) * g[i];
+        if (cx(i) && cz(i)) xz += cx(i) * cz(i) * g[i];
+        if (cy(i) && cz(i)) yz += cy(i) * cz(i) * g[i];
+    }
+    const float d3 = m.drho * (1.0f / 3.0f);
+    P[0] = xx - d3 - m.rho * m.ux * m.ux;
+    P[1] = yy - d3 - m.rho * m.uy * m.uy;
+    P[2] = zz - d3 - m.rho * m.uz * m.uz;
+    P[3] = xy - m.rho * m.ux * m.uy;
+    P[4] = xz - m.rho * m.ux * m.uz;
+    P[5] = yz - m.rho * m.uy * m.uz;
+}
+
+__device__ __forceinline__ float stress_norm(const float P[6])
+{
+    return sqrtf(P[0] * P[0] + P[1] * P[1] + P[2] * P[2] +
+                 2.0f * (P[3] * P[3] + P[4] * P[4] + P[5] * P[5]));
+}
+
+template <int MODEL>
+__device__ __forceinline__ float tau_of(const Geo &G, const float g[Q], const Macro &m)
+{
+    if (MODEL == 0) return G.tau0;
+    float P[6];
+    neq_stress(g, m, P);
+    const float q = stress_norm(P);
+    return 0.5f * (G.tau0 + sqrtf(G.tau0 * G.tau0 + G.kcs * q / m.rho));
+}
+
+// shifted equilibrium f_eq - w
+__device__ __forceinline__ float geq(int i, const Macro &m, float usq15)
+{
+    const float cu = cx(i) * m.ux + cy(i) * m.uy + cz(i) * m.uz;
+    return wgt(i) * (m.drho + m.rho * (3.0f * cu + 4.5f * cu * cu - usq15));
+}
+
+template <int MODEL>
+__device__ __forceinline__ void collide(const Geo &G, float g[Q], const Macro &m)
+{
+    const float om = 1.0f / tau_of<MODEL>(G, g, m);
+    const float usq15 = 1.5f * (m.ux * m.ux + m.uy * m.uy + m.uz * m.uz);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g[i] = g[i] - om * (g[i] - geq(i, m, usq15));
+}
+
+__device__ __forceinline__ void accumulate_qoi(const Geo &G, uint32_t c, uint8_t fl, const Macro &m)
+{
+    if (G.qpart) {
+        float4 *p = reinterpret_cast<float4 *>(G.qpart) + c;
+        float4 v = *p;
+        v.x += m.ux;
+        v.y += m.uy;
+        v.z += m.uz;
+        v.w += sqrtf(m.ux * m.ux + m.uy * m.uy + m.uz * m.uz);
+        *p = v;
+    }
+    if ((fl & FL_PROBE) && G.psum) {
+        const int p = probe_index(G, (int32_t)c);
+        if (p >= 0) G.psum[p] += (double)m.ux;
+    }
+}
+
+template <int BS, int MODEL, int PARITY>
+__global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
+                                             int32_t n_tiles, StepArgs a, int32_t *__restrict__ health)
+{
+    const int tile = xcd_tile();
+    if (tile >= n_tiles) return;
+    const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
+    const Geo &G = geo[ii];
+    const int32_t lc = (tile - G.tile0) * BS + (int32_t)threadIdx.x;
+    const bool active = lc < G.ncells;
+    const uint32_t c = active ? (uint32_t)lc : 0u;
+    const uint8_t fl = active ? G.flags[c] : (uint8_t)FL_SOLID;
+    const bool fluid = !(fl & FL_SOLID);
+    float *__restrict__ f = G.f;
+    const uint32_t qs = (uint32_t)G.qs;
+
+    int x = 0, y = 0, z = 0;
+    float g[Q];
+    if (fluid) {
+        if (PARITY == 1 && (fl & FL_NEAR)) coords(G, c, x, y, z);
+        load_state<PARITY>(G, c, fl, x, y, z, a.step, g);
+        const Macro m = macro_of(g);
+        if (!(m.rho > 0.0f) || !isfinite(m.rho)) atomicOr(health + ii, 1);
+        if (a.accumulate) accumulate_qoi(G, c, fl, m);
+        if (a.record == 1) {
+            float4 *r = reinterpret_cast<float4 *>(a.rec[ii]) + (size_t)a.rec_slot * (size_t)G.ncells + c;
+            *r = make_float4(m.rho, m.ux, m.uy, m.uz);
+        } else if (a.record == 2) {
+            float *r = a.rec[ii] + (size_t)a.rec_slot * (size_t)Q * G.qs;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) r[i * qs + c] = g[i];
+        }
+        collide<MODEL>(G, g, m);
+    }
+    if (PARITY == 1) __syncthreads();
+    if (!fluid) return;
+    if (PARITY == 0) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[opp(i) * qs + c] = g[i];
+    } else if (!(fl & FL_NEAR)) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i * qs + (uint32_t)((int32_t)c + off_of(G, i))] = g[i];
+    } else {
+        const uint32_t sm = G.smask[c];
+        const float U = (fl & FL_INLET) ? inflow_speed(G, z) : 0.0f;
+        const float r = ramp_factor(G, a.step);
+        f[c] = g[0];
+#pragma unroll
+        for (int k = 1; k < Q; ++k) {
+            Link d0, d1;
+            const int nd = push_dsts(G.box, x, y, z, k, sm, d0, d1);
+            if (nd > 0) {
+                float v = g[k];
+                if (d0.kind == R_INLET) v += inlet_term(opp(k), U, G, r);
+                f[d0.pop * qs + cell_of(G, d0)] = v;
+            }
+            if (nd > 1) f[d1.pop * qs + cell_of(G, d1)] = g[k];
+        }
+    }
+}
+
+// QoIs of the current state f^n without advancing it.
+template <int PARITY>
+__global__ __launch_bounds__(512) void k_capture(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
+                                                 int32_t n_tiles, int64_t step, int32_t *__restrict__ health)
+{
+    const int tile = xcd_tile();
+    if (tile >= n_tiles) return;
+    const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
+    const Geo &G = geo[ii];
+    const int32_t lc = (tile - G.tile0) * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+    if (lc >= G.ncells) return;
+    const uint32_t c = (uint32_t)lc;
+    const uint8_t fl = G.flags[c];
+    if (fl & FL_SOLID) return;
+    int x = 0, y = 0, z = 0;
+    coords(G, c, x, y, z);
+    float g[Q];
+    load_state<PARITY>(G, c, fl, x, y, z, step, g);
+    const Macro m = macro_of(g);
+    if (!(m.rho > 0.0f) || !isfinite(m.rho)) atomicOr(health + ii, 1);
+    accumulate_qoi(G, c, fl, m);
+}
+
+__global__ __launch_bounds__(512) void k_flush(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
+                                               int32_t n_tiles)
+{
+    const int tile = xcd_tile();
+    if (tile >= n_tiles) return;
+    const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
+    const Geo &G = geo[ii];
+    if (!G.qpart) return;
+    const int32_t lc = (tile - G.tile0) * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+    if (lc >= G.ncells) return;
+    float4 *p = reinterpret_cast<float4 *>(G.qpart) + lc;
+    const float4 v = *p;
+    double *s = G.qsum + 4 * (size_t)lc;
+    s[0] += v.x;
+    s[1] += v.y;
+    s[2] += v.z;
+    s[3] += v.w;
+    *p = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// mode 0: fields (ux, uy, uz, |u|) [ncells][4]; mode 1: populations [19][qs]
+template <int PARITY>
+__global__ __launch_bounds__(256) void k_fields(const Geo *__restrict__ geo, int32_t ii, int64_t step, float *out,
+                                                int32_t mode)
+{
+    const Geo &G = geo[ii];
+    const int32_t lc = blockIdx.x * 256 + (int32_t)threadIdx.x;
+    if (lc >= G.ncells) return;
+    const uint32_t c = (uint32_t)lc;
+    const uint8_t fl = G.flags[c];
+    const uint32_t qs = (uint32_t)G.qs;
+    if (fl & FL_SOLID) {
+        if (mode == 0) reinterpret_cast<float4 *>(out)[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+        else
+            for (int i = 0; i < Q; ++i) out[i * qs + c] = 0.0f;
+        return;
+    }
+    int x = 0, y = 0, z = 0;
+    coords(G, c, x, y, z);
+    float g[Q];
+    load_state<PARITY>(G, c, fl, x, y, z, step, g);
+    if (mode == 0) {
+        const Macro m = macro_of(g);
+        reinterpret_cast<float4 *>(out)[c] =
+            make_float4(m.ux, m.uy, m.uz, sqrtf(m.ux * m.ux + m.uy * m.uy + m.uz * m.uz));
+    } else {
+        for (int i = 0; i < Q; ++i) out[i * qs + c] = g[i];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_average(const double *__restrict__ qsum, const double *__restrict__ psum,
+                                                 int32_t n4, int32_t np, double inv, float *out, float *pout)
+{
+    const int32_t e = blockIdx.x * 256 + (int32_t)threadIdx.x;
+    if (e < n4) out[e] = (float)(qsum[e] * inv);
+    if (pout && e < np) pout[e] = (float)(psum[e] * inv);
+}
+
+__global__ __launch_bounds__(256) void k_zero(float *qpart, double *qsum, double *psum, int32_t n4, int32_t np)
+{
+    const int32_t e = blockIdx.x * 256 + (int32_t)threadIdx.x;
+    if (e < n4) {
+        if (qpart) qpart[e] = 0.0f;
+        if (qsum) qsum[e] = 0.0;
+    }
+    if (psum && e < np) psum[e] = 0.0;
+}
+
+// Geometry: per-cell flags and solid-link masks from the solid mask.
+__global__ __launch_bounds__(256) void k_init_geometry(Box b, const uint8_t *__restrict__ solid,
+                                                       uint8_t *__restrict__ flags, uint32_t *__restrict__ smask,
+                                                       const int32_t *__restrict__ probes, int32_t n_probes,
+                                                       int32_t ncells)
+{
+    const int32_t c = blockIdx.x * 256 + (int32_t)threadIdx.x;
+    if (c >= ncells) return;
+    const int x = c % b.nx, y = (c / b.nx) % b.ny, z = c / (b.nx * b.ny);
+    uint8_t fl;
+    uint32_t m;
+    cell_flags(b, solid, x, y, z, fl, m);
+    if (!(fl & FL_SOLID)) {
+        int lo = 0, hi = n_probes - 1;
+        while (lo <= hi) {
+            int mid = (lo + hi) >> 1;
+            if (probes[mid] == c) { fl |= FL_PROBE; break; }
+            if (probes[mid] < c) lo = mid + 1; else hi = mid - 1;
+        }
+    }
+    flags[c] = fl;
+    smask[c] = m;
+}
+
+// ------------------------------------------------------------------ moments
+
+struct Weights {
+    double w[256];
+};
+
+template <int NQMAX>
+__global__ __launch_bounds__(256) void k_moments_arg(const float *__restrict__ q, int32_t nq, int64_t n,
+                                                     Weights W, double *__restrict__ mean,
+                                                     double *__restrict__ var, unsigned long long *nneg)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    double v[NQMAX];
+    double m = 0.0;
+#pragma unroll
+    for (int j = 0; j < NQMAX; ++j) {
+        if (j < nq) {
+            v[j] = (double)q[(int64_t)j * n + e];
+            m += W.w[j] * v[j];
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < NQMAX; ++j) {
+        if (j < nq) {
+            const double d = v[j] - m;
+            s += W.w[j] * d * d;
+        }
+    }
+    mean[e] = m;
+    var[e] = s;
+    if (nneg && s < 0.0) atomicAdd(nneg, 1ull);
+}
+
+__global__ __launch_bounds__(256) void k_moments_arg_shift(const float *__restrict__ q, int32_t nq, int64_t n,
+                                                           Weights W, double *__restrict__ mean,
+                                                           double *__restrict__ var, unsigned long long *nneg)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    const double K = (double)q[e];
+    double s1 = 0.0, s2 = 0.0;
+    for (int j = 0; j < nq; ++j) {
+        const double d = (double)q[(int64_t)j * n + e] - K;
+        s1 += W.w[j] * d;
+        s2 += W.w[j] * d * d;
+    }
+    mean[e] = K + s1;
+    const double s = s2 - s1 * s1;
+    var[e] = s;
+    if (nneg && s < 0.0) atomicAdd(nneg, 1ull);
+}
+
+// ------------------------------------------------------------------ adjoint
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// d u_in / d theta_t . c for link i at height z: (c . dir) dU/dtheta_t for
+// speed and z0, U (c . d dir / d phi) for the direction.
+__device__ __forceinline__ void inflow_dtheta(const Geo &G, int z, int i, float out[3])
+{
+    const float cd = (float)cx(i) * G.cphi + (float)cy(i) * G.sphi;
+    const float cdd = -(float)cx(i) * G.sphi + (float)cy(i) * G.cphi;
+    if (G.inflow == 0) {
+        out[0] = cd;
+        out[1] = G.speed * cdd;
+        out[2] = 0.0f;
+    } else {
+        const float L = logf(((float)z + 0.5f) / G.z0);
+        const float U = G.speed * KAPPA_INV * L;
+        out[0] = KAPPA_INV * L * cd;
+        out[1] = U * cdd;
+        out[2] = -G.speed * KAPPA_INV / G.z0 * cd;
+    }
+}
+
+template <int BS, int MODEL>
+__global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
+                                                int32_t n_tiles, AdjArgs a)
+{
+    const int tile = xcd_tile();
+    if (tile >= n_tiles) return;
+    const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
+    const Geo &G = geo[ii];
+    const int32_t lc = (tile - G.tile0) * BS + (int32_t)threadIdx.x;
+    const bool active = lc < G.ncells;
+    const uint32_t c = active ? (uint32_t)lc : 0u;
+    const uint8_t fl = active ? G.flags[c] : (uint8_t)FL_SOLID;
+    const bool fluid = !(fl & FL_SOLID);
+    const uint32_t qs = (uint32_t)G.qs;
+    double gr0 = 0.0, gr1 = 0.0, gr2 = 0.0;
+    if (fluid) {
+        const float *__restrict__ lin = a.lam_in[ii];
+        float *__restrict__ lout = a.lam_out[ii];
+        // mu = P^T lam^{n+1}: sum over the destination links of each post-collision value
+        float mu[Q];
+        if (!(fl & FL_NEAR)) {
+#pragma unroll
+            for (int k = 0; k < Q; ++k) mu[k] = lin[k * qs + (uint32_t)((int32_t)c + off_of(G, k))];
+        } else {
+            int x, y, z;
+            coords(G, c, x, y, z);
+            const uint32_t sm = G.smask[c];
+            const float r = ramp_factor(G, a.step);
+            mu[0] = lin[c];
+#pragma unroll
+            for (int k = 1; k < Q; ++k) {
+                Link d0, d1;
+                const int nd = push_dsts(G.box, x, y, z, k, sm, d0, d1);
+                float s = 0.0f;
+                if (nd > 1) s += lin[d1.pop * qs + cell_of(G, d1)];
+                if (nd > 0) {
+                    const float l = lin[d0.pop * qs + cell_of(G, d0)];
+                    s += l;
+                    if (d0.kind == R_INLET) {
+                        float dt[3];
+                        const int q = opp(k);
+                        inflow_dtheta(G, z, q, dt);
+                        const double f6 = 6.0 * (double)wgt(q) * (double)r * (double)l;
+                        gr0 += f6 * dt[0];
+                        gr1 += f6 * dt[1];
+                        gr2 += f6 * dt[2];
+                    }
+                }
+                mu[k] = s;
+            }
+        }
+        // state of step n
+        float rho, ux, uy, uz, om;
+        float A = 0.0f, P[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, qn = 0.0f, tau = G.tau0;
+        if (a.record == 1) {
+            const float4 s =
+                reinterpret_cast<const float4 *>(a.rec[ii])[(size_t)a.rec_slot * (size_t)G.ncells + c];
+            rho = s.x;
+            ux = s.y;
+            uy = s.z;
+            uz = s.w;
+            om = 1.0f / G.tau0;
+        } else {
+            const float *rp = a.rec[ii] + (size_t)a.rec_slot * (size_t)Q * G.qs;
+            float g[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) g[i] = rp[i * qs + c];
+            const Macro m = macro_of(g);
+            rho = m.rho;
+            ux = m.ux;
+            uy = m.uy;
+            uz = m.uz;
+            if (MODEL == 1) {
+                neq_stress(g, m, P);
+                qn = stress_norm(P);
+                tau = 0.5f * (G.tau0 + sqrtf(G.tau0 * G.tau0 + G.kcs * qn / m.rho));
+                const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) A += mu[i] * (g[i] - geq(i, m, usq15));
+            }
+            om = 1.0f / tau;
+        }
+        // BGK part: (1 - om) mu_k + om [s_rho + (c_k - u) . t]
+        float m0 = 0.f, m1x = 0.f, m1y = 0.f, m1z = 0.f;
+        float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const float wm = wgt(i) * mu[i];
+            m0 += wm;
+            if (cx(i)) { m1x += cx(i) * wm; mxx += wm; }
+            if (cy(i)) { m1y += cy(i) * wm; myy += wm; }
+            if (cz(i)) { m1z += cz(i) * wm; mzz += wm; }
+            if (cx(i) && cy(i)) mxy += cx(i) * cy(i) * wm;
+            if (cx(i) && cz(i)) mxz += cx(i) * cz(i) * wm;
+            if (cy(i) && cz(i)) myz += cy(i) * cz(i) * wm;
+        }
+        const float usq = ux * ux + uy * uy + uz * uz;
+        const float m2ux = mxx * ux + mxy * uy + mxz * uz;
+        const float m2uy = mxy * ux + myy * uy + myz * uz;
+        const float m2uz = mxz * ux + myz * uy + mzz * uz;
+        const float srho = m0 * (1.0f - 1.5f * usq) + 3.0f * (m1x * ux + m1y * uy + m1z * uz) +
+                           4.5f * (ux * m2ux + uy * m2uy + uz * m2uz);
+        const float tx = 3.0f * m1x + 9.0f * m2ux - 3.0f * ux * m0;
+        const float ty = 3.0f * m1y + 9.0f * m2uy - 3.0f * uy * m0;
+        const float tz = 3.0f * m1z + 9.0f * m2uz - 3.0f * uz * m0;
+        // Smagorinsky: + (A / tau^2) dtau/df_k
+        float sa = 0.0f, sb = 0.0f;
+        if (MODEL == 1 && qn > 0.0f) {
+            const float R = sqrtf(G.tau0 * G.tau0 + G.kcs * qn / rho);
+            const float pre = A / (tau * tau) * G.kcs / (4.0f * R);
+            sa = pre / (rho * qn);
+            sb = -pre * qn / (rho * rho) - sa * (P[0] + P[1] + P[2]) * (1.0f / 3.0f);
+        }
+        // objective source at the probes: pw_p / count * (c_kx - u_x) / rho
+        float src = 0.0f;
+        if (a.in_window && (fl & FL_PROBE) && a.pw[ii]) {
+            const int p = probe_index(G, (int32_t)c);
+            if (p >= 0) src = (float)(a.pw[ii][p] * a.inv_count) / rho;
+        }
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const float ex = cx(k) - ux, ey = cy(k) - uy, ez = cz(k) - uz;
+            float lk = (1.0f - om) * mu[k] + om * (srho + ex * tx + ey * ty + ez * tz);
+            if (MODEL == 1) {
+                const float quad = ex * (P[0] * ex + P[3] * ey + P[4] * ez) +
+                                   ey * (P[3] * ex + P[1] * ey + P[5] * ez) +
+                                   ez * (P[4] * ex + P[5] * ey + P[2] * ez);
+                lk += sa * quad + sb;
+            }
+            lk += src * ex;
+            lout[k * qs + c] = lk;
+        }
+    }
+    // gradient: wave reduction, one FP64 atomic per wave that touched an inlet
+    const bool any_inlet = __any(fluid && (fl & FL_INLET));
+    if (any_inlet) {
+        gr0 = wave_sum(gr0);
+        gr1 = wave_sum(gr1);
+        gr2 = wave_sum(gr2);
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(a.grad + 3 * ii + 0, gr0);
+            atomicAdd(a.grad + 3 * ii + 1, gr1);
+            atomicAdd(a.grad + 3 * ii + 2, gr2);
+        }
+    }
+}
+
+// lam^N = dj_N / df^N from the (even, naturally stored) current state.
+__global__ __launch_bounds__(512) void k_adjoint_init(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
+                                                      int32_t n_tiles, AdjArgs a)
+{
+    const int tile = xcd_tile();
+    if (tile >= n_tiles) return;
+    const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
+    const Geo &G = geo[ii];
+    const int32_t lc = (tile - G.tile0) * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+    if (lc >= G.ncells) return;
+    const uint32_t c = (uint32_t)lc;
+    const uint32_t qs = (uint32_t)G.qs;
+    const uint8_t fl = G.flags[c];
+    float *lout = a.lam_out[ii];
+    float src = 0.0f, ux = 0.0f;
+    if (!(fl & FL_SOLID) && a.in_window && (fl & FL_PROBE) && a.pw[ii]) {
+        const int p = probe_index(G, (int32_t)c);
+        if (p >= 0) {
+            float g[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) g[i] = G.f[i * qs + c];
+            const Macro m = macro_of(g);
+            src = (float)(a.pw[ii][p] * a.inv_count) / m.rho;
+            ux = m.ux;
+        }
+    }
+    for (int k = 0; k < Q; ++k) lout[k * qs + c] = src * (cx(k) - ux);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launches
+
+static inline int grid_of(int32_t n_tiles) { return ((n_tiles + 7) / 8) * 8; }
+
+template <int BS, int MODEL>
+static void step_bs(int parity, const Geo *geo, const int32_t *ti, int32_t nt, const StepArgs &a, int32_t *h,
+                    hipStream_t s)
+{
+    const dim3 grid(grid_of(nt)), block(BS);
+    if (parity == 0) hipLaunchKernelGGL((k_step<BS, MODEL, 0>), grid, block, 0, s, geo, ti, nt, a, h);
+    else hipLaunchKernelGGL((k_step<BS, MODEL, 1>), grid, block, 0, s, geo, ti, nt, a, h);
+}
+
+int launch_step(int block, int model, int parity, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
+                const StepArgs &a, int32_t *health, hipStream_t s)
+{
+    if (n_tiles <= 0) return 0;
+    if (block == 128) {
+        if (model == 0) step_bs<128, 0>(parity, geo, tile_inst, n_tiles, a, health, s);
+        else step_bs<128, 1>(parity, geo, tile_inst, n_tiles, a, health, s);
+    } else if (block == 512) {
+        if (model == 0) step_bs<512, 0>(parity, geo, tile_inst, n_tiles, a, health, s);
+        else step_bs<512, 1>(parity, geo, tile_inst, n_tiles, a, health, s);
+    } else if (block == 256) {
+        if (model == 0) step_bs<256, 0>(parity, geo, tile_inst, n_tiles, a, health, s);
+        else step_bs<256, 1>(parity, geo, tile_inst, n_tiles, a, health, s);
+    } else {
+        return -1;
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_init_geometry(const Box &b, const uint8_t *solid, uint8_t *flags, uint32_t *smask, const int32_t *probes,
+                         int32_t n_probes, hipStream_t s)
+{
+    const int32_t n = b.nx * b.ny * b.nz;
+    hipLaunchKernelGGL(k_init_geometry, dim3((n + 255) / 256), dim3(256), 0, s, b, solid, flags, smask, probes,
+                       n_probes, n);
+    return (int)hipGetLastError();
+}
+
+int launch_capture(int tcells, int parity, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, int64_t step,
+                   int32_t *health, hipStream_t s)
+{
+    const dim3 grid(grid_of(n_tiles)), block(tcells);
+    if (parity == 0) hipLaunchKernelGGL(k_capture<0>, grid, block, 0, s, geo, tile_inst, n_tiles, step, health);
+    else hipLaunchKernelGGL(k_capture<1>, grid, block, 0, s, geo, tile_inst, n_tiles, step, health);
+    return (int)hipGetLastError();
+}
+
+int launch_flush(int tcells, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_flush, dim3(grid_of(n_tiles)), dim3(tcells), 0, s, geo, tile_inst, n_tiles);
+    return (int)hipGetLastError();
+}
+
+int launch_fields(int parity, const Geo *geo, int32_t inst, const Geo &g, int64_t step, float *out, int32_t mode,
+                  hipStream_t s)
+{
+    const dim3 grid((g.ncells + 255) / 256), block(256);
+    if (parity == 0) hipLaunchKernelGGL(k_fields<0>, grid, block, 0, s, geo, inst, step, out, mode);
+    else hipLaunchKernelGGL(k_fields<1>, grid, block, 0, s, geo, inst, step, out, mode);
+    return (int)hipGetLastError();
+}
+
+int launch_average(const Geo &g, double inv_count, float *out, float *pout, hipStream_t s)
+{
+    const int32_t n4 = 4 * g.ncells;
+    const int32_t n = n4 > g.n_probes ? n4 : g.n_probes;
+    hipLaunchKernelGGL(k_average, dim3((n + 255) / 256), dim3(256), 0, s, g.qsum, g.psum, g.qsum ? n4 : 0,
+                       g.n_probes, inv_count, out, pout);
+    return (int)hipGetLastError();
+}
+
+int launch_zero_qoi(const Geo &g, hipStream_t s)
+{
+    const int32_t n4 = 4 * g.ncells;
+    const int32_t n = n4 > g.n_probes ? n4 : g.n_probes;
+    hipLaunchKernelGGL(k_zero, dim3((n + 255) / 256), dim3(256), 0, s, g.qpart, g.qsum, g.psum, n4, g.n_probes);
+    return (int)hipGetLastError();
+}
+
+int launch_moments(const float *q, const double *w, int32_t nq, int64_t n, double *mean, double *var,
+                   unsigned long long *nneg, hipStream_t s)
+{
+    Weights W;
+    for (int j = 0; j < 256; ++j) W.w[j] = j < nq ? w[j] : 0.0;
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (nq <= 8) hipLaunchKernelGGL(k_moments_arg<8>, grid, block, 0, s, q, nq, n, W, mean, var, nneg);
+    else if (nq <= 16) hipLaunchKernelGGL(k_moments_arg<16>, grid, block, 0, s, q, nq, n, W, mean, var, nneg);
+    else if (nq <= 32) hipLaunchKernelGGL(k_moments_arg<32>, grid, block, 0, s, q, nq, n, W, mean, var, nneg);
+    else hipLaunchKernelGGL(k_moments_arg_shift, grid, block, 0, s, q, nq, n, W, mean, var, nneg);
+    return (int)hipGetLastError();
+}
+
+template <int BS>
+static void adjoint_bs(int model, const Geo *geo, const int32_t *ti, int32_t nt, const AdjArgs &a, hipStream_t s)
+{
+    const dim3 grid(grid_of(nt)), block(BS);
+    if (model == 0) hipLaunchKernelGGL((k_adjoint<BS, 0>), grid, block, 0, s, geo, ti, nt, a);
+    else hipLaunchKernelGGL((k_adjoint<BS, 1>), grid, block, 0, s, geo, ti, nt, a);
+}
+
+int launch_adjoint(int block, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, const AdjArgs &a,
+                   hipStream_t s)
+{
+    if (block == 128) adjoint_bs<128>(a.model, geo, tile_inst, n_tiles, a, s);
+    else if (block == 512) adjoint_bs<512>(a.model, geo, tile_inst, n_tiles, a, s);
+    else if (block == 256) adjoint_bs<256>(a.model, geo, tile_inst, n_tiles, a, s);
+    else return -1;
+    return (int)hipGetLastError();
+}
+
+int launch_adjoint_init(int tcells, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, const AdjArgs &a,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adjoint_init, dim3(grid_of(n_tiles)), dim3(tcells), 0, s, geo, tile_inst, n_tiles, a);
+    return (int)hipGetLastError();
+}
+
+}  // namespace lbmsc

@@ -1,0 +1,816 @@
+// lbm_sc.hip -- host side of the C ABI declared in include/lbm_sc.h.
+//
+// Owns validation, the batched plan (flattened tile list over instances of
+// any size, per-instance device table), the step loop with its QoI window,
+// HIP-graph replay of step pairs, the block-size autotuner and the calls
+// into the kernels of kernels.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "lbm_sc.h"
+#include "kernels.h"
+#include "quadrature.h"
+
+using namespace lbmsc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(LBM_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+
+int64_t ncells_of(const lbm_domain *d) { return (int64_t)d->nx * d->ny * d->nz; }
+
+int64_t stride_of(int64_t ncells)
+{
+    // an odd number of 256-byte blocks per population plane, so the 19 planes
+    // do not all start on the same HBM channel
+    int64_t blocks = (ncells + 63) / 64;
+    if ((blocks & 1) == 0) blocks += 1;
+    return blocks * 64;
+}
+
+int check_domain(const lbm_domain *d)
+{
+    if (!d) return fail(LBM_E_INVALID, "domain is NULL");
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(LBM_E_INVALID, "non-positive box size");
+    const int64_t n = ncells_of(d);
+    if (n > (int64_t)INT32_MAX || 19 * stride_of(n) > (int64_t)INT32_MAX)
+        return fail(LBM_E_INVALID, "box of %lld cells exceeds the 32-bit index range", (long long)n);
+    const int *f = d->face;
+    for (int k = 0; k < 6; ++k)
+        if (f[k] < LBM_WALL || f[k] > LBM_PERIODIC) return fail(LBM_E_INVALID, "face %d has unknown kind %d", k, f[k]);
+    for (int a = 0; a < 3; ++a)
+        if ((f[2 * a] == LBM_PERIODIC) != (f[2 * a + 1] == LBM_PERIODIC))
+            return fail(LBM_E_INVALID, "periodic faces must come in pairs (axis %d)", a);
+    if (!(f[0] == LBM_WALL || f[0] == LBM_INLET || f[0] == LBM_PERIODIC))
+        return fail(LBM_E_INVALID, "-x face must be WALL, INLET or PERIODIC");
+    if (!(f[1] == LBM_WALL || f[1] == LBM_OUTLET || f[1] == LBM_PERIODIC))
+        return fail(LBM_E_INVALID, "+x face must be WALL, OUTLET or PERIODIC");
+    if (f[2] == LBM_INLET || f[2] == LBM_OUTLET || f[2] == LBM_FREESLIP || f[3] == LBM_INLET ||
+        f[3] == LBM_OUTLET || f[3] == LBM_FREESLIP)
+        return fail(LBM_E_INVALID, "y faces must be WALL or PERIODIC");
+    if (!(f[4] == LBM_WALL || f[4] == LBM_PERIODIC)) return fail(LBM_E_INVALID, "-z face must be WALL or PERIODIC");
+    if (!(f[5] == LBM_WALL || f[5] == LBM_FREESLIP || f[5] == LBM_PERIODIC))
+        return fail(LBM_E_INVALID, "+z face must be WALL, FREESLIP or PERIODIC");
+    if (f[1] == LBM_OUTLET && (d->nx & 1))
+        return fail(LBM_E_INVALID, "an outlet needs an even nx (got %d)", d->nx);
+    if (f[1] == LBM_OUTLET && d->nx < 2) return fail(LBM_E_INVALID, "an outlet needs nx >= 2");
+    return LBM_OK;
+}
+
+Box box_of(const lbm_domain *d)
+{
+    Box b;
+    b.nx = d->nx;
+    b.ny = d->ny;
+    b.nz = d->nz;
+    for (int k = 0; k < 6; ++k) b.face[k] = d->face[k];
+    return b;
+}
+
+struct GeoPtrs {
+    uint8_t *flags;
+    uint32_t *smask;
+    int32_t *probes;
+};
+
+GeoPtrs geo_ptrs(const void *base, const lbm_domain *d)
+{
+    const int64_t n = ncells_of(d);
+    char *b = (char *)base;
+    GeoPtrs p;
+    p.flags = (uint8_t *)b;
+    p.smask = (uint32_t *)(b + align256(n));
+    p.probes = (int32_t *)(b + align256(n) + align256(4 * n));
+    return p;
+}
+
+int check_device()
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(LBM_E_UNSUPPORTED, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+    return LBM_OK;
+}
+
+}  // namespace
+
+struct lbm_plan {
+    int n_inst = 0;
+    int model = 0;
+    int block = 256;
+    std::vector<lbm_instance> inst;
+    std::vector<Geo> geo_h;
+    Geo *geo_d = nullptr;
+    int32_t *tiles_d = nullptr;
+    int32_t n_tiles = 0;
+    int32_t *health_d = nullptr;
+    int64_t step = 0;
+    int64_t avg_begin = 0, avg_end = 0;
+    int pending = 0;             // states accumulated in the FP32 partials since the last flush
+    int flush_every = 64;
+    int ramp_max = 0;
+    bool use_graph = false;
+    hipGraphExec_t gexec = nullptr;
+    int graph_pairs = 8;
+    std::map<std::vector<uintptr_t>, void *> tables;
+};
+
+namespace {
+
+int build_tiles(lbm_plan *p)
+{
+    std::vector<int32_t> tiles;
+    for (int i = 0; i < p->n_inst; ++i) {
+        Geo &g = p->geo_h[i];
+        g.tile0 = (int32_t)tiles.size();
+        const int64_t nt = (g.ncells + p->block - 1) / p->block;
+        if ((int64_t)tiles.size() + nt > (int64_t)INT32_MAX / 2) return fail(LBM_E_INVALID, "too many tiles");
+        for (int64_t t = 0; t < nt; ++t) tiles.push_back(i);
+    }
+    if (p->tiles_d) HIPCHK(hipFree(p->tiles_d));
+    p->tiles_d = nullptr;
+    p->n_tiles = (int32_t)tiles.size();
+    HIPCHK(hipMalloc(&p->tiles_d, sizeof(int32_t) * std::max<size_t>(1, tiles.size())));
+    HIPCHK(hipMemcpy(p->tiles_d, tiles.data(), sizeof(int32_t) * tiles.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(p->geo_d, p->geo_h.data(), sizeof(Geo) * p->n_inst, hipMemcpyHostToDevice));
+    if (p->gexec) {
+        HIPCHK(hipGraphExecDestroy(p->gexec));
+        p->gexec = nullptr;
+    }
+    return LBM_OK;
+}
+
+void set_theta(Geo &g, const lbm_instance &in)
+{
+    g.inflow = in.inflow;
+    g.speed = in.theta[0];
+    g.phi = in.theta[1];
+    g.cphi = std::cos(in.theta[1]);
+    g.sphi = std::sin(in.theta[1]);
+    g.z0 = in.theta[2];
+}
+
+// device copy of a host array of pointers, cached by content
+template <class T>
+int table_of(lbm_plan *p, const T *host, T **out)
+{
+    std::vector<uintptr_t> key(p->n_inst);
+    for (int i = 0; i < p->n_inst; ++i) key[i] = (uintptr_t)host[i];
+    auto it = p->tables.find(key);
+    if (it != p->tables.end()) {
+        *out = (T *)it->second;
+        return LBM_OK;
+    }
+    if (p->tables.size() >= 64) {
+        HIPCHK(hipDeviceSynchronize());
+        for (auto &kv : p->tables) HIPCHK(hipFree(kv.second));
+        p->tables.clear();
+    }
+    void *d = nullptr;
+    HIPCHK(hipMalloc(&d, sizeof(uintptr_t) * p->n_inst));
+    HIPCHK(hipMemcpy(d, key.data(), sizeof(uintptr_t) * p->n_inst, hipMemcpyHostToDevice));
+    p->tables[key] = d;
+    *out = (T *)d;
+    return LBM_OK;
+}
+
+bool step_accumulates(const lbm_plan *p, int64_t n) { return p->avg_begin < n && n < p->avg_end; }
+
+int flush(lbm_plan *p, hipStream_t s)
+{
+    if (launch_flush(p->block, p->geo_d, p->tiles_d, p->n_tiles, s)) return fail(LBM_E_HIP, "flush launch failed");
+    p->pending = 0;
+    return LBM_OK;
+}
+
+int ensure_graph(lbm_plan *p)
+{
+    if (p->gexec) return LBM_OK;
+    hipStream_t cap;
+    HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    StepArgs a{};
+    a.step = (p->ramp_max + 1) / 2 * 2 + 2;
+    HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < p->graph_pairs; ++k) {
+        launch_step(p->block, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, cap);
+        launch_step(p->block, p->model, 1, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, cap);
+    }
+    hipGraph_t g;
+    HIPCHK(hipStreamEndCapture(cap, &g));
+    HIPCHK(hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0));
+    HIPCHK(hipGraphDestroy(g));
+    HIPCHK(hipStreamDestroy(cap));
+    return LBM_OK;
+}
+
+bool pair_plain(const lbm_plan *p, int64_t n)
+{
+    for (int64_t m = n; m < n + 2; ++m) {
+        if (m < p->ramp_max) return false;
+        if (p->avg_end > p->avg_begin && m >= p->avg_begin && m < p->avg_end + 1) return false;
+    }
+    return true;
+}
+
+int run_steps(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_d, int32_t n_slots, hipStream_t s)
+{
+    int32_t left = n_steps;
+    while (left > 0) {
+        const int64_t n = p->step;
+        // replay captured pairs over stretches without ramp, QoI or recording
+        if (p->use_graph && kind == 0 && (n & 1) == 0 && left >= 2 * p->graph_pairs) {
+            bool plain = true;
+            for (int k = 0; k < p->graph_pairs && plain; ++k) plain = pair_plain(p, n + 2 * k);
+            if (plain) {
+                int r = ensure_graph(p);
+                if (r) return r;
+                HIPCHK(hipGraphLaunch(p->gexec, s));
+                p->step += 2 * p->graph_pairs;
+                left -= 2 * p->graph_pairs;
+                continue;
+            }
+        }
+        StepArgs a{};
+        a.step = n;
+        a.accumulate = step_accumulates(p, n) ? 1 : 0;
+        a.record = kind;
+        a.rec = rec_d;
+        a.rec_slot = kind ? (n % n_slots) : 0;
+        if (launch_step(p->block, p->model, (int)(n & 1), p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s))
+            return fail(LBM_E_HIP, "step launch failed: %s", hipGetErrorString(hipGetLastError()));
+        p->step = n + 1;
+        --left;
+        if (a.accumulate) ++p->pending;
+        if (p->avg_end > p->avg_begin && p->step == p->avg_end && p->step > p->avg_begin) {
+            // the last state of the window is never collided inside the window
+            if (launch_capture(p->block, (int)(p->step & 1), p->geo_d, p->tiles_d, p->n_tiles, p->step,
+                               p->health_d, s))
+                return fail(LBM_E_HIP, "capture launch failed");
+            ++p->pending;
+            int r = flush(p, s);
+            if (r) return r;
+        } else if (p->pending >= p->flush_every) {
+            int r = flush(p, s);
+            if (r) return r;
+        }
+    }
+    return LBM_OK;
+}
+
+int check_plan(const lbm_plan *p)
+{
+    if (!p) return fail(LBM_E_INVALID, "plan is NULL");
+    return LBM_OK;
+}
+
+std::string tune_key(const lbm_plan *p)
+{
+    hipDeviceProp_t prop;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipGetDeviceProperties(&prop, dev);
+    std::vector<std::string> dims;
+    for (auto &in : p->inst) {
+        char b[64];
+        snprintf(b, sizeof b, "%dx%dx%d", in.dom.nx, in.dom.ny, in.dom.nz);
+        dims.push_back(b);
+    }
+    std::sort(dims.begin(), dims.end());
+    std::ostringstream os;
+    os << std::string(prop.gcnArchName).substr(0, 6) << "|m" << p->model << "|n" << p->n_inst;
+    // run-length encoded multiset of box sizes
+    for (size_t i = 0; i < dims.size();) {
+        size_t j = i;
+        while (j < dims.size() && dims[j] == dims[i]) ++j;
+        os << "|" << dims[i] << "*" << (j - i);
+        i = j;
+    }
+    return os.str();
+}
+
+std::string tune_path()
+{
+    const char *e = std::getenv("LBMSC_TUNE_CACHE");
+    if (e && *e) return e;
+    const char *h = std::getenv("HOME");
+    return std::string(h ? h : ".") + "/.cache/lbmsc_tune.json";
+}
+
+std::map<std::string, int> read_tune_cache()
+{
+    std::map<std::string, int> m;
+    std::ifstream in(tune_path());
+    if (!in) return m;
+    std::stringstream ss;
+    ss << in.rdbuf();
+    const std::string t = ss.str();
+    size_t pos = 0;
+    for (;;) {
+        size_t a = t.find('"', pos);
+        if (a == std::string::npos) break;
+        size_t b = t.find('"', a + 1);
+        if (b == std::string::npos) break;
+        size_t c = t.find(':', b);
+        if (c == std::string::npos) break;
+        m[t.substr(a + 1, b - a - 1)] = std::atoi(t.c_str() + c + 1);
+        pos = c + 1;
+    }
+    return m;
+}
+
+void write_tune_cache(const std::map<std::string, int> &m)
+{
+    const std::string path = tune_path();
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {
+        std::string dir = path.substr(0, slash);
+        std::string cmd = "mkdir -p '" + dir + "'";
+        if (std::system(cmd.c_str()) != 0) return;
+    }
+    std::ofstream out(path + ".tmp");
+    out << "{\n";
+    size_t k = 0;
+    for (auto &kv : m) out << "  \"" << kv.first << "\": " << kv.second << (++k < m.size() ? ",\n" : "\n");
+    out << "}\n";
+    out.close();
+    std::rename((path + ".tmp").c_str(), path.c_str());
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+const char *lbm_version(void) { return "lbmsc 1.0 (gfx950, D3Q19 AA in-place, BGK/Smagorinsky, adjoint)"; }
+
+int lbm_quadrature(int32_t kind, int32_t level, int32_t dim, double *nodes_host, double *weights_host, int32_t cap,
+                   int32_t *n_out)
+{
+    std::vector<double> x, w;
+    if (kind == LBM_QUAD_GAUSS_LEGENDRE) {
+        if (dim != 1) return fail(LBM_E_INVALID, "Gauss-Legendre rules are one-dimensional");
+        if (level < 1 || level > 256) return fail(LBM_E_INVALID, "Gauss-Legendre point count %d out of range", level);
+        if (!gauss_legendre(level, x, w)) return fail(LBM_E_INVALID, "Gauss-Legendre eigen-solve failed");
+    } else if (kind == LBM_QUAD_SMOLYAK_CC) {
+        if (!smolyak_cc(level, dim, x, w)) return fail(LBM_E_INVALID, "Smolyak level %d dim %d not supported", level, dim);
+    } else {
+        return fail(LBM_E_INVALID, "unknown quadrature kind %d", kind);
+    }
+    const int32_t n = (int32_t)w.size();
+    if (n_out) *n_out = n;
+    if (!nodes_host && !weights_host) return LBM_OK;
+    if (!nodes_host || !weights_host) return fail(LBM_E_INVALID, "nodes and weights must both be given");
+    if (cap < n) return fail(LBM_E_INVALID, "capacity %d < %d nodes", cap, n);
+    std::memcpy(nodes_host, x.data(), sizeof(double) * x.size());
+    std::memcpy(weights_host, w.data(), sizeof(double) * w.size());
+    return LBM_OK;
+}
+
+int lbm_node_params(const double *xi_host, int32_t dim, double base, double rel, double angle_deg, double z0,
+                    float theta_out[3])
+{
+    if (!xi_host || !theta_out || dim < 1) return fail(LBM_E_INVALID, "bad arguments to lbm_node_params");
+    theta_out[0] = (float)(base * (1.0 + rel * xi_host[0]));
+    theta_out[1] = dim > 1 ? (float)(angle_deg * xi_host[1] * M_PI / 180.0) : 0.0f;
+    theta_out[2] = (float)z0;
+    return LBM_OK;
+}
+
+int64_t lbm_geometry_bytes(const lbm_domain *dom, int32_t n_probes)
+{
+    if (check_domain(dom) || n_probes < 0) return -1;
+    const int64_t n = ncells_of(dom);
+    return align256(n) + align256(4 * n) + align256(4 * (int64_t)std::max(1, n_probes));
+}
+
+int64_t lbm_population_stride(const lbm_domain *dom)
+{
+    if (check_domain(dom)) return -1;
+    return stride_of(ncells_of(dom));
+}
+
+int lbm_init_geometry(const lbm_domain *dom, const uint8_t *solid_host, const int32_t *probe_host, int32_t n_probes,
+                      void *geom_dev, float *f_dev, hipStream_t stream)
+{
+    int r = check_domain(dom);
+    if (r) return r;
+    if (!solid_host || !geom_dev || !f_dev) return fail(LBM_E_INVALID, "NULL buffer");
+    if (n_probes < 0 || (n_probes > 0 && !probe_host)) return fail(LBM_E_INVALID, "bad probe list");
+    r = check_device();
+    if (r) return r;
+    const int64_t n = ncells_of(dom);
+    const int nx = dom->nx, ny = dom->ny, nz = dom->nz;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                if (!solid_host[((int64_t)z * ny + y) * nx + x]) continue;
+                if (dom->face[5] == LBM_FREESLIP && z == nz - 1)
+                    return fail(LBM_E_INVALID, "solid cell (%d,%d,%d) in the layer under a free-slip sky", x, y, z);
+                if (dom->face[1] == LBM_OUTLET && x >= nx - 2)
+                    return fail(LBM_E_INVALID, "solid cell (%d,%d,%d) in the last two columns before an outlet", x, y, z);
+            }
+    for (int32_t k = 0; k < n_probes; ++k) {
+        const int32_t c = probe_host[k];
+        if (c < 0 || c >= n) return fail(LBM_E_INVALID, "probe %d outside the box", k);
+        if (k > 0 && c <= probe_host[k - 1]) return fail(LBM_E_INVALID, "probe cells must be strictly increasing");
+        if (solid_host[c]) return fail(LBM_E_INVALID, "probe %d sits in a solid cell", k);
+    }
+    const int64_t qs = stride_of(n);
+    GeoPtrs gp = geo_ptrs(geom_dev, dom);
+    HIPCHK(hipStreamSynchronize(stream));
+    if (n_probes > 0) HIPCHK(hipMemcpy(gp.probes, probe_host, sizeof(int32_t) * n_probes, hipMemcpyHostToDevice));
+    // stage the solid mask in the last population plane (cleared right after)
+    uint8_t *stage = (uint8_t *)(f_dev + 18 * qs);
+    HIPCHK(hipMemcpy(stage, solid_host, (size_t)n, hipMemcpyHostToDevice));
+    if (launch_init_geometry(box_of(dom), stage, gp.flags, gp.smask, gp.probes, n_probes, stream))
+        return fail(LBM_E_HIP, "geometry kernel launch failed");
+    HIPCHK(hipMemsetAsync(f_dev, 0, sizeof(float) * 19 * (size_t)qs, stream));
+    return LBM_OK;
+}
+
+int lbm_plan_create(const lbm_instance *inst, int32_t n_inst, const lbm_plan_opts *opts, lbm_plan **plan_out)
+{
+    if (!inst || n_inst < 1 || !plan_out) return fail(LBM_E_INVALID, "bad plan arguments");
+    *plan_out = nullptr;
+    int r = check_device();
+    if (r) return r;
+    const int block = opts && opts->block ? opts->block : 256;
+    if (block != 128 && block != 256 && block != 512) return fail(LBM_E_INVALID, "block must be 128, 256 or 512");
+    lbm_plan *p = new lbm_plan();
+    p->n_inst = n_inst;
+    p->block = block;
+    p->inst.assign(inst, inst + n_inst);
+    p->model = inst[0].model;
+    if (opts) {
+        p->avg_begin = opts->avg_begin;
+        p->avg_end = opts->avg_end;
+        p->use_graph = opts->use_graph != 0;
+    }
+    p->geo_h.resize(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        const lbm_instance &in = inst[i];
+        r = check_domain(&in.dom);
+        if (!r && (!in.geom_dev || !in.f_dev)) r = fail(LBM_E_INVALID, "instance %d: NULL buffer", i);
+        if (!r && in.model != p->model) r = fail(LBM_E_INVALID, "instance %d: all instances of a plan share one model", i);
+        if (!r && in.model != LBM_BGK && in.model != LBM_SMAGORINSKY) r = fail(LBM_E_INVALID, "instance %d: unknown model", i);
+        if (!r && !(in.tau0 > 0.5f)) r = fail(LBM_E_INVALID, "instance %d: tau0 must exceed 1/2 (got %g)", i, in.tau0);
+        if (!r && !(in.cs >= 0.0f)) r = fail(LBM_E_INVALID, "instance %d: negative Smagorinsky constant", i);
+        if (!r && in.inflow != LBM_INFLOW_UNIFORM && in.inflow != LBM_INFLOW_LOGLAW)
+            r = fail(LBM_E_INVALID, "instance %d: unknown inflow kind", i);
+        if (!r && in.inflow == LBM_INFLOW_LOGLAW && !(in.theta[2] > 0.0f))
+            r = fail(LBM_E_INVALID, "instance %d: log-law roughness z0 must be positive", i);
+        if (!r && ((in.qoi_part_dev == nullptr) != (in.qoi_sum_dev == nullptr)))
+            r = fail(LBM_E_INVALID, "instance %d: QoI partial and sum buffers go together", i);
+        if (!r && in.n_probes < 0) r = fail(LBM_E_INVALID, "instance %d: negative probe count", i);
+        if (r) {
+            delete p;
+            return r;
+        }
+        Geo &g = p->geo_h[i];
+        std::memset(&g, 0, sizeof g);
+        const int64_t n = ncells_of(&in.dom);
+        GeoPtrs gp = geo_ptrs(in.geom_dev, &in.dom);
+        g.f = in.f_dev;
+        g.flags = gp.flags;
+        g.smask = gp.smask;
+        g.probes = gp.probes;
+        g.qpart = in.qoi_part_dev;
+        g.qsum = in.qoi_sum_dev;
+        g.psum = in.probe_sum_dev;
+        g.qs = stride_of(n);
+        g.ncells = (int32_t)n;
+        g.n_probes = in.n_probes;
+        g.box = box_of(&in.dom);
+        g.offy = in.dom.nx;
+        g.offz = in.dom.nx * in.dom.ny;
+        g.dx = make_fastdiv((uint32_t)in.dom.nx);
+        g.dxy = make_fastdiv((uint32_t)(in.dom.nx * in.dom.ny));
+        g.tau0 = in.tau0;
+        g.kcs = in.model == LBM_SMAGORINSKY ? (float)(18.0 * std::sqrt(2.0) * in.cs * in.cs) : 0.0f;
+        g.ramp = in.ramp;
+        set_theta(g, in);
+        p->ramp_max = std::max(p->ramp_max, in.ramp);
+    }
+    if (hipMalloc(&p->geo_d, sizeof(Geo) * n_inst) != hipSuccess ||
+        hipMalloc(&p->health_d, sizeof(int32_t) * n_inst) != hipSuccess ||
+        hipMemset(p->health_d, 0, sizeof(int32_t) * n_inst) != hipSuccess) {
+        lbm_plan_destroy(p);
+        return fail(LBM_E_HIP, "plan allocation failed");
+    }
+    r = build_tiles(p);
+    if (r) {
+        lbm_plan_destroy(p);
+        return r;
+    }
+    *plan_out = p;
+    return LBM_OK;
+}
+
+void lbm_plan_destroy(lbm_plan *p)
+{
+    if (!p) return;
+    (void)hipDeviceSynchronize();
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    for (auto &kv : p->tables) (void)hipFree(kv.second);
+    if (p->geo_d) (void)hipFree(p->geo_d);
+    if (p->tiles_d) (void)hipFree(p->tiles_d);
+    if (p->health_d) (void)hipFree(p->health_d);
+    delete p;
+}
+
+int64_t lbm_plan_step(const lbm_plan *p) { return p ? p->step : -1; }
+
+int lbm_plan_set_step(lbm_plan *p, int64_t step)
+{
+    int r = check_plan(p);
+    if (r) return r;
+    if (step < 0 || (step & 1)) return fail(LBM_E_INVALID, "the step counter can only be set to an even step");
+    p->step = step;
+    p->pending = 0;
+    return LBM_OK;
+}
+
+int lbm_plan_set_theta(lbm_plan *p, int32_t i, const float theta[3])
+{
+    int r = check_plan(p);
+    if (r) return r;
+    if (i < 0 || i >= p->n_inst || !theta) return fail(LBM_E_INVALID, "bad instance index or theta");
+    if (p->inst[i].inflow == LBM_INFLOW_LOGLAW && !(theta[2] > 0.0f)) return fail(LBM_E_INVALID, "z0 must be positive");
+    for (int k = 0; k < 3; ++k) p->inst[i].theta[k] = theta[k];
+    set_theta(p->geo_h[i], p->inst[i]);
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(p->geo_d + i, &p->geo_h[i], sizeof(Geo), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+int lbm_plan_reset_qoi(lbm_plan *p, hipStream_t s)
+{
+    int r = check_plan(p);
+    if (r) return r;
+    for (int i = 0; i < p->n_inst; ++i)
+        if (launch_zero_qoi(p->geo_h[i], s)) return fail(LBM_E_HIP, "zero launch failed");
+    HIPCHK(hipMemsetAsync(p->health_d, 0, sizeof(int32_t) * p->n_inst, s));
+    p->pending = 0;
+    return LBM_OK;
+}
+
+int lbm_sync(lbm_plan *p, hipStream_t s)
+{
+    (void)p;
+    HIPCHK(hipStreamSynchronize(s));
+    return LBM_OK;
+}
+
+int lbm_check_health(lbm_plan *p, hipStream_t s, int32_t *bad_inst)
+{
+    int r = check_plan(p);
+    if (r) return r;
+    std::vector<int32_t> h(p->n_inst);
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(h.data(), p->health_d, sizeof(int32_t) * p->n_inst, hipMemcpyDeviceToHost));
+    for (int i = 0; i < p->n_inst; ++i)
+        if (h[i]) {
+            if (bad_inst) *bad_inst = i;
+            return fail(LBM_E_UNSTABLE, "instance %d became unstable (rho <= 0 or not finite)", i);
+        }
+    if (bad_inst) *bad_inst = -1;
+    return LBM_OK;
+}
+
+int lbm_collide_stream(lbm_plan *p, int32_t n_steps, hipStream_t s)
+{
+    int r = check_plan(p);
+    if (r) return r;
+    if (n_steps < 0) return fail(LBM_E_INVALID, "negative step count");
+    return run_steps(p, n_steps, 0, nullptr, 1, s);
+}
+
+int lbm_collide_stream_record(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_host, int32_t n_slots,
+                              hipStream_t s)
+{
+    int r = check_plan(p);
+    if (r) return r;
+    if (n_steps < 0 || n_slots < 1 || !rec_host) return fail(LBM_E_INVALID, "bad record arguments");
+    if (kind != 1 && kind != 2) return fail(LBM_E_INVALID, "record kind must be 1 (rho,u) or 2 (populations)");
+    for (int i = 0; i < p->n_inst; ++i)
+        if (!rec_host[i]) return fail(LBM_E_INVALID, "instance %d: NULL record buffer", i);
+    float **rec_d = nullptr;
+    r = table_of(p, (float *const *)rec_host, &rec_d);
+    if (r) return r;
+    return run_steps(p, n_steps, kind, rec_d, n_slots, s);
+}
+
+int lbm_read_fields(lbm_plan *p, int32_t i, float *out_dev, hipStream_t s)
+{
+    int r = check_plan(p);
+    if (r) return r;
+    if (i < 0 || i >= p->n_inst || !out_dev) return fail(LBM_E_INVALID, "bad instance index or output");
+    if (launch_fields((int)(p->step & 1), p->geo_d, i, p->geo_h[i], p->step, out_dev, 0, s))
+        return fail(LBM_E_HIP, "fields launch failed");
+    return LBM_OK;
+}
+
+int lbm_read_populations(lbm_plan *p, int32_t i, float *out_dev, hipStream_t s)
+{
+    int r = check_plan(p);
+    if (r) return r;
+    if (i < 0 || i >= p->n_inst || !out_dev) return fail(LBM_E_INVALID, "bad instance index or output");
+    if (launch_fields((int)(p->step & 1), p->geo_d, i, p->geo_h[i], p->step, out_dev, 1, s))
+        return fail(LBM_E_HIP, "populations launch failed");
+    return LBM_OK;
+}
+
+int lbm_qoi_average(lbm_plan *p, int32_t i, float *out_dev, float *probe_out_dev, hipStream_t s)
+{
+    int r = check_plan(p);
+    if (r) return r;
+    if (i < 0 || i >= p->n_inst) return fail(LBM_E_INVALID, "bad instance index");
+    const int64_t cnt = p->avg_end - p->avg_begin;
+    if (cnt <= 0) return fail(LBM_E_INVALID, "the plan has no QoI window");
+    const Geo &g = p->geo_h[i];
+    if (out_dev && !g.qsum) return fail(LBM_E_INVALID, "instance %d has no QoI sums", i);
+    if (probe_out_dev && !g.psum) return fail(LBM_E_INVALID, "instance %d has no probe sums", i);
+    Geo gg = g;
+    if (!out_dev) gg.qsum = nullptr;
+    if (!probe_out_dev) gg.n_probes = 0;
+    if (launch_average(gg, 1.0 / (double)cnt, out_dev, probe_out_dev, s)) return fail(LBM_E_HIP, "average launch failed");
+    return LBM_OK;
+}
+
+int lbm_sc_moments(const float *q_dev, const double *w_host, int32_t n_nodes, int64_t n_elems, double *mean_dev,
+                   double *var_dev, unsigned long long *n_negative_dev, hipStream_t stream)
+{
+    if (!q_dev || !w_host || !mean_dev || !var_dev) return fail(LBM_E_INVALID, "NULL buffer");
+    if (n_nodes < 1 || n_nodes > 256) return fail(LBM_E_INVALID, "node count %d outside [1, 256]", n_nodes);
+    if (n_elems < 0) return fail(LBM_E_INVALID, "negative element count");
+    double sw = 0.0;
+    for (int j = 0; j < n_nodes; ++j) sw += w_host[j];
+    if (std::fabs(sw - 1.0) > 1e-12) return fail(LBM_E_INVALID, "weights sum to %.17g, not 1", sw);
+    if (n_elems == 0) return LBM_OK;
+    if (launch_moments(q_dev, w_host, n_nodes, n_elems, mean_dev, var_dev, n_negative_dev, stream))
+        return fail(LBM_E_HIP, "moments launch failed");
+    return LBM_OK;
+}
+
+int lbm_adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float *const *lam_out_host,
+                     float *const *rec_host, int32_t kind, int32_t n_slots, const double *const *pw_host,
+                     double *dJdtheta_dev, hipStream_t s)
+{
+    int r = check_plan(p);
+    if (r) return r;
+    if (!lam_in_host || !lam_out_host || !rec_host || !pw_host || !dJdtheta_dev || n_slots < 1 || step < 0)
+        return fail(LBM_E_INVALID, "bad adjoint arguments");
+    if (kind != 1 && kind != 2) return fail(LBM_E_INVALID, "record kind must be 1 or 2");
+    if (p->model == LBM_SMAGORINSKY && kind != 2)
+        return fail(LBM_E_INVALID, "the Smagorinsky adjoint needs recorded populations (kind 2)");
+    for (int i = 0; i < p->n_inst; ++i)
+        if (!lam_in_host[i] || !lam_out_host[i] || !rec_host[i] || lam_in_host[i] == lam_out_host[i])
+            return fail(LBM_E_INVALID, "instance %d: missing or aliased adjoint buffers", i);
+    AdjArgs a{};
+    r = table_of(p, (float *const *)lam_in_host, (float ***)&a.lam_in);
+    if (!r) r = table_of(p, (float *const *)lam_out_host, (float ***)&a.lam_out);
+    if (!r) r = table_of(p, (float *const *)rec_host, (float ***)&a.rec);
+    if (!r) r = table_of(p, (const double *const *)pw_host, (const double ***)&a.pw);
+    if (r) return r;
+    a.step = step;
+    a.model = p->model;
+    a.record = kind;
+    a.rec_slot = step % n_slots;
+    a.in_window = (p->avg_begin < step && step <= p->avg_end) ? 1 : 0;
+    a.inv_count = p->avg_end > p->avg_begin ? 1.0 / (double)(p->avg_end - p->avg_begin) : 0.0;
+    a.grad = dJdtheta_dev;
+    if (launch_adjoint(p->block, p->geo_d, p->tiles_d, p->n_tiles, a, s))
+        return fail(LBM_E_HIP, "adjoint launch failed: %s", hipGetErrorString(hipGetLastError()));
+    return LBM_OK;
+}
+
+int lbm_adjoint_init(lbm_plan *p, float *const *lam_out_host, const double *const *pw_host, hipStream_t s)
+{
+    int r = check_plan(p);
+    if (r) return r;
+    if (!lam_out_host || !pw_host) return fail(LBM_E_INVALID, "bad adjoint arguments");
+    if (p->step & 1) return fail(LBM_E_INVALID, "the adjoint starts from an even step");
+    for (int i = 0; i < p->n_inst; ++i)
+        if (!lam_out_host[i]) return fail(LBM_E_INVALID, "instance %d: NULL adjoint buffer", i);
+    AdjArgs a{};
+    r = table_of(p, (float *const *)lam_out_host, (float ***)&a.lam_out);
+    if (!r) r = table_of(p, (const double *const *)pw_host, (const double ***)&a.pw);
+    if (r) return r;
+    a.step = p->step;
+    a.model = p->model;
+    a.in_window = (p->avg_begin < p->step && p->step <= p->avg_end) ? 1 : 0;
+    a.inv_count = p->avg_end > p->avg_begin ? 1.0 / (double)(p->avg_end - p->avg_begin) : 0.0;
+    if (launch_adjoint_init(p->block, p->geo_d, p->tiles_d, p->n_tiles, a, s))
+        return fail(LBM_E_HIP, "adjoint init launch failed");
+    return LBM_OK;
+}
+
+int lbm_plan_autotune(lbm_plan *p, hipStream_t s, int32_t *block_out)
+{
+    int r = check_plan(p);
+    if (r) return r;
+    if (p->step & 1) return fail(LBM_E_INVALID, "autotune from an even step");
+    const std::string key = tune_key(p);
+    std::map<std::string, int> cache = read_tune_cache();
+    auto it = cache.find(key);
+    int best = 0;
+    if (it != cache.end() && (it->second == 128 || it->second == 256 || it->second == 512)) {
+        best = it->second;
+    } else {
+        // save the populations, time step pairs for each block size, restore
+        std::vector<size_t> bytes(p->n_inst);
+        size_t total = 0;
+        for (int i = 0; i < p->n_inst; ++i) total += (bytes[i] = sizeof(float) * 19 * (size_t)p->geo_h[i].qs);
+        char *save = nullptr;
+        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(hipMalloc(&save, total));
+        size_t off = 0;
+        for (int i = 0; i < p->n_inst; ++i) {
+            HIPCHK(hipMemcpyAsync(save + off, p->geo_h[i].f, bytes[i], hipMemcpyDeviceToDevice, s));
+            off += bytes[i];
+        }
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        float best_ms = 1e30f;
+        const int cand[3] = {256, 128, 512};
+        const int saved_block = p->block;
+        for (int bs : cand) {
+            p->block = bs;
+            r = build_tiles(p);
+            if (r) break;
+            StepArgs a{};
+            a.step = p->ramp_max + 2;
+            for (int w = 0; w < 2; ++w) {
+                launch_step(bs, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
+                launch_step(bs, p->model, 1, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
+            }
+            HIPCHK(hipEventRecord(e0, s));
+            const int pairs = 6;
+            for (int w = 0; w < pairs; ++w) {
+                launch_step(bs, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
+                launch_step(bs, p->model, 1, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
+            }
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = bs;
+            }
+        }
+        if (!best) best = saved_block;
+        off = 0;
+        for (int i = 0; i < p->n_inst; ++i) {
+            HIPCHK(hipMemcpyAsync(p->geo_h[i].f, save + off, bytes[i], hipMemcpyDeviceToDevice, s));
+            off += bytes[i];
+        }
+        HIPCHK(hipMemsetAsync(p->health_d, 0, sizeof(int32_t) * p->n_inst, s));
+        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(hipFree(save));
+        HIPCHK(hipEventDestroy(e0));
+        HIPCHK(hipEventDestroy(e1));
+        if (r) return r;
+        cache[key] = best;
+        write_tune_cache(cache);
+    }
+    p->block = best;
+    r = build_tiles(p);
+    if (r) return r;
+    if (block_out) *block_out = best;
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,209 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+* every function declared in include/lbm_sc.h is exported by liblbmsc.so and
+  bound by the Python binding;
+* host-only entry points (collocation rules, node parameters, sizes, argument
+  validation) against the oracle;
+* the link rules the kernels use, via the host build of the same header:
+  the scatter map is the exact inverse of the gather map, the in-place odd
+  step is race-free for every workgroup size, and the rule kinds equal the
+  oracle's independent implementation.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2508_18202_amd import inputs
+from paper_2508_18202_amd import lbmsc as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm_sc.h")
+HOSTCHECK = os.path.join(ROOT, "paper_2508_18202_amd", "liblbmsc_hostcheck.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    lib = ctypes.CDLL(L.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(L.EXPORTED) == names
+
+
+def test_version_and_error_channel():
+    assert "gfx950" in L.lbm_version()
+    with pytest.raises(L.LbmError):
+        L.lbm_quadrature("gauss_legendre", 5, 2)
+    assert "one-dimensional" in L.lbm_last_error()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 11, 20])
+def test_gauss_legendre_matches_oracle(n):
+    x, w = L.lbm_quadrature("gauss_legendre", n, 1)
+    xo, wo = orc.gauss_legendre(n)
+    assert np.abs(x[:, 0] - xo).max() < 1e-14
+    assert np.abs(w - wo).max() < 1e-14
+
+
+@pytest.mark.parametrize("level,dim", [(0, 2), (1, 2), (2, 2), (3, 2), (2, 3), (1, 1), (3, 1)])
+def test_smolyak_matches_oracle(level, dim):
+    x, w = L.lbm_quadrature("smolyak_cc", level, dim)
+    xo, wo = orc.smolyak_cc(level, dim)
+    key = lambda X: [tuple(np.round(p, 10) + 0.0) for p in X]
+    a = dict(zip(key(x), w))
+    b = dict(zip(key(xo), wo))
+    assert set(a) == set(b)
+    for k in a:
+        assert abs(a[k] - b[k]) < 1e-14
+
+
+def test_node_params_match_oracle():
+    for w in (inputs.cfg1(), inputs.cfg2(), inputs.cfg4()):
+        x, _ = L.lbm_quadrature(w.quadrature, w.quad_level, w.quad_dim)
+        for xi in x:
+            th = L.lbm_node_params(xi, w.speed_base, w.speed_rel, w.angle_deg, w.z0)
+            tho = orc.node_params(w, xi)
+            assert np.abs(th - tho).max() < 1e-7 * max(1.0, np.abs(tho).max())
+
+
+def test_sizes_and_validation():
+    d = L.domain(256, 128, 64, inputs.URBAN_FACES)
+    qs = L.lbm_population_stride(d)
+    assert qs >= 256 * 128 * 64 and qs % 64 == 0 and (qs // 64) % 2 == 1
+    assert L.lbm_geometry_bytes(d, 0) >= 5 * 256 * 128 * 64
+    bad = [
+        L.domain(33, 16, 16, inputs.BOX_FACES),                                            # odd nx with outlet
+        L.domain(32, 16, 16, ("outlet", "inlet", "wall", "wall", "wall", "wall")),        # kinds on wrong faces
+        L.domain(32, 16, 16, ("inlet", "outlet", "periodic", "wall", "wall", "wall")),    # unpaired periodic
+        L.domain(32, 16, 16, ("inlet", "outlet", "wall", "wall", "freeslip", "wall")),    # free-slip ground
+        L.domain(0, 16, 16, inputs.BOX_FACES),
+    ]
+    for b in bad:
+        with pytest.raises(L.LbmError):
+            L.lbm_population_stride(b)
+
+
+# ---------------------------------------------------------------- link rules
+
+_hc = None
+
+
+def hostcheck():
+    global _hc
+    if _hc is None:
+        _hc = ctypes.CDLL(HOSTCHECK)
+        _hc.lbmhc_check.restype = ctypes.c_int
+        _hc.lbmhc_fastdiv.restype = ctypes.c_int
+    return _hc
+
+
+FACE_SETS = [
+    inputs.BOX_FACES,
+    inputs.URBAN_FACES,
+    ("inlet", "outlet", "wall", "wall", "wall", "freeslip"),
+    ("periodic", "periodic", "periodic", "periodic", "periodic", "periodic"),
+    ("wall", "wall", "wall", "wall", "wall", "wall"),
+    ("inlet", "outlet", "periodic", "periodic", "periodic", "periodic"),
+    ("periodic", "periodic", "wall", "wall", "wall", "freeslip"),
+    ("inlet", "wall", "periodic", "periodic", "wall", "wall"),
+]
+
+
+def _random_solid(nx, ny, nz, faces, seed):
+    rng = np.random.default_rng(seed)
+    s = (rng.random((nz, ny, nx)) < 0.15).astype(np.uint8)
+    if faces[5] == "freeslip":
+        s[nz - 1] = 0
+    if faces[1] == "outlet":
+        s[:, :, nx - 2:] = 0
+    return s
+
+
+def _check(nx, ny, nz, faces, solid, block):
+    face = (ctypes.c_int * 6)(*[L.FACES[f] for f in faces])
+    stats = (ctypes.c_int64 * 6)()
+    s = np.ascontiguousarray(solid, np.uint8)
+    rc = hostcheck().lbmhc_check(nx, ny, nz, face, s.ctypes.data_as(ctypes.c_void_p), block, stats)
+    return rc, list(stats)
+
+
+@pytest.mark.parametrize("faces", FACE_SETS)
+@pytest.mark.parametrize("block", [128, 256, 512])
+def test_scatter_is_inverse_and_race_free(faces, block):
+    for seed, (nx, ny, nz) in enumerate([(8, 6, 5), (12, 4, 7), (10, 9, 3), (16, 16, 4)]):
+        solid = _random_solid(nx, ny, nz, faces, seed)
+        rc, stats = _check(nx, ny, nz, faces, solid, block)
+        assert rc == 0, (faces, nx, ny, nz, rc, stats)
+        assert stats[0] > 0
+
+
+@pytest.mark.parametrize("w", [inputs.cfg1(), inputs.scaled(inputs.cfg2(), 64, 32, 24),
+                               inputs.scaled(inputs.cfg4(), 64, 32, 24)])
+def test_workload_geometries_race_free(w):
+    solid = inputs.solid_mask(w)
+    for block in (128, 256, 512):
+        rc, stats = _check(w.nx, w.ny, w.nz, w.faces, solid, block)
+        assert rc == 0, (rc, stats)
+    if w.faces[1] == "outlet":
+        assert stats[2] > 0 and stats[3] > 0      # duplicated outflow values exist and are shared
+
+
+def test_odd_nx_outlet_would_split_rows():
+    """With an odd nx a workgroup boundary can fall between the last two
+    cells of a row; the checker finds the resulting cross-workgroup slot
+    (this is why the library rejects odd nx with an outlet)."""
+    nx, ny, nz = 9, 32, 4
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    rc, stats = _check(nx, ny, nz, inputs.BOX_FACES, solid, 128)
+    assert rc == 10 and stats[4] > 0
+
+
+@pytest.mark.parametrize("faces", FACE_SETS)
+def test_rule_kinds_match_oracle(faces):
+    nx, ny, nz = 10, 7, 6
+    solid = _random_solid(nx, ny, nz, faces, 11)
+    face = (ctypes.c_int * 6)(*[L.FACES[f] for f in faces])
+    mine = np.zeros((19, nx * ny * nz), np.int32)
+    s = np.ascontiguousarray(solid, np.uint8)
+    hostcheck().lbmhc_rules(nx, ny, nz, face, s.ctypes.data_as(ctypes.c_void_p),
+                            mine.ctypes.data_as(ctypes.c_void_p))
+    case = orc.Case(nx, ny, nz, list(faces), solid, tau0=0.6)
+    theirs = case.link_rules()
+    # both number the kinds stream=0, bounce=1, inlet=2, free-slip=3, outlet=4, rest=5
+    assert np.array_equal(mine, theirs)
+
+
+def test_fastdiv_exact():
+    rng = np.random.default_rng(0)
+    for d in [1, 2, 3, 7, 32, 96, 128, 192, 255, 256, 257, 4096, 32768, 49152, 131072, 1 << 20, 12345, (1 << 31) - 1]:
+        v = np.concatenate([np.arange(0, 70000, dtype=np.uint32),
+                            rng.integers(0, 1 << 31, 200000, dtype=np.uint64).astype(np.uint32),
+                            np.array([(1 << 31) - 1, (1 << 31) - 2], dtype=np.uint32)])
+        v = np.ascontiguousarray(v)
+        assert hostcheck().lbmhc_fastdiv(ctypes.c_uint32(d), v.ctypes.data_as(ctypes.c_void_p),
+                                         ctypes.c_int64(v.size)) == 0, d
+
+
+def test_kernel_lattice_matches_oracle():
+    c = (ctypes.c_int * 57)()
+    w = (ctypes.c_float * 19)()
+    o = (ctypes.c_int * 19)()
+    z = (ctypes.c_int * 19)()
+    hostcheck().lbmhc_lattice(c, w, o, z)
+    co, wo, oo = orc.lattice()
+    assert np.array_equal(np.array(list(c)).reshape(19, 3), co)
+    assert np.abs(np.array(list(w)) - wo).max() < 1e-8
+    assert list(o) == list(oo)
+    for i in range(19):
+        zi = list(z)[i]
+        assert (co[zi] == co[i] * np.array([1, 1, -1])).all()

@@ -1,0 +1,286 @@
+"""GPU parity of the HIP path against the FP64 oracle (through the C ABI).
+
+Tolerances (FP32 populations vs FP64 oracle): relative L2 over fluid cells
+<= 1e-5 per velocity channel; <= 1e-4 on quadrature mean and standard
+deviation.  Every comparison uses the same seeded inputs on both sides.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as orc
+from paper_2508_18202_amd import inputs
+from paper_2508_18202_amd import lbmsc as L
+from paper_2508_18202_amd import sc
+from gpu_util import oracle_case, per_channel_rel, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+FIELD_TOL = 1e-5
+MOMENT_TOL = 1e-4
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _ensemble(w, solid, thetas, probes=None, **kw):
+    cg = sc.make_geometry(w, solid, probes)
+    return sc.Ensemble([cg], [thetas], **kw), cg
+
+
+@pytest.mark.parametrize("model", ["bgk", "smagorinsky"])
+def test_step_by_step_populations(model):
+    """Every step of a small case with all boundary kinds: populations after
+    1, 2, 3, 4 and 9 steps (both storage parities) against the oracle."""
+    _say(f"step-by-step {model}")
+    w = inputs.scaled(inputs.cfg2(), 24, 12, 10, model=model, tau0=0.56, cs=0.12 if model != "bgk" else 0.0,
+                      ramp=5)
+    solid = np.zeros((w.nz, w.ny, w.nx), np.uint8)
+    solid[0:5, 3:7, 7:11] = 1
+    solid[0:3, 8:10, 14:16] = 1
+    theta = (0.012, math.radians(4.0), 0.5)
+    ens, cg = _ensemble(w, solid, [theta])
+    case = oracle_case(w, solid, theta)
+    f = case.init()
+    _, wl, _ = orc.lattice()
+    fluid = cg.fluid
+    done = 0
+    try:
+        for target in (1, 2, 3, 4, 9):
+            ens.advance(target - done)
+            while done < target:
+                f = case.step(done, f)
+                done += 1
+            g = ens.populations(0).cpu().numpy().astype(np.float64)
+            ref = f - wl[:, None]
+            err = np.abs(g[:, fluid] - ref[:, fluid]).max()
+            scale = np.abs(ref[:, fluid]).max()
+            assert err <= 1e-5 * scale + 1e-9, (target, err, scale)
+            u = ens.fields(0).cpu().numpy()
+            o = orc.qoi_fields(case, f)
+            for k, e in enumerate(per_channel_rel(u, o, fluid)[:3]):
+                assert e < FIELD_TOL, (target, k, e)
+    finally:
+        ens.close()
+
+
+def test_cfg1_full_parity():
+    """Small case (BGK tau 0.6, 32x16x16, one block, 5 Gauss-Legendre nodes,
+    1000 steps): final velocity fields per node and their moments."""
+    w = inputs.cfg1()
+    solid = inputs.solid_mask(w)
+    _say("cfg1: GPU")
+    r = sc.run_sc(w, solid)
+    ens = r["ensemble"]
+    try:
+        q = r["q"].cpu().numpy()
+        fluid = r["geometry"].fluid
+        x, a = orc.collocation(w)
+        assert np.abs(r["weights"] - a).max() < 1e-14
+        qo = []
+        for j, xi in enumerate(x):
+            _say(f"cfg1: oracle node {j}")
+            th = orc.node_params(w, xi)
+            res = orc.run(oracle_case(w, solid, th), w.steps)
+            qo.append(res["final"])
+            errs = per_channel_rel(q[j], res["final"], fluid)
+            assert max(errs) < FIELD_TOL, (j, errs)
+        qo = np.stack(qo)                       # [nodes, 4, cells]
+        eo, vo = orc.moments(qo, a)
+        mean = r["mean"].cpu().numpy().T        # [4, cells]
+        var = r["var"].cpu().numpy().T
+        for k in range(4):
+            assert rel_l2(mean[k], eo[k], fluid) < MOMENT_TOL
+            assert rel_l2(np.sqrt(np.maximum(var[k], 0)), np.sqrt(np.maximum(vo[k], 0)), fluid) < MOMENT_TOL
+        assert r["n_negative"] == 0            # Gauss-Legendre weights are positive
+    finally:
+        ens.close()
+
+
+@pytest.mark.parametrize("ramp", [1000, 40])
+def test_urban_les_short_horizon(ramp):
+    """Urban LES recipe (Smagorinsky Cs 0.1, log-law inflow, 13 Smolyak nodes)
+    on a reduced 64x32x24 box, 200 steps, time averages over the last 50."""
+    w = inputs.scaled(inputs.cfg2(steps=200, avg_len=50), 64, 32, 24, ramp=ramp)
+    solid = inputs.solid_mask(w)
+    _say(f"urban short ramp={ramp}: GPU")
+    r = sc.run_sc(w, solid)
+    ens = r["ensemble"]
+    try:
+        q = r["q"].cpu().numpy()
+        fluid = r["geometry"].fluid
+        x, a = orc.collocation(w)
+        qo = []
+        for j, xi in enumerate(x):
+            th = orc.node_params(w, xi)
+            res = orc.run(oracle_case(w, solid, th), w.steps, avg_start=w.avg_start)
+            qo.append(res["avg"])
+            errs = per_channel_rel(q[j], res["avg"], fluid)
+            assert max(errs) < FIELD_TOL, (j, errs)
+        qo = np.stack(qo)
+        eo, vo = orc.moments(qo, a)
+        mean = r["mean"].cpu().numpy().T
+        var = r["var"].cpu().numpy().T
+        for k in range(4):
+            assert rel_l2(mean[k], eo[k], fluid) < MOMENT_TOL, k
+            so = np.sqrt(np.maximum(vo[k], 0))
+            assert rel_l2(np.sqrt(np.maximum(var[k], 0)), so, fluid) < MOMENT_TOL, k
+    finally:
+        ens.close()
+
+
+def test_full_size_urban_first_steps():
+    """The bench launch configuration (13 nodes of 256x128x64 in one plan,
+    graph replay on): the first 24 steps of the fastest and slowest nodes
+    against the oracle at full size."""
+    w = inputs.cfg2()
+    solid = inputs.solid_mask(w)
+    x, a, th = sc.collocation(w)
+    cg = sc.make_geometry(w, solid)
+    w0 = inputs.scaled(w, w.nx, w.ny, w.nz, ramp=0)   # full inflow from step 0
+    cg.w = w0
+    ens = sc.Ensemble([cg], [th], use_graph=True)
+    try:
+        _say("full-size urban: GPU 24 steps")
+        ens.advance(24)
+        fluid = cg.fluid
+        xo, ao = orc.collocation(w)
+        for j in (int(np.argmax(th[:, 0])), int(np.argmin(th[:, 0]))):
+            _say(f"full-size urban: oracle node {j}")
+            tho = orc.node_params(w, xo[j])
+            case = oracle_case(w0, solid, tho)
+            res = orc.run(case, 24)
+            u = ens.fields(j).cpu().numpy()
+            errs = per_channel_rel(u, res["final"], fluid)
+            assert max(errs[:2] + errs[3:]) < FIELD_TOL, (j, errs)
+            assert errs[2] < 10 * FIELD_TOL, (j, errs)     # u_z is small this early
+        assert ens.health() == -1
+    finally:
+        ens.close()
+
+
+def test_moments_kernel_against_oracle():
+    rng = np.random.default_rng(3)
+    for nq in (1, 5, 13, 32, 40, 121):
+        q = rng.standard_normal((nq, 1000, 4)).astype(np.float32) * 0.01 + 0.05
+        if nq == 13:
+            _, a = orc.smolyak_cc(2, 2)
+        elif nq == 5:
+            _, a = orc.gauss_legendre(5)
+        else:
+            a = rng.random(nq)
+            a /= a.sum()
+        qt = torch.from_numpy(q).cuda()
+        mean, var, nneg = sc.moments(qt, a, count_negative=True)
+        eo, vo = orc.moments(q.astype(np.float64), a)
+        assert np.abs(mean.cpu().numpy() - eo).max() < 1e-15 * 100
+        assert np.abs(var.cpu().numpy() - vo).max() < 1e-13 * max(1e-30, np.abs(vo).max()) + 1e-18
+        assert nneg == int((vo < 0).sum())
+    # empty input and bad weights
+    mean, var = sc.moments(torch.zeros(3, 0, device="cuda"), np.array([0.2, 0.3, 0.5]))
+    with pytest.raises(L.LbmError):
+        sc.moments(torch.zeros(3, 10, device="cuda"), np.array([0.2, 0.3, 0.6]))
+
+
+def test_batched_uneven_matches_one_at_a_time():
+    """Three box sizes x three nodes in one plan equal the same instances run
+    as separate plans, bit for bit, and each matches the oracle."""
+    sizes = [(32, 16, 12), (48, 24, 16), (64, 32, 20)]
+    base = inputs.cfg3_cases(steps=60)[0]
+    cases, thetas, ws, solids = [], [], [], []
+    xo, ao = orc.collocation(base)
+    sel = [0, 6, 12]
+    for k, (nx, ny, nz) in enumerate(sizes):
+        wk = inputs.scaled(base, nx, ny, nz, ramp=10)
+        sk = inputs.building_array_mask(nx, ny, nz, 3, 2, 77 + k)
+        ws.append(wk)
+        solids.append(sk)
+        cases.append(sc.make_geometry(wk, sk))
+        thetas.append([orc.node_params(wk, xo[j]) for j in sel])
+    ens = sc.Ensemble(cases, thetas, use_graph=False)
+    try:
+        ens.advance(60)
+        batched = [ens.populations(i).cpu().numpy().copy() for i in range(len(ens))]
+    finally:
+        ens.close()
+    i = 0
+    for k in range(3):
+        for j in range(3):
+            single = sc.Ensemble([sc.make_geometry(ws[k], solids[k])], [[thetas[k][j]]], use_graph=False)
+            try:
+                single.advance(60)
+                s = single.populations(0).cpu().numpy()
+                assert np.array_equal(s, batched[i]), (k, j)
+                if j == 1:
+                    res = orc.run(oracle_case(ws[k], solids[k], thetas[k][j]), 60)
+                    u = single.fields(0).cpu().numpy()
+                    errs = per_channel_rel(u, res["final"], solids[k].reshape(-1) == 0)
+                    assert max(errs) < FIELD_TOL, (k, errs)
+            finally:
+                single.close()
+            i += 1
+
+
+@pytest.mark.parametrize("block", [128, 512])
+def test_block_sizes_and_graphs_bitwise(block):
+    w = inputs.scaled(inputs.cfg2(), 64, 32, 24, ramp=4)
+    solid = inputs.solid_mask(w)
+    _, _, th = sc.collocation(w)
+    outs = []
+    for kw in (dict(block=256, use_graph=False), dict(block=block, use_graph=True)):
+        ens, _ = _ensemble(w, solid, th[:3], **kw)
+        try:
+            ens.advance(57)
+            outs.append([ens.populations(i).cpu().numpy() for i in range(3)])
+        finally:
+            ens.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_unstable_instance_is_isolated():
+    """A node whose populations are poisoned is reported by the health check;
+    the other nodes of the batch are bit-identical to a batch without it."""
+    w = inputs.scaled(inputs.cfg2(), 32, 16, 12, ramp=0)
+    solid = inputs.solid_mask(w)
+    _, _, th = sc.collocation(w)
+    ens, cg = _ensemble(w, solid, th[:3], use_graph=False)
+    ref, _ = _ensemble(w, solid, th[:3], use_graph=False)
+    try:
+        ens.f[1][5 * cg.qs + 100] = float("nan")
+        ens.advance(10)
+        ref.advance(10)
+        assert ens.health() == 1
+        assert ref.health() == -1
+        for i in (0, 2):
+            assert np.array_equal(ens.populations(i).cpu().numpy(), ref.populations(i).cpu().numpy())
+    finally:
+        ens.close()
+        ref.close()
+
+
+def test_rejections():
+    w = inputs.cfg1()
+    solid = inputs.solid_mask(w).copy()
+    solid[:, :, w.nx - 1] = 1                     # solid in the outflow column
+    cg = sc.make_geometry(w, solid)
+    f = torch.empty(19 * cg.qs, device="cuda")
+    with pytest.raises(L.LbmError):
+        sc.init_populations(cg, f)
+    good = sc.make_geometry(inputs.scaled(w, w.nx, w.ny, w.nz, tau0=0.5), inputs.solid_mask(w))
+    with pytest.raises(L.LbmError):               # tau0 <= 1/2
+        sc.Ensemble([good], [[(0.05, 0.0, 0.0)]])
