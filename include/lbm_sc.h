@@ -55,7 +55,8 @@ enum {
 };
 
 /* Boundary kind of each box face, order -x, +x, -y, +y, -z, +z (Sec. 2.2
- * boundary list; the box replaces the paper's cylinder, see the design notes).
+ * boundary list, on a box instead of the paper's cylinder: inflow through
+ * the -x face, outflow through +x).
  *   WALL      half-way bounce-back (no-slip building walls and ground);
  *   INLET     local velocity condition as moving-wall bounce-back with
  *             rho_w = 1: f_i = f*_opp(i) + 6 w_i c_i.u_in (only on -x);
@@ -181,7 +182,8 @@ int lbm_plan_autotune(lbm_plan *plan, hipStream_t stream, int32_t *block_out);
  * probe sums of u_x (solid cells contribute nothing). */
 int lbm_collide_stream(lbm_plan *plan, int32_t n_steps, hipStream_t stream);
 
-/* Same, and also record the state of every step n for the adjoint sweep:
+/* Same, and also record the state of every step n for the adjoint sweep
+ * (recording runs do not add to the QoI sums):
  * record_kind 1 saves (rho, u) as [slot][ncells][4] floats (BGK adjoint),
  * record_kind 2 saves f - w as [slot][19][stride] floats (Smagorinsky
  * adjoint); slot = n % n_slots; rec_dev[i] is instance i's buffer. */

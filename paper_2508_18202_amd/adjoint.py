@@ -1,0 +1,194 @@
+"""Checkpointed discrete adjoint of a batched run and its autograd wrapper.
+
+The gradient of probe QoIs with respect to the inflow parameters is not part
+of arXiv 2508.18202; it differentiates the paper's deterministic solver
+(Sec. 2.2) with respect to the uncertain boundary data of Sec. 3 and feeds a
+gradient-based assimilation of the inflow noise model.
+
+Schedule for a run of N steps with snapshots every C steps:
+  forward   advance 0 -> N, copying the populations at steps 0, C, 2C, ...
+  init      lam^N = dj_N/df^N                               (lbm_adjoint_init)
+  segments  for each segment [s0, s1) from last to first:
+              restore the snapshot of s0, re-run s0 -> s1 recording the state
+              of every step (rho, u for BGK; populations for Smagorinsky),
+              then lam^n from lam^{n+1} for n = s1-1 ... s0  (lbm_adjoint_step)
+dJ/dtheta accumulates in FP64 inside the adjoint kernel.
+
+With ``group_size`` set, the forward pass advances the whole batch without
+snapshots, and the reverse sweep runs group by group (each group re-runs its
+own forward with snapshots on a plan of its own), so snapshot and record
+memory scale with the group, not the batch.
+"""
+from __future__ import annotations
+
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import lbmsc as L
+from .sc import Ensemble, init_populations, stream_handle
+
+
+class CheckpointedAdjoint:
+    """Forward run with snapshots and the reverse sweep over one Ensemble.
+
+    The ensemble's plan window (avg_begin, avg_end] defines the objective
+    j_n = sum_p pw[p] u_x(f^n, p) / count; avg_end must equal the run length.
+    """
+
+    def __init__(self, ens: Ensemble, steps: int, ckpt: int = 100, group_size: Optional[int] = None):
+        if steps % 2 or ckpt % 2:
+            raise ValueError("run length and checkpoint spacing must be even")
+        if ens.avg_end != steps:
+            raise ValueError("the QoI window must end at the last step")
+        self.ens = ens
+        self.steps = steps
+        self.ckpt = ckpt
+        n = len(ens)
+        self.groups = [list(range(n))] if not group_size else \
+            [list(range(k, min(n, k + group_size))) for k in range(0, n, group_size)]
+        self.grouped = bool(group_size) and group_size < n
+        self.model = ens.instances[0].model
+        self.kind = L.RECORD_MACROS if self.model == L.BGK else L.RECORD_POPULATIONS
+        self.marks = list(range(0, steps, ckpt))
+        self.snaps: List[List[torch.Tensor]] = []
+        gmax = max(len(g) for g in self.groups)
+        # record and adjoint buffers for the largest group (reused group after group)
+        self.rec: List[torch.Tensor] = []
+        self.lam = [[], []]
+        for k in range(gmax):
+            cgs = [ens.cases[ens.index[g[k]][0]] for g in self.groups if k < len(g)]
+            per_slot = max(4 * cg.ncells if self.kind == L.RECORD_MACROS else 19 * cg.qs for cg in cgs)
+            lam_len = max(19 * cg.qs for cg in cgs)
+            self.rec.append(torch.empty(ckpt * per_slot, dtype=torch.float32, device="cuda"))
+            for b in range(2):
+                self.lam[b].append(torch.empty(lam_len, dtype=torch.float32, device="cuda"))
+        self.grad = torch.zeros(n, 3, dtype=torch.float64, device="cuda")
+        self._subplans = {}
+
+    # ------------------------------------------------------------------ forward
+    def _advance_with_snapshots(self, plan, fs: Sequence[torch.Tensor]):
+        self.snaps = []
+        for s0 in self.marks:
+            self.snaps.append([f.clone() for f in fs])
+            L.lbm_collide_stream(plan, min(self.ckpt, self.steps - s0), stream_handle())
+
+    def forward(self):
+        """Advance the batch from rest to step N; returns the probe averages per instance."""
+        ens = self.ens
+        ens.reset()
+        if self.grouped:
+            ens.advance(self.steps)
+        else:
+            self._advance_with_snapshots(ens.plan, ens.f)
+        out = []
+        for i in range(len(ens)):
+            cg = ens.cases[ens.index[i][0]]
+            p = torch.empty(len(cg.probes), dtype=torch.float32, device="cuda")
+            ens.averages_into(i, None, p)
+            out.append(p)
+        return out
+
+    # ----------------------------------------------------------------- backward
+    def _subplan(self, gi: int):
+        if gi not in self._subplans:
+            insts = []
+            for i in self.groups[gi]:
+                inst = L.lbm_instance.from_buffer_copy(self.ens.instances[i])
+                inst.qoi_part_dev = None
+                inst.qoi_sum_dev = None
+                inst.probe_sum_dev = None
+                insts.append(inst)
+            self._subplans[gi] = L.lbm_plan_create(insts, self.ens.avg_begin, self.ens.avg_end,
+                                                   use_graph=False)
+        return self._subplans[gi]
+
+    def _sweep(self, plan, members: Sequence[int], pw_ptr, grad: torch.Tensor):
+        s = stream_handle()
+        k = len(members)
+        lam_ptr = [[t.data_ptr() for t in self.lam[b][:k]] for b in range(2)]
+        rec_ptr = [t.data_ptr() for t in self.rec[:k]]
+        fs = [self.ens.f[i] for i in members]
+        N = self.steps
+        L.lbm_adjoint_init(plan, lam_ptr[N % 2], pw_ptr, s)
+        for m in reversed(range(len(self.marks))):
+            s0 = self.marks[m]
+            s1 = min(s0 + self.ckpt, N)
+            for f, snap in zip(fs, self.snaps[m]):
+                f.copy_(snap)
+            L.lbm_plan_set_step(plan, s0)
+            L.lbm_collide_stream_record(plan, s1 - s0, self.kind, rec_ptr, self.ckpt, s)
+            for n in range(s1 - 1, s0 - 1, -1):
+                L.lbm_adjoint_step(plan, n, lam_ptr[(n + 1) % 2], lam_ptr[n % 2], rec_ptr,
+                                   self.kind, self.ckpt, pw_ptr, grad.data_ptr(), s)
+
+    def backward(self, pweights: Sequence[Optional[torch.Tensor]]):
+        """dJ/dtheta [n_inst, 3] (FP64) of J_i = sum_p pweights[i][p] <u_x(p)>.
+
+        Leaves every instance at step 0 in the rest state."""
+        ens = self.ens
+        pw = [p.to(torch.float64).contiguous() if p is not None else None for p in pweights]
+        pw_ptr = [p.data_ptr() if p is not None else None for p in pw]
+        self.grad.zero_()
+        if not self.grouped:
+            if L.lbm_plan_step(ens.plan) != self.steps:
+                raise RuntimeError("backward needs the state of the last forward step (call forward first)")
+            self._sweep(ens.plan, self.groups[0], pw_ptr, self.grad)
+        else:
+            for gi, members in enumerate(self.groups):
+                plan = self._subplan(gi)
+                for i in members:
+                    L.lbm_plan_set_theta(plan, members.index(i), list(ens.instances[i].theta))
+                    init_populations(ens.cases[ens.index[i][0]], ens.f[i])
+                L.lbm_plan_set_step(plan, 0)
+                self._advance_with_snapshots(plan, [ens.f[i] for i in members])
+                g = torch.zeros(len(members), 3, dtype=torch.float64, device="cuda")
+                self._sweep(plan, members, [pw_ptr[i] for i in members], g)
+                self.grad[members[0]:members[-1] + 1] = g
+                self.snaps = []
+        # the first snapshot is the rest state at step 0
+        L.lbm_plan_set_step(ens.plan, 0)
+        return self.grad.clone()
+
+    def close(self):
+        for p in self._subplans.values():
+            L.lbm_plan_destroy(p)
+        self._subplans = {}
+
+
+def set_thetas(runner: CheckpointedAdjoint, theta) -> None:
+    """Inflow parameters [n_inst, 3] of every instance of the runner's batch."""
+    ens = runner.ens
+    for i in range(len(ens)):
+        t = [float(v) for v in theta[i]]
+        L.lbm_plan_set_theta(ens.plan, i, t)
+        for k in range(3):
+            ens.instances[i].theta[k] = t[k]
+
+
+class ProbeQoI(torch.autograd.Function):
+    """theta [n_inst, 3] (FP64) -> probe time averages of u_x [n_inst, n_probes].
+
+    The backward pass is the checkpointed discrete adjoint: the incoming
+    gradient becomes the probe weights of the adjoint source.  Requires every
+    instance to share one probe count."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, runner: CheckpointedAdjoint):
+        set_thetas(runner, theta.detach().cpu().numpy())
+        q = runner.forward()
+        ctx.runner = runner
+        ctx.theta_device = theta.device
+        return torch.stack(q).to(torch.float64)
+
+    @staticmethod
+    def backward(ctx, grad_out: torch.Tensor):
+        runner = ctx.runner
+        g = grad_out.to(torch.float64)
+        pw = [g[i].contiguous() for i in range(g.shape[0])]
+        dth = runner.backward(pw)
+        return dth.to(ctx.theta_device), None
+
+
+def probe_qoi(theta: torch.Tensor, runner: CheckpointedAdjoint) -> torch.Tensor:
+    return ProbeQoI.apply(theta, runner)

@@ -263,7 +263,8 @@ int run_steps(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_d, i
         }
         StepArgs a{};
         a.step = n;
-        a.accumulate = step_accumulates(p, n) ? 1 : 0;
+        // recording runs re-play steps for the adjoint and leave the QoI sums alone
+        a.accumulate = (kind == 0 && step_accumulates(p, n)) ? 1 : 0;
         a.record = kind;
         a.rec = rec_d;
         a.rec_slot = kind ? (n % n_slots) : 0;
@@ -272,7 +273,7 @@ int run_steps(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_d, i
         p->step = n + 1;
         --left;
         if (a.accumulate) ++p->pending;
-        if (p->avg_end > p->avg_begin && p->step == p->avg_end && p->step > p->avg_begin) {
+        if (kind == 0 && p->avg_end > p->avg_begin && p->step == p->avg_end && p->step > p->avg_begin) {
             // the last state of the window is never collided inside the window
             if (launch_capture(p->block, (int)(p->step & 1), p->geo_d, p->tiles_d, p->n_tiles, p->step,
                                p->health_d, s))
@@ -671,13 +672,14 @@ int lbm_qoi_average(lbm_plan *p, int32_t i, float *out_dev, float *probe_out_dev
 int lbm_sc_moments(const float *q_dev, const double *w_host, int32_t n_nodes, int64_t n_elems, double *mean_dev,
                    double *var_dev, unsigned long long *n_negative_dev, hipStream_t stream)
 {
-    if (!q_dev || !w_host || !mean_dev || !var_dev) return fail(LBM_E_INVALID, "NULL buffer");
+    if (!w_host) return fail(LBM_E_INVALID, "NULL weights");
     if (n_nodes < 1 || n_nodes > 256) return fail(LBM_E_INVALID, "node count %d outside [1, 256]", n_nodes);
     if (n_elems < 0) return fail(LBM_E_INVALID, "negative element count");
     double sw = 0.0;
     for (int j = 0; j < n_nodes; ++j) sw += w_host[j];
     if (std::fabs(sw - 1.0) > 1e-12) return fail(LBM_E_INVALID, "weights sum to %.17g, not 1", sw);
     if (n_elems == 0) return LBM_OK;
+    if (!q_dev || !mean_dev || !var_dev) return fail(LBM_E_INVALID, "NULL buffer");
     if (launch_moments(q_dev, w_host, n_nodes, n_elems, mean_dev, var_dev, n_negative_dev, stream))
         return fail(LBM_E_HIP, "moments launch failed");
     return LBM_OK;

@@ -82,8 +82,8 @@ class Workload:
     ramp: int                       # inflow ramp length T_r in steps (0: none)
     n_cases: int = 1
     seed_base: int = 0
-    buildings: Optional[Tuple[int, int]] = None   # (n_bx, n_by) array, None: cfg1 block
-    probe_kind: Optional[str] = None              # "plane" (cfg4) or "points" (cfg5)
+    buildings: Optional[Tuple[int, int]] = None   # (n_bx, n_by) array, None: the single block
+    probe_kind: Optional[str] = None              # "plane" or "points", see probe_cells
     ckpt_every: int = 0
 
     @property
@@ -119,7 +119,7 @@ def building_array_mask(nx: int, ny: int, nz: int, nbx: int, nby: int,
     return mask
 
 
-def cfg1_block_mask(nx: int = 32, ny: int = 16, nz: int = 16) -> np.ndarray:
+def small_block_mask(nx: int = 32, ny: int = 16, nz: int = 16) -> np.ndarray:
     """The single 6x6x8 block of the small case: x in [10,16), y in [5,11), z in [0,8)."""
     mask = np.zeros((nz, ny, nx), dtype=np.uint8)
     mask[0:8, 5:11, 10:16] = 1
@@ -128,13 +128,13 @@ def cfg1_block_mask(nx: int = 32, ny: int = 16, nz: int = 16) -> np.ndarray:
 
 def solid_mask(w: Workload, case: int = 0) -> np.ndarray:
     if w.buildings is None:
-        return cfg1_block_mask(w.nx, w.ny, w.nz)
+        return small_block_mask(w.nx, w.ny, w.nz)
     return building_array_mask(w.nx, w.ny, w.nz, w.buildings[0], w.buildings[1],
                                w.seed(case))
 
 
 def probe_cells(w: Workload, mask: np.ndarray) -> np.ndarray:
-    """Linear cell indices (x fastest) of the probe set, int64, fluid cells only.
+    """Sorted linear cell indices (x fastest) of the probe set, int64, fluid cells only.
 
     * "plane": the y-z plane at x = 3nx/4, y in [ny/4, 3ny/4), z in [0, nz/3),
       i.e. 32 x 16 cells at the 128x64x48 size; solid cells are left out.
@@ -171,30 +171,31 @@ def probe_cells(w: Workload, mask: np.ndarray) -> np.ndarray:
                 order = np.lexsort((fx, fy, d2))
                 k = order[0]
                 out.append((zp * ny + int(fy[k])) * nx + int(fx[k]))
-        return np.asarray(out, dtype=np.int64)
+        return np.sort(np.asarray(out, dtype=np.int64))
     raise ValueError(f"unknown probe kind {w.probe_kind!r}")
 
 
 BOX_FACES = ("inlet", "outlet", "wall", "wall", "wall", "wall")
 URBAN_FACES = ("inlet", "outlet", "periodic", "periodic", "wall", "freeslip")
 
-# Molecular relaxation time of the LES cases (nu = 5e-4 in lattice units); the
-# workloads do not fix it, see the design notes.
+# Molecular relaxation time of the LES cases (nu = 5e-4 in lattice units).  The
+# workload descriptions leave it open; with Cs = 0.1 this value keeps the FP64
+# reference finite through 2000 steps of the 256x128x64 urban case.
 LES_TAU0 = 0.5015
 
 
-def cfg1() -> Workload:
+def small_block() -> Workload:
     """Small plain SC-LBM case: BGK tau=0.6, 32x16x16 box, one block, 5 GL nodes."""
-    return Workload(name="cfg1_small_bgk", nx=32, ny=16, nz=16, faces=BOX_FACES,
+    return Workload(name="small_block_bgk_32x16x16", nx=32, ny=16, nz=16, faces=BOX_FACES,
                     model="bgk", tau0=0.6, cs=0.0, inflow="uniform",
                     speed_base=0.05, speed_rel=0.1, angle_deg=0.0, z0=0.0,
                     quadrature="gauss_legendre", quad_level=5, quad_dim=1,
                     steps=1000, avg_start=1000, ramp=0, seed_base=1000)
 
 
-def cfg2(steps: int = 20000, avg_len: int = 5000) -> Workload:
+def urban_les(steps: int = 20000, avg_len: int = 5000) -> Workload:
     """Urban-like LES ensemble: Smagorinsky Cs=0.1, 256x128x64, 6x4 buildings, 13 Smolyak nodes."""
-    return Workload(name="cfg2_urban_les", nx=256, ny=128, nz=64, faces=URBAN_FACES,
+    return Workload(name="urban_les_256x128x64", nx=256, ny=128, nz=64, faces=URBAN_FACES,
                     model="smagorinsky", tau0=LES_TAU0, cs=0.1, inflow="loglaw",
                     speed_base=0.004, speed_rel=0.15, angle_deg=5.0, z0=0.5,
                     quadrature="smolyak_cc", quad_level=2, quad_dim=2,
@@ -202,16 +203,16 @@ def cfg2(steps: int = 20000, avg_len: int = 5000) -> Workload:
                     seed_base=2000, buildings=(6, 4))
 
 
-CFG3_SIZES = ((128, 64, 32), (192, 96, 48), (256, 128, 64))
+UNEVEN_SIZES = ((128, 64, 32), (192, 96, 48), (256, 128, 64))
 
 
-def cfg3_cases(steps: int = 5000, per_size: int = 16) -> List[Workload]:
+def uneven_cases(steps: int = 5000, per_size: int = 16) -> List[Workload]:
     """48 uneven cases (16 per size) of the batched run; each gets 13 Smolyak nodes."""
     out = []
     case = 0
-    for (nx, ny, nz) in CFG3_SIZES:
+    for (nx, ny, nz) in UNEVEN_SIZES:
         for _ in range(per_size):
-            out.append(Workload(name=f"cfg3_{nx}x{ny}x{nz}_{case}", nx=nx, ny=ny, nz=nz,
+            out.append(Workload(name=f"uneven_{nx}x{ny}x{nz}_{case}", nx=nx, ny=ny, nz=nz,
                                 faces=URBAN_FACES, model="smagorinsky", tau0=LES_TAU0,
                                 cs=0.1, inflow="loglaw", speed_base=0.004,
                                 speed_rel=0.15, angle_deg=5.0, z0=0.5,
@@ -222,9 +223,9 @@ def cfg3_cases(steps: int = 5000, per_size: int = 16) -> List[Workload]:
     return out
 
 
-def cfg4(steps: int = 2000, avg_len: int = 500) -> Workload:
+def adjoint_case(steps: int = 2000, avg_len: int = 500) -> Workload:
     """Adjoint case: BGK tau=0.6, 128x64x48, 4x3 buildings, probe-plane QoI, 13 nodes."""
-    return Workload(name="cfg4_adjoint_bgk", nx=128, ny=64, nz=48, faces=URBAN_FACES,
+    return Workload(name="adjoint_bgk_128x64x48", nx=128, ny=64, nz=48, faces=URBAN_FACES,
                     model="bgk", tau0=0.6, cs=0.0, inflow="loglaw",
                     speed_base=0.004, speed_rel=0.15, angle_deg=5.0, z0=0.5,
                     quadrature="smolyak_cc", quad_level=2, quad_dim=2,
@@ -233,9 +234,9 @@ def cfg4(steps: int = 2000, avg_len: int = 500) -> Workload:
                     ckpt_every=100)
 
 
-def cfg5(steps: int = 2000, avg_len: int = 500) -> Workload:
+def assimilation_case(steps: int = 2000, avg_len: int = 500) -> Workload:
     """Data-assimilation scale: Smagorinsky, 512x256x128, 10x6 buildings, 64 probes."""
-    return Workload(name="cfg5_da_les", nx=512, ny=256, nz=128, faces=URBAN_FACES,
+    return Workload(name="assimilation_les_512x256x128", nx=512, ny=256, nz=128, faces=URBAN_FACES,
                     model="smagorinsky", tau0=LES_TAU0, cs=0.1, inflow="loglaw",
                     speed_base=0.004, speed_rel=0.15, angle_deg=5.0, z0=0.5,
                     quadrature="smolyak_cc", quad_level=2, quad_dim=2,

@@ -68,7 +68,7 @@ def test_smolyak_matches_oracle(level, dim):
 
 
 def test_node_params_match_oracle():
-    for w in (inputs.cfg1(), inputs.cfg2(), inputs.cfg4()):
+    for w in (inputs.small_block(), inputs.urban_les(), inputs.adjoint_case()):
         x, _ = L.lbm_quadrature(w.quadrature, w.quad_level, w.quad_dim)
         for xi in x:
             th = L.lbm_node_params(xi, w.speed_base, w.speed_rel, w.angle_deg, w.z0)
@@ -147,8 +147,8 @@ def test_scatter_is_inverse_and_race_free(faces, block):
         assert stats[0] > 0
 
 
-@pytest.mark.parametrize("w", [inputs.cfg1(), inputs.scaled(inputs.cfg2(), 64, 32, 24),
-                               inputs.scaled(inputs.cfg4(), 64, 32, 24)])
+@pytest.mark.parametrize("w", [inputs.small_block(), inputs.scaled(inputs.urban_les(), 64, 32, 24),
+                               inputs.scaled(inputs.adjoint_case(), 64, 32, 24)])
 def test_workload_geometries_race_free(w):
     solid = inputs.solid_mask(w)
     for block in (128, 256, 512):

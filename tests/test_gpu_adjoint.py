@@ -1,0 +1,111 @@
+"""GPU discrete adjoint against the FP64 oracle adjoint (through the C ABI).
+
+The oracle adjoint is itself pinned to central finite differences and a
+dot-product test (test_oracle_adjoint.py).  Tolerance: per parameter k,
+max_j |g_jk - g^oracle_jk| / max_j |g^oracle_jk| <= 1e-4 over the nodes j.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as orc
+from paper_2508_18202_amd import inputs, sc
+from paper_2508_18202_amd.adjoint import CheckpointedAdjoint, probe_qoi
+from gpu_util import oracle_case
+
+pytestmark = pytest.mark.gpu
+GRAD_TOL = 1e-4
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _plane_probes(w, solid):
+    xp = (3 * w.nx) // 4
+    cells = [(z * w.ny + y) * w.nx + xp for z in range(w.nz // 2) for y in range(w.ny)
+             if not solid[z, y, xp]]
+    return np.asarray(cells, dtype=np.int64)
+
+
+def _compare(w, solid, thetas, steps, avg_start, ckpt, label):
+    probes = _plane_probes(w, solid)
+    cg = sc.make_geometry(w, solid, probes)
+    ens = sc.Ensemble([cg], [thetas], avg_begin=avg_start, avg_end=steps, use_graph=False)
+    try:
+        run = CheckpointedAdjoint(ens, steps, ckpt)
+        q = run.forward()
+        pw = np.full(len(probes), 1.0 / len(probes))
+        g = run.backward([torch.from_numpy(pw).cuda() for _ in thetas]).cpu().numpy()
+    finally:
+        ens.close()
+    go = []
+    for j, th in enumerate(thetas):
+        _say(f"{label}: oracle adjoint node {j}")
+        case = oracle_case(w, solid, [float(v) for v in th])
+        gj, _ = orc.adjoint(case, steps, avg_start, probes, pw, ckpt=ckpt)
+        go.append(gj)
+        res = orc.run(case, steps, avg_start=avg_start, probes=probes)
+        assert np.abs(q[j].cpu().numpy() - res["probe"]).max() < 1e-5 * np.abs(res["probe"]).max()
+    go = np.array(go)
+    for k in range(3):
+        scale = np.abs(go[:, k]).max()
+        if scale == 0.0:
+            assert np.abs(g[:, k]).max() == 0.0
+            continue
+        err = np.abs(g[:, k] - go[:, k]).max() / scale
+        assert err < GRAD_TOL, (label, k, err, g[:, k], go[:, k])
+    return g, go
+
+
+def _small(model, inflow):
+    w = inputs.scaled(inputs.adjoint_case(), 20, 10, 10, model=model, cs=0.1 if model != "bgk" else 0.0,
+                      tau0=0.56, inflow=inflow, ramp=0)
+    solid = np.zeros((w.nz, w.ny, w.nx), np.uint8)
+    solid[0:5, 3:7, 6:10] = 1
+    return w, solid
+
+
+@pytest.mark.parametrize("model,inflow", [("bgk", "loglaw"), ("bgk", "uniform"), ("smagorinsky", "loglaw")])
+def test_adjoint_small(model, inflow):
+    w, solid = _small(model, inflow)
+    if inflow == "uniform":
+        thetas = [(0.05, 0.0, 0.0), (0.045, 0.08, 0.0), (0.055, -0.05, 0.0)]
+    else:
+        thetas = [(0.012, 0.0, 0.5), (0.010, 0.07, 0.5), (0.014, -0.06, 0.4)]
+    _compare(w, solid, thetas, steps=90, avg_start=60, ckpt=20, label=f"{model}/{inflow}")
+
+
+def test_adjoint_urban_recipe_reduced():
+    """The adjoint workload recipe (BGK tau 0.6, log-law inflow, building
+    array, probe plane) on a 48x24x20 box: three of the 13 Smolyak nodes,
+    300 steps, objective over the last 100, snapshots every 100."""
+    w = inputs.scaled(inputs.adjoint_case(), 48, 24, 20)
+    solid = inputs.solid_mask(w)
+    x, a, th = sc.collocation(w)
+    sel = [0, 6, 12]
+    _compare(w, solid, [th[j] for j in sel], steps=300, avg_start=200, ckpt=100, label="adjoint-recipe-reduced")
+
+
+def test_autograd_wrapper_matches_direct_adjoint():
+    w, solid = _small("bgk", "loglaw")
+    probes = _plane_probes(w, solid)
+    thetas = [(0.012, 0.0, 0.5), (0.010, 0.07, 0.5)]
+    cg = sc.make_geometry(w, solid, probes)
+    ens = sc.Ensemble([cg], [thetas], avg_begin=40, avg_end=60, use_graph=False)
+    try:
+        run = CheckpointedAdjoint(ens, 60, 20)
+        theta = torch.tensor(thetas, dtype=torch.float64, requires_grad=True)
+        q = probe_qoi(theta, run)
+        wts = torch.linspace(0.5, 1.5, q.shape[1], dtype=torch.float64).to(q.device)
+        J = (q * wts).sum()
+        (gt,) = torch.autograd.grad(J, theta)
+        run.forward()
+        gd = run.backward([wts, wts]).cpu()
+        assert torch.allclose(gt.cpu(), gd, rtol=1e-12, atol=0)
+    finally:
+        ens.close()

@@ -1,0 +1,111 @@
+"""Gradient-based inflow assimilation through the GPU adjoint.
+
+The gradient of the assimilation loss is pinned by the same loss built on
+the FP64 oracle (oracle forward for the observations and the node QoIs,
+oracle adjoint for the node gradients, chained through the quadrature
+moments by hand).  The recovered parameters themselves are not pinned.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as orc
+from paper_2508_18202_amd import inputs
+from paper_2508_18202_amd.assimilation import Assimilation, node_thetas, sc_stats
+from gpu_util import oracle_case
+
+pytestmark = pytest.mark.gpu
+
+
+def _case():
+    w = inputs.scaled(inputs.assimilation_case(), 40, 20, 16, steps=80, avg_start=50, ramp=10)
+    solid = inputs.solid_mask(w)
+    probes = inputs.probe_cells(w, solid)
+    return w, solid, probes
+
+
+def _oracle_loss_grad(w, solid, probes, truth, params, noise, rel=0.05):
+    x, a = orc.collocation(w)
+
+    def thetas(p):
+        mu, s = p
+        return [(w.speed_base * (mu + s * xi[0]), np.deg2rad(w.angle_deg * xi[1]), w.z0) for xi in x]
+
+    def node_q(th):
+        return np.array([orc.run(oracle_case(w, solid, t), w.steps, avg_start=w.avg_start,
+                                 probes=probes)["probe"] for t in th])
+
+    qt = node_q(thetas(truth))
+    e_t = (a[:, None] * qt).sum(0)
+    s_t = np.sqrt(np.maximum((a[:, None] * (qt - e_t) ** 2).sum(0), 1e-30))
+    n = len(e_t)
+    eo = e_t * (1 + rel * noise[:n])
+    so = s_t * (1 + rel * noise[n:2 * n])
+    th = thetas(params)
+    q = node_q(th)
+    e = (a[:, None] * q).sum(0)
+    v = (a[:, None] * (q - e) ** 2).sum(0)
+    s = np.sqrt(np.maximum(v, 1e-30))
+    scale = (rel * eo) ** 2
+    L = (((e - eo) ** 2 + (s - so) ** 2) / scale).sum()
+    dL_de = 2 * (e - eo) / scale
+    dL_ds = 2 * (s - so) / scale
+    # d e / d q_j = a_j ; d s / d q_j = a_j (q_j - e) / s   (sum_j a_j = 1)
+    dL_dq = a[:, None] * dL_de[None, :] + a[:, None] * (q - e) / s * dL_ds[None, :]
+    g = np.zeros(2)
+    for j, t in enumerate(th):
+        gj, _ = orc.adjoint(oracle_case(w, solid, t), w.steps, w.avg_start, probes, dL_dq[j] * 1.0,
+                            ckpt=20)
+        # d theta_j / d (mu, s): u* = base (mu + s xi_1)
+        g[0] += gj[0] * w.speed_base
+        g[1] += gj[0] * w.speed_base * x[j][0]
+    return L, g
+
+
+def test_assimilation_gradient_matches_oracle_chain():
+    w, solid, probes = _case()
+    truth, params = (1.08, 0.22), (1.0, 0.15)
+    noise = inputs.da_noise(2 * len(probes))
+    da = Assimilation(w, w.steps, w.steps - w.avg_start, ckpt=20, solid=solid, probes=probes)
+    try:
+        da.observe(truth, noise)
+        p = torch.tensor(params, dtype=torch.float64, requires_grad=True)
+        L = da.loss(p)
+        (g,) = torch.autograd.grad(L, p)
+        g = g.numpy()
+        Lo, go = _oracle_loss_grad(w, solid, probes, truth, params, noise)
+        assert abs(float(L) - Lo) < 1e-4 * Lo
+        assert np.abs(g - go).max() < 1e-4 * np.abs(go).max(), (g, go)
+    finally:
+        da.close()
+
+
+def test_grouped_backward_equals_batched():
+    w, solid, probes = _case()
+    noise = inputs.da_noise(2 * len(probes))
+    grads = []
+    for group in (None, 4):
+        da = Assimilation(w, w.steps, w.steps - w.avg_start, ckpt=20, group_size=group,
+                          solid=solid, probes=probes)
+        try:
+            da.observe((1.08, 0.22), noise)
+            p = torch.tensor((1.0, 0.15), dtype=torch.float64, requires_grad=True)
+            (g,) = torch.autograd.grad(da.loss(p), p)
+            grads.append(g.numpy())
+        finally:
+            da.close()
+    assert np.abs(grads[0] - grads[1]).max() <= 1e-12 * np.abs(grads[0]).max()
+
+
+def test_descent_reduces_loss():
+    w, solid, probes = _case()
+    da = Assimilation(w, w.steps, w.steps - w.avg_start, ckpt=20, solid=solid, probes=probes)
+    try:
+        da.observe((1.08, 0.22), inputs.da_noise(2 * len(probes)))
+        hist = da.run((1.0, 0.15), iters=4, step0=1e-4)
+        losses = [h["loss"] for h in hist]
+        assert losses[-1] < losses[0]
+        assert all(np.isfinite(losses))
+    finally:
+        da.close()

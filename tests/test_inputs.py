@@ -23,13 +23,13 @@ def test_splitmix64_reference_vector():
 def test_geometry_hashes_are_stable():
     with open(os.path.join(GOLDEN, "geometry_hashes.json")) as fh:
         want = json.load(fh)
-    ws = [inputs.cfg1(), inputs.cfg2(), inputs.cfg4(), inputs.cfg5()] + inputs.cfg3_cases()
+    ws = [inputs.small_block(), inputs.urban_les(), inputs.adjoint_case(), inputs.assimilation_case()] + inputs.uneven_cases()
     for w in ws:
         assert inputs.mask_hash(inputs.solid_mask(w)) == want[w.name], w.name
 
 
-@pytest.mark.parametrize("w,F,nb", [(inputs.cfg2(), 16, 24), (inputs.cfg4(), 10, 12),
-                                   (inputs.cfg5(), 16, 60)])
+@pytest.mark.parametrize("w,F,nb", [(inputs.urban_les(), 16, 24), (inputs.adjoint_case(), 10, 12),
+                                   (inputs.assimilation_case(), 16, 60)])
 def test_building_array_rules(w, F, nb):
     m = inputs.solid_mask(w)
     assert m.shape == (w.nz, w.ny, w.nx)
@@ -49,8 +49,8 @@ def test_building_array_rules(w, F, nb):
     assert not m[w.nz - 8:].any()
 
 
-def test_cfg3_footprints():
-    for w in inputs.cfg3_cases()[::16]:
+def test_uneven_case_footprints():
+    for w in inputs.uneven_cases()[::16]:
         from scipy.ndimage import label
         lab, n = label(inputs.solid_mask(w)[0])
         assert n == 24
@@ -58,18 +58,18 @@ def test_cfg3_footprints():
         assert (lab == 1).sum() == F * F
 
 
-def test_cfg1_block():
-    m = inputs.solid_mask(inputs.cfg1())
+def test_small_block_geometry():
+    m = inputs.solid_mask(inputs.small_block())
     assert m.sum() == 6 * 6 * 8 and m[0:8, 5:11, 10:16].all()
 
 
 def test_probe_sets():
-    w4 = inputs.cfg4()
+    w4 = inputs.adjoint_case()
     m4 = inputs.solid_mask(w4)
     p4 = inputs.probe_cells(w4, m4)
     assert len(p4) == 32 * 16 and (m4.reshape(-1)[p4] == 0).all()
     assert (p4 % w4.nx == 96).all()
-    w5 = inputs.cfg5()
+    w5 = inputs.assimilation_case()
     m5 = inputs.solid_mask(w5)
     p5 = inputs.probe_cells(w5, m5)
     assert len(p5) == 64 and len(set(p5.tolist())) == 64

@@ -192,8 +192,8 @@ def test_freeslip_is_mirror_of_double_channel():
     assert np.abs(uf3[2] + uf3[2][::-1]).max() < 1e-14
 
 
-def test_cfg1_mirror_symmetry():
-    w = inputs.cfg1()
+def test_small_block_mirror_symmetry():
+    w = inputs.small_block()
     solid = inputs.solid_mask(w)
     assert (solid == solid[:, ::-1, :]).all()
     case = orc.Case.from_workload(w, solid, (0.05, 0.0, 0.0))

@@ -103,10 +103,10 @@ def test_moments_exact_for_polynomials():
     assert abs(e2[0] - E2) < 1e-15 and abs(v2[0] - V2) < 1e-15
 
 
-def test_cfg1_inlet_speed_std():
+def test_small_block_inlet_speed_std():
     """Uniform inflow U = 0.05 (1 + 0.1 xi): E[U] = 0.05, Std[U] = 0.005 / sqrt(3)."""
     from paper_2508_18202_amd import inputs
-    w = inputs.cfg1()
+    w = inputs.small_block()
     x, a = orc.collocation(w)
     U = np.array([orc.node_params(w, xi)[0] for xi in x])
     e, v = orc.moments(U[:, None], a)
