@@ -39,8 +39,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1, help="untimed SC passes")
     ap.add_argument("--lbm-steps", type=int, default=20000, help="time steps per pass")
     ap.add_argument("--avg-len", type=int, default=5000, help="QoI averaging window")
-    ap.add_argument("--block", type=int, default=0, help="cells per workgroup (0: autotuned)")
+    ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0: autotuned shape)")
+    ap.add_argument("--cells-per-thread", type=int, default=1)
+    ap.add_argument("--nontemporal", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost leg")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the batched vs one-at-a-time leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-calib", action="store_true",
                     help="also run a plain copy of known size (HBM counter calibration)")
@@ -87,6 +91,90 @@ def cpu_baseline(w, solid, theta, seconds: float):
                       f"{n} time steps past the inflow ramp, {dt:.1f} s"}
 
 
+def adjoint_leg(variant, steps: int = 2000, avg_len: int = 500, ckpt: int = 100):
+    """Forward sweep (with snapshots) vs checkpointed adjoint sweep of the
+    adjoint workload: 13 Smolyak nodes of 128x64x48, BGK, probe-plane QoI."""
+    import torch
+    from paper_2508_18202_amd import inputs, sc
+    from paper_2508_18202_amd.adjoint import CheckpointedAdjoint
+    w = inputs.adjoint_case(steps=steps, avg_len=avg_len)
+    solid = inputs.solid_mask(w)
+    probes = inputs.probe_cells(w, solid)
+    x, a, th = sc.collocation(w)
+    cg = sc.make_geometry(w, solid, probes)
+    ens = sc.Ensemble([cg], [th], avg_begin=w.avg_start, avg_end=w.steps, fields=False,
+                      use_graph=True, variant=variant)
+    try:
+        run = CheckpointedAdjoint(ens, steps, ckpt)
+        pw = [torch.full((len(probes),), 1.0 / len(probes), dtype=torch.float64, device="cuda")] * len(ens)
+        run.forward()
+        run.backward(pw)                       # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run.forward()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = run.backward(pw)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fluid = int((solid == 0).sum())
+        return {"workload": "13 Smolyak nodes x 128x64x48 BGK tau 0.6, log-law inflow, probe plane, "
+                            f"{steps} steps, objective over the last {avg_len}, snapshots every {ckpt}",
+                "forward_s": round(t1 - t0, 4), "adjoint_s": round(t2 - t1, 4),
+                "ratio": round((t2 - t1) / (t1 - t0), 3),
+                "forward_mlups": round(len(ens) * fluid * steps / (t1 - t0) / 1e6, 1),
+                "grad_finite": bool(torch.isfinite(g).all())}
+    finally:
+        ens.close()
+
+
+def uneven_leg(variant, steps: int = 60):
+    """The 48 uneven cases x 13 nodes (624 instances) advanced in one plan vs
+    the same instances advanced one plan at a time (one launch per instance
+    per step)."""
+    import torch
+    from paper_2508_18202_amd import inputs, sc
+    cases = inputs.uneven_cases(steps=steps)
+    cgs, ths, fluid = [], [], 0
+    for w in cases:
+        s = inputs.solid_mask(w)
+        cgs.append(sc.make_geometry(w, s))
+        ths.append(sc.collocation(w)[2])
+        fluid += 13 * int((s == 0).sum())
+    ens = sc.Ensemble(cgs, ths, use_graph=False, variant=variant)
+    try:
+        ens.advance(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ens.advance(steps)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        # one plan per instance over the batch's own population arrays
+        from paper_2508_18202_amd import lbmsc as L
+        plans = []
+        for k, inst in enumerate(ens.instances):
+            plans.append(L.lbm_plan_create([inst], use_graph=False, block=variant[0],
+                                           cells_per_thread=variant[1], nontemporal=variant[2]))
+            L.lbm_plan_set_step(plans[-1], ens.step)
+        stream = sc.stream_handle()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for n in range(steps):
+            for p in plans:
+                L.lbm_collide_stream(p, 1, stream)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        for p in plans:
+            L.lbm_plan_destroy(p)
+        return {"workload": "48 cases (16 each of 128x64x32, 192x96x48, 256x128x64) x 13 nodes = "
+                            f"{len(ens)} instances, {steps} steps",
+                "batched_mlups": round(fluid * steps / tb / 1e6, 1),
+                "one_at_a_time_mlups": round(fluid * steps / ts / 1e6, 1),
+                "speedup": round(ts / tb, 3)}
+    finally:
+        ens.close()
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -110,14 +198,15 @@ def main():
     ramp = min(w.ramp, w.avg_start)
     plain = max(0, w.avg_start - ramp)
     plain -= plain % 16
-    block = args.block
-
-    # block size from the project's autotuner (cached per arch/model/box sizes)
-    if block == 0:
+    # launch shape (block, cells per thread, non-temporal) from the project's
+    # autotuner, cached per architecture / model / box sizes
+    if args.block:
+        variant = (args.block, args.cells_per_thread, args.nontemporal)
+    else:
         x, a, th = sc.collocation(w)
         cg = sc.make_geometry(w, solid)
         ens = sc.Ensemble([cg], [th], use_graph=False)
-        block = L.lbm_plan_autotune(ens.plan, sc.stream_handle())
+        variant = L.lbm_plan_autotune(ens.plan, sc.stream_handle())
         ens.close()
         del ens, cg
 
@@ -125,7 +214,7 @@ def main():
         x, a, th = sc.collocation(w)                       # collocation rule + node parameters
         cg = sc.make_geometry(w, solid)
         ens = sc.Ensemble([cg], [th], avg_begin=w.avg_start, avg_end=w.steps,
-                          use_graph=True, block=block)     # geometry + rest state of all nodes
+                          use_graph=True, variant=variant)  # geometry + rest state of all nodes
         try:
             ens.advance(ramp)
             e0 = torch.cuda.Event(enable_timing=True)
@@ -185,7 +274,7 @@ def main():
             "lbm_steps": lbm_steps,
             "instances": n_inst,
             "fluid_cells_per_instance": n_fluid,
-            "block": block,
+            "launch": {"block": variant[0], "cells_per_thread": variant[1], "nontemporal": variant[2]},
             "parallelism": "batched instances, 1 GPU",
         },
         "roofline": {
@@ -201,6 +290,10 @@ def main():
         },
         "kernel_mlups": round(n_inst * n_fluid / avg_launch_s / 1e6, 1),
     }
+    if not args.no_adjoint:
+        out["adjoint_vs_forward"] = adjoint_leg(variant)
+    if not args.no_uneven:
+        out["batched_vs_one_at_a_time"] = uneven_leg(variant)
     if not args.no_cpu:
         x, a, th = sc.collocation(w)
         out["cpu_baseline"] = cpu_baseline(w, solid, th[0], args.cpu_seconds)

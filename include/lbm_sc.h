@@ -106,10 +106,13 @@ typedef struct lbm_instance {
 } lbm_instance;
 
 typedef struct lbm_plan_opts {
-    int64_t avg_begin;       /* QoI window: states f^n with avg_begin < n <= avg_end */
-    int64_t avg_end;         /* avg_end <= avg_begin disables accumulation */
-    int32_t use_graph;       /* replay step pairs from captured HIP graphs where possible */
-    int32_t block;           /* cells per workgroup: 128, 256 or 512; 0 = default (256) */
+    int64_t avg_begin;         /* QoI window: states f^n with avg_begin < n <= avg_end */
+    int64_t avg_end;           /* avg_end <= avg_begin disables accumulation */
+    int32_t use_graph;         /* replay step pairs from captured HIP graphs where possible */
+    int32_t block;             /* threads per workgroup: 128, 256 or 512; 0 = default (256) */
+    int32_t cells_per_thread;  /* 1 or 2; 0 = default (1).  A workgroup owns block *
+                                  cells_per_thread consecutive cells of one instance */
+    int32_t nontemporal;       /* 1: streaming (non-temporal) population loads and stores */
 } lbm_plan_opts;
 
 typedef struct lbm_plan lbm_plan;
@@ -166,10 +169,14 @@ int lbm_sync(lbm_plan *plan, hipStream_t stream);
 /* Synchronises stream; returns LBM_E_UNSTABLE and the first bad instance
  * index through *bad_inst if any instance saw rho <= 0 or a non-finite rho. */
 int lbm_check_health(lbm_plan *plan, hipStream_t stream, int32_t *bad_inst);
-/* Pick the block size by timing step pairs on a copy of the batch state
- * (state, step counter and QoI sums are restored).  Results are cached in
- * the JSON file named by LBMSC_TUNE_CACHE (default ~/.cache/lbmsc_tune.json). */
-int lbm_plan_autotune(lbm_plan *plan, hipStream_t stream, int32_t *block_out);
+/* Launch shape of the step kernels: variant_out = {block, cells_per_thread,
+ * nontemporal}.  lbm_plan_autotune times step pairs of every shape on the
+ * batch (populations, step counter and QoI sums are restored afterwards),
+ * keeps the fastest and caches it in the JSON file named by LBMSC_TUNE_CACHE
+ * (default ~/.cache/lbmsc_tune.json), keyed by architecture, model, instance
+ * count and box sizes. */
+int lbm_plan_variant(const lbm_plan *plan, int32_t variant_out[3]);
+int lbm_plan_autotune(lbm_plan *plan, hipStream_t stream, int32_t variant_out[3]);
 
 /* --------------------------------------------- collide and stream (a4/a6)
  * Advance every instance of the plan by n_steps time steps of Eq.

@@ -14,6 +14,7 @@
 #include <cstdint>
 #include <cstring>
 #include <unordered_map>
+#include <utility>
 #include <vector>
 
 #include "rules.h"
@@ -181,3 +182,76 @@ void lbmhc_lattice(int *c, float *w, int *o, int *zf)
 }
 
 }  // extern "C"
+
+namespace {
+
+Shape shape_of(const Geo3 &g)
+{
+    Shape s;
+    s.nx = g.b.nx;
+    s.ny = g.b.ny;
+    s.nz = g.b.nz;
+    s.offy = g.b.nx;
+    s.offz = g.b.nx * g.b.ny;
+    for (int k = 0; k < 6; ++k) s.face[k] = g.b.face[k];
+    return s;
+}
+
+// 0 when gather_rel<I> and scatter_rel<I> agree with pull_src / push_dsts at cell (x,y,z)
+template <int I>
+int check_rel_one(const Geo3 &g, const Shape &s, int x, int y, int z)
+{
+    const int64_t c = g.cell(x, y, z);
+    const Preds p = preds_of(s, x, y, z);
+    const uint32_t m = g.m[c];
+    const RelLink r = gather_rel<I>(s, p, m);
+    const Link src = pull_src(g.b, x, y, z, I, m);
+    if (I == 0) {
+        if (r.slot != 0 || r.delta != 0 || r.inlet) return 20;
+    } else {
+        const int64_t want = g.cell(src.x, src.y, src.z);
+        if (c + r.delta != want || r.slot != opp(src.pop)) return 21;
+        if (r.inlet != (src.kind == R_INLET)) return 22;
+        Link d[2];
+        const int nd = push_dsts(g.b, x, y, z, I, m, d[0], d[1]);
+        RelLink a, e;
+        scatter_rel<I>(s, p, m, a, e);
+        const int nr = (int)a.valid + (int)e.valid;
+        if (nr != nd) return 23;
+        RelLink got[2];
+        int k = 0;
+        if (a.valid) got[k++] = a;
+        if (e.valid) got[k++] = e;
+        for (int j = 0; j < nd; ++j) {
+            const int64_t dc = g.cell(d[j].x, d[j].y, d[j].z);
+            if (c + got[j].delta != dc || got[j].slot != d[j].pop) return 24;
+            if (got[j].inlet != (d[j].kind == R_INLET)) return 25;
+        }
+    }
+    return 0;
+}
+
+template <int... Is>
+int check_rel_all(const Geo3 &g, const Shape &s, int x, int y, int z, std::integer_sequence<int, Is...>)
+{
+    int r = 0;
+    ((r = r ? r : check_rel_one<Is>(g, s, x, y, z)), ...);
+    return r;
+}
+
+}  // namespace
+
+extern "C" int lbmhc_check_relative(int nx, int ny, int nz, const int *face, const uint8_t *solid)
+{
+    Geo3 g;
+    build(g, nx, ny, nz, face, solid);
+    const Shape s = shape_of(g);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                if (g.fl[g.cell(x, y, z)] & FL_SOLID) continue;
+                const int r = check_rel_all(g, s, x, y, z, std::make_integer_sequence<int, Q>{});
+                if (r) return r;
+            }
+    return 0;
+}

@@ -41,7 +41,18 @@ struct StepArgs {
     int64_t rec_slot;          // slot index n % n_slots
 };
 
-int launch_step(int block, int model, int parity, const Geo *geo, const int32_t *tile_inst,
+// Launch shape of the step kernels: threads per workgroup, cells per
+// thread (a tile holds bs * cpt consecutive cells) and non-temporal
+// population loads/stores.
+struct Variant {
+    int bs;
+    int cpt;
+    int nt;
+    int tile() const { return bs * cpt; }
+};
+
+bool variant_ok(const Variant &v);
+int launch_step(const Variant &v, int model, int parity, const Geo *geo, const int32_t *tile_inst,
                 int32_t n_tiles, const StepArgs &a, int32_t *health, hipStream_t s);
 int launch_init_geometry(const Box &b, const uint8_t *solid, uint8_t *flags, uint32_t *smask,
                          const int32_t *probes, int32_t n_probes, hipStream_t s);
@@ -69,7 +80,7 @@ struct AdjArgs {
     double *grad;              // [n_inst][3]
 };
 
-int launch_adjoint(int block, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
+int launch_adjoint(int tile_cells, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
                    const AdjArgs &a, hipStream_t s);
 int launch_adjoint_init(int tcells, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
                         const AdjArgs &a, hipStream_t s);

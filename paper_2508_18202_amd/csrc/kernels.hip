@@ -21,6 +21,8 @@
 // tau_eff = (tau0 + sqrt(tau0^2 + 18 sqrt(2) Cs^2 Q / rho)) / 2,
 // Q = |Pi_neq| (Eqs. tauEff, turbVisc with |S| from the local
 // non-equilibrium stress).
+#include <utility>
+
 #include "kernels.h"
 
 namespace lbmsc {
@@ -28,6 +30,39 @@ namespace lbmsc {
 namespace {
 
 constexpr float KAPPA_INV = 1.0f / 0.41f;
+
+// Pointers taken from the instance table are generic; casting them to the
+// global address space lets the compiler emit global (not flat) memory
+// instructions with a scalar base and 32-bit lane offsets.
+#define GLOBAL_AS __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GLOBAL_AS T *gp(T *p)
+{
+    return (GLOBAL_AS T *)p;
+}
+template <class T>
+__device__ __forceinline__ const GLOBAL_AS T *gp(const T *p)
+{
+    return (const GLOBAL_AS T *)p;
+}
+
+// Element idx of a uniform base through a 32-bit byte offset, so that the
+// access uses a scalar base address plus one 32-bit lane offset.  NT marks
+// streaming (non-temporal) accesses.
+template <bool NT = false, class T>
+__device__ __forceinline__ T ldg(const GLOBAL_AS T *base, uint32_t idx)
+{
+    const GLOBAL_AS T *p = (const GLOBAL_AS T *)((const GLOBAL_AS char *)base + idx * (uint32_t)sizeof(T));
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT = false, class T>
+__device__ __forceinline__ void stg(GLOBAL_AS T *base, uint32_t idx, T v)
+{
+    GLOBAL_AS T *p = (GLOBAL_AS T *)((GLOBAL_AS char *)base + idx * (uint32_t)sizeof(T));
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
 // contiguous range of tiles so neighbouring tiles share one L2.
@@ -61,7 +96,7 @@ __device__ __forceinline__ int probe_index(const Geo &G, int32_t c)
     int lo = 0, hi = G.n_probes - 1;
     while (lo <= hi) {
         int mid = (lo + hi) >> 1;
-        int v = G.probes[mid];
+        int v = gp(G.probes)[mid];
         if (v == c) return mid;
         if (v < c) lo = mid + 1; else hi = mid - 1;
     }
@@ -88,6 +123,59 @@ __device__ __forceinline__ int32_t off_of(const Geo &G, int i)
     return cx(i) + cy(i) * G.offy + cz(i) * G.offz;
 }
 
+__device__ __forceinline__ Shape shape_of(const Geo &G)
+{
+    Shape S;
+    S.nx = G.box.nx;
+    S.ny = G.box.ny;
+    S.nz = G.box.nz;
+    S.offy = G.offy;
+    S.offz = G.offz;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) S.face[k] = G.box.face[k];
+    return S;
+}
+
+// Boundary-aware gather of all 19 populations f^n(x) from the swapped
+// post-collision values of step n-1, one compile-time direction at a time.
+template <bool NT = false, int... Is>
+__device__ __forceinline__ void gather_all(const Geo &G, const Shape &S, const Preds &p, uint32_t sm, uint32_t c,
+                                           float U, float r, float g[Q], std::integer_sequence<int, Is...>)
+{
+    const GLOBAL_AS float *__restrict__ f = gp(G.f);
+    const uint32_t qs = (uint32_t)G.qs;
+    (
+        [&] {
+            const RelLink l = gather_rel<Is>(S, p, sm);
+            const float v = ldg<NT>(f, (uint32_t)l.slot * qs + (uint32_t)((int32_t)c + l.delta));
+            g[Is] = l.inlet ? v + inlet_term(Is, U, G, r) : v;
+        }(),
+        ...);
+}
+
+// Boundary-aware scatter of the post-collision values to every destination
+// link of the next (naturally stored) state.
+template <bool NT = false, int... Ks>
+__device__ __forceinline__ void scatter_all(const Geo &G, const Shape &S, const Preds &p, uint32_t sm, uint32_t c,
+                                            float U, float r, const float g[Q], std::integer_sequence<int, Ks...>)
+{
+    GLOBAL_AS float *__restrict__ f = gp(G.f);
+    const uint32_t qs = (uint32_t)G.qs;
+    (
+        [&] {
+            RelLink a, e;
+            scatter_rel<Ks>(S, p, sm, a, e);
+            if (a.valid) {
+                const float v = a.inlet ? g[Ks] + inlet_term(opp(Ks), U, G, r) : g[Ks];
+                stg<NT>(f, (uint32_t)a.slot * qs + (uint32_t)((int32_t)c + a.delta), v);
+            }
+            if (e.valid) stg<NT>(f, (uint32_t)e.slot * qs + (uint32_t)((int32_t)c + e.delta), g[Ks]);
+        }(),
+        ...);
+}
+
+using Dirs = std::make_integer_sequence<int, Q>;
+
 // Populations f^n(x) of a fluid cell in the current storage state.
 // parity 0: natural slots; parity 1: gathered from the swapped
 // post-collision values of step n-1 (inlet momentum uses r(n-1)).
@@ -95,25 +183,20 @@ template <int PARITY>
 __device__ __forceinline__ void load_state(const Geo &G, uint32_t c, uint8_t fl, int x, int y, int z,
                                            int64_t n, float g[Q])
 {
-    const float *__restrict__ f = G.f;
+    const GLOBAL_AS float *__restrict__ f = gp(G.f);
     const uint32_t qs = (uint32_t)G.qs;
     if (PARITY == 0) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) g[i] = f[i * qs + c];
+        for (int i = 0; i < Q; ++i) g[i] = ldg(f + (size_t)i * qs, c);
     } else if (!(fl & FL_NEAR)) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) g[i] = f[opp(i) * qs + (uint32_t)((int32_t)c - off_of(G, i))];
+        for (int i = 0; i < Q; ++i) g[i] = ldg(f + (size_t)opp(i) * qs - off_of(G, i), c);
     } else {
-        const uint32_t sm = G.smask[c];
+        const Shape S = shape_of(G);
+        const Preds p = preds_of(S, x, y, z);
+        const uint32_t sm = gp(G.smask)[c];
         const float U = (fl & FL_INLET) ? inflow_speed(G, z) : 0.0f;
-        const float r = ramp_factor(G, n - 1);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const Link s = pull_src(G.box, x, y, z, i, sm);
-            float v = f[opp(s.pop) * qs + cell_of(G, s)];
-            if (s.kind == R_INLET) v += inlet_term(i, U, G, r);
-            g[i] = v;
-        }
+        gather_all(G, S, p, sm, c, U, ramp_factor(G, n - 1), g, Dirs{});
     }
 }
 
@@ -199,21 +282,22 @@ __device__ __forceinline__ void collide(const Geo &G, float g[Q], const Macro &m
 __device__ __forceinline__ void accumulate_qoi(const Geo &G, uint32_t c, uint8_t fl, const Macro &m)
 {
     if (G.qpart) {
-        float4 *p = reinterpret_cast<float4 *>(G.qpart) + c;
-        float4 v = *p;
-        v.x += m.ux;
-        v.y += m.uy;
-        v.z += m.uz;
-        v.w += sqrtf(m.ux * m.ux + m.uy * m.uy + m.uz * m.uz);
-        *p = v;
+        GLOBAL_AS float *p = gp(G.qpart) + 4 * (size_t)c;
+        p[0] += m.ux;
+        p[1] += m.uy;
+        p[2] += m.uz;
+        p[3] += sqrtf(m.ux * m.ux + m.uy * m.uy + m.uz * m.uz);
     }
     if ((fl & FL_PROBE) && G.psum) {
         const int p = probe_index(G, (int32_t)c);
-        if (p >= 0) G.psum[p] += (double)m.ux;
+        if (p >= 0) gp(G.psum)[p] += (double)m.ux;
     }
 }
 
-template <int BS, int MODEL, int PARITY>
+// One time step of every instance.  A workgroup of BS threads owns a tile of
+// BS * CPT consecutive cells of one instance; thread t handles cells
+// t, t + BS, ... so every load and store instruction stays coalesced.
+template <int BS, int CPT, bool NT, int MODEL, int PARITY>
 __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
                                              int32_t n_tiles, StepArgs a, int32_t *__restrict__ health)
 {
@@ -221,62 +305,91 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
     if (tile >= n_tiles) return;
     const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
     const Geo &G = geo[ii];
-    const int32_t lc = (tile - G.tile0) * BS + (int32_t)threadIdx.x;
-    const bool active = lc < G.ncells;
-    const uint32_t c = active ? (uint32_t)lc : 0u;
-    const uint8_t fl = active ? G.flags[c] : (uint8_t)FL_SOLID;
-    const bool fluid = !(fl & FL_SOLID);
-    float *__restrict__ f = G.f;
+    GLOBAL_AS float *__restrict__ f = gp(G.f);
     const uint32_t qs = (uint32_t)G.qs;
+    const int32_t base = (tile - G.tile0) * (BS * CPT) + (int32_t)threadIdx.x;
 
-    int x = 0, y = 0, z = 0;
-    float g[Q];
-    if (fluid) {
-        if (PARITY == 1 && (fl & FL_NEAR)) coords(G, c, x, y, z);
-        load_state<PARITY>(G, c, fl, x, y, z, a.step, g);
-        const Macro m = macro_of(g);
-        if (!(m.rho > 0.0f) || !isfinite(m.rho)) atomicOr(health + ii, 1);
-        if (a.accumulate) accumulate_qoi(G, c, fl, m);
-        if (a.record == 1) {
-            float4 *r = reinterpret_cast<float4 *>(a.rec[ii]) + (size_t)a.rec_slot * (size_t)G.ncells + c;
-            *r = make_float4(m.rho, m.ux, m.uy, m.uz);
-        } else if (a.record == 2) {
-            float *r = a.rec[ii] + (size_t)a.rec_slot * (size_t)Q * G.qs;
+    uint32_t c[CPT];
+    uint8_t fl[CPT];
+    bool fluid[CPT], near_wave[CPT];
+    Preds pr[CPT];
+    uint32_t sm[CPT];
+    float U[CPT];
+    float g[CPT][Q];
+    Shape S;
+    if (PARITY == 1) S = shape_of(G);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) r[i * qs + c] = g[i];
+    for (int j = 0; j < CPT; ++j) {
+        const int32_t lc = base + j * BS;
+        const bool active = lc < G.ncells;
+        c[j] = active ? (uint32_t)lc : 0u;
+        fl[j] = active ? gp(G.flags)[c[j]] : (uint8_t)FL_SOLID;
+        fluid[j] = !(fl[j] & FL_SOLID);
+        // odd steps: wavefronts without boundary cells take the plain stencil,
+        // the others evaluate the boundary rules for all of their lanes at once
+        near_wave[j] = PARITY == 1 && __any(fluid[j] && (fl[j] & FL_NEAR));
+        pr[j] = Preds{false, false, false, false, false, false};
+        sm[j] = 0;
+        U[j] = 0.0f;
+        if (near_wave[j] && fluid[j]) {
+            int x, y, z;
+            coords(G, c[j], x, y, z);
+            pr[j] = preds_of(S, x, y, z);
+            sm[j] = gp(G.smask)[c[j]];
+            U[j] = (fl[j] & FL_INLET) ? inflow_speed(G, z) : 0.0f;
         }
-        collide<MODEL>(G, g, m);
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        if (!fluid[j]) continue;
+        if (PARITY == 0) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) g[j][i] = ldg<NT>(f + (size_t)i * qs, c[j]);
+        } else if (!near_wave[j]) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) g[j][i] = ldg<NT>(f + (size_t)opp(i) * qs - off_of(G, i), c[j]);
+        } else {
+            gather_all<NT>(G, S, pr[j], sm[j], c[j], U[j], ramp_factor(G, a.step - 1), g[j], Dirs{});
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        if (!fluid[j]) continue;
+        const Macro m = macro_of(g[j]);
+        if (!(m.rho > 0.0f) || !isfinite(m.rho)) atomicOr(health + ii, 1);
+        if (a.accumulate) accumulate_qoi(G, c[j], fl[j], m);
+        if (a.record == 1) {
+            GLOBAL_AS float *r = gp(a.rec[ii]) + 4 * ((size_t)a.rec_slot * (size_t)G.ncells + c[j]);
+            r[0] = m.rho;
+            r[1] = m.ux;
+            r[2] = m.uy;
+            r[3] = m.uz;
+        } else if (a.record == 2) {
+            GLOBAL_AS float *r = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)Q * G.qs;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) stg(r + (size_t)i * qs, c[j], g[j][i]);
+        }
+        collide<MODEL>(G, g[j], m);
     }
     if (PARITY == 1) __syncthreads();
-    if (!fluid) return;
-    if (PARITY == 0) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) f[opp(i) * qs + c] = g[i];
-    } else if (!(fl & FL_NEAR)) {
+    for (int j = 0; j < CPT; ++j) {
+        if (!fluid[j]) continue;
+        if (PARITY == 0) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) f[i * qs + (uint32_t)((int32_t)c + off_of(G, i))] = g[i];
-    } else {
-        const uint32_t sm = G.smask[c];
-        const float U = (fl & FL_INLET) ? inflow_speed(G, z) : 0.0f;
-        const float r = ramp_factor(G, a.step);
-        f[c] = g[0];
+            for (int i = 0; i < Q; ++i) stg<NT>(f + (size_t)opp(i) * qs, c[j], g[j][i]);
+        } else if (!near_wave[j]) {
 #pragma unroll
-        for (int k = 1; k < Q; ++k) {
-            Link d0, d1;
-            const int nd = push_dsts(G.box, x, y, z, k, sm, d0, d1);
-            if (nd > 0) {
-                float v = g[k];
-                if (d0.kind == R_INLET) v += inlet_term(opp(k), U, G, r);
-                f[d0.pop * qs + cell_of(G, d0)] = v;
-            }
-            if (nd > 1) f[d1.pop * qs + cell_of(G, d1)] = g[k];
+            for (int i = 0; i < Q; ++i) stg<NT>(f + (size_t)i * qs + off_of(G, i), c[j], g[j][i]);
+        } else {
+            scatter_all<NT>(G, S, pr[j], sm[j], c[j], U[j], ramp_factor(G, a.step), g[j], Dirs{});
         }
     }
 }
 
 // QoIs of the current state f^n without advancing it.
 template <int PARITY>
-__global__ __launch_bounds__(512) void k_capture(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
+__global__ __launch_bounds__(1024) void k_capture(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
                                                  int32_t n_tiles, int64_t step, int32_t *__restrict__ health)
 {
     const int tile = xcd_tile();
@@ -286,7 +399,7 @@ __global__ __launch_bounds__(512) void k_capture(const Geo *__restrict__ geo, co
     const int32_t lc = (tile - G.tile0) * (int32_t)blockDim.x + (int32_t)threadIdx.x;
     if (lc >= G.ncells) return;
     const uint32_t c = (uint32_t)lc;
-    const uint8_t fl = G.flags[c];
+    const uint8_t fl = gp(G.flags)[c];
     if (fl & FL_SOLID) return;
     int x = 0, y = 0, z = 0;
     coords(G, c, x, y, z);
@@ -297,7 +410,7 @@ __global__ __launch_bounds__(512) void k_capture(const Geo *__restrict__ geo, co
     accumulate_qoi(G, c, fl, m);
 }
 
-__global__ __launch_bounds__(512) void k_flush(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
+__global__ __launch_bounds__(1024) void k_flush(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
                                                int32_t n_tiles)
 {
     const int tile = xcd_tile();
@@ -326,7 +439,7 @@ __global__ __launch_bounds__(256) void k_fields(const Geo *__restrict__ geo, int
     const int32_t lc = blockIdx.x * 256 + (int32_t)threadIdx.x;
     if (lc >= G.ncells) return;
     const uint32_t c = (uint32_t)lc;
-    const uint8_t fl = G.flags[c];
+    const uint8_t fl = gp(G.flags)[c];
     const uint32_t qs = (uint32_t)G.qs;
     if (fl & FL_SOLID) {
         if (mode == 0) reinterpret_cast<float4 *>(out)[c] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -471,56 +584,80 @@ __device__ __forceinline__ void inflow_dtheta(const Geo &G, int z, int i, float 
     }
 }
 
+// mu_k = sum of lam^{n+1} over the destination links of direction k, and the
+// inflow-parameter gradient of the moving-wall links among them.
+template <int... Ks>
+__device__ __forceinline__ void adjoint_gather(const Geo &G, const Shape &S, const Preds &p, uint32_t sm, uint32_t c,
+                                               int z, float r, const GLOBAL_AS float *__restrict__ lin, float mu[Q],
+                                               double &gr0,
+                                               double &gr1, double &gr2, std::integer_sequence<int, Ks...>)
+{
+    const uint32_t qs = (uint32_t)G.qs;
+    (
+        [&] {
+            RelLink a, e;
+            scatter_rel<Ks>(S, p, sm, a, e);
+            float s = 0.0f;
+            if (e.valid) s += ldg(lin, (uint32_t)e.slot * qs + (uint32_t)((int32_t)c + e.delta));
+            if (a.valid) {
+                const float l = ldg(lin, (uint32_t)a.slot * qs + (uint32_t)((int32_t)c + a.delta));
+                s += l;
+                if (a.inlet) {
+                    float dt[3];
+                    constexpr int q = opp(Ks);
+                    inflow_dtheta(G, z, q, dt);
+                    const double f6 = 6.0 * (double)wgt(q) * (double)r * (double)l;
+                    gr0 += f6 * dt[0];
+                    gr1 += f6 * dt[1];
+                    gr2 += f6 * dt[2];
+                }
+            }
+            mu[Ks] = s;
+        }(),
+        ...);
+}
+
+template <int MODEL>
+__device__ __forceinline__ void adjoint_cell(const Geo &G, int ii, int32_t first, const AdjArgs &a);
+
+// One adjoint step of the cells of one tile (tile_cells a multiple of BS).
 template <int BS, int MODEL>
 __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
-                                                int32_t n_tiles, AdjArgs a)
+                                                int32_t n_tiles, int32_t tile_cells, AdjArgs a)
 {
     const int tile = xcd_tile();
     if (tile >= n_tiles) return;
     const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
     const Geo &G = geo[ii];
-    const int32_t lc = (tile - G.tile0) * BS + (int32_t)threadIdx.x;
+    for (int32_t sub = 0; sub < tile_cells; sub += BS) adjoint_cell<MODEL>(G, ii, (tile - G.tile0) * tile_cells + sub, a);
+}
+
+template <int MODEL>
+__device__ __forceinline__ void adjoint_cell(const Geo &G, int ii, int32_t first, const AdjArgs &a)
+{
+    const int32_t lc = first + (int32_t)threadIdx.x;
     const bool active = lc < G.ncells;
     const uint32_t c = active ? (uint32_t)lc : 0u;
-    const uint8_t fl = active ? G.flags[c] : (uint8_t)FL_SOLID;
+    const uint8_t fl = active ? gp(G.flags)[c] : (uint8_t)FL_SOLID;
     const bool fluid = !(fl & FL_SOLID);
     const uint32_t qs = (uint32_t)G.qs;
     double gr0 = 0.0, gr1 = 0.0, gr2 = 0.0;
     if (fluid) {
-        const float *__restrict__ lin = a.lam_in[ii];
-        float *__restrict__ lout = a.lam_out[ii];
+        const GLOBAL_AS float *__restrict__ lin = gp(a.lam_in[ii]);
+        GLOBAL_AS float *__restrict__ lout = gp(a.lam_out[ii]);
         // mu = P^T lam^{n+1}: sum over the destination links of each post-collision value
         float mu[Q];
         if (!(fl & FL_NEAR)) {
 #pragma unroll
-            for (int k = 0; k < Q; ++k) mu[k] = lin[k * qs + (uint32_t)((int32_t)c + off_of(G, k))];
+            for (int k = 0; k < Q; ++k) mu[k] = ldg(lin + (size_t)k * qs + off_of(G, k), c);
         } else {
             int x, y, z;
             coords(G, c, x, y, z);
-            const uint32_t sm = G.smask[c];
+            const Shape S = shape_of(G);
+            const Preds pr = preds_of(S, x, y, z);
+            const uint32_t sm = gp(G.smask)[c];
             const float r = ramp_factor(G, a.step);
-            mu[0] = lin[c];
-#pragma unroll
-            for (int k = 1; k < Q; ++k) {
-                Link d0, d1;
-                const int nd = push_dsts(G.box, x, y, z, k, sm, d0, d1);
-                float s = 0.0f;
-                if (nd > 1) s += lin[d1.pop * qs + cell_of(G, d1)];
-                if (nd > 0) {
-                    const float l = lin[d0.pop * qs + cell_of(G, d0)];
-                    s += l;
-                    if (d0.kind == R_INLET) {
-                        float dt[3];
-                        const int q = opp(k);
-                        inflow_dtheta(G, z, q, dt);
-                        const double f6 = 6.0 * (double)wgt(q) * (double)r * (double)l;
-                        gr0 += f6 * dt[0];
-                        gr1 += f6 * dt[1];
-                        gr2 += f6 * dt[2];
-                    }
-                }
-                mu[k] = s;
-            }
+            adjoint_gather(G, S, pr, sm, c, z, r, lin, mu, gr0, gr1, gr2, Dirs{});
         }
         // state of step n
         float rho, ux, uy, uz, om;
@@ -601,7 +738,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
                 lk += sa * quad + sb;
             }
             lk += src * ex;
-            lout[k * qs + c] = lk;
+            stg(lout + (size_t)k * qs, c, lk);
         }
     }
     // gradient: wave reduction, one FP64 atomic per wave that touched an inlet
@@ -619,7 +756,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
 }
 
 // lam^N = dj_N / df^N from the (even, naturally stored) current state.
-__global__ __launch_bounds__(512) void k_adjoint_init(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
+__global__ __launch_bounds__(1024) void k_adjoint_init(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
                                                       int32_t n_tiles, AdjArgs a)
 {
     const int tile = xcd_tile();
@@ -630,7 +767,7 @@ __global__ __launch_bounds__(512) void k_adjoint_init(const Geo *__restrict__ ge
     if (lc >= G.ncells) return;
     const uint32_t c = (uint32_t)lc;
     const uint32_t qs = (uint32_t)G.qs;
-    const uint8_t fl = G.flags[c];
+    const uint8_t fl = gp(G.flags)[c];
     float *lout = a.lam_out[ii];
     float src = 0.0f, ux = 0.0f;
     if (!(fl & FL_SOLID) && a.in_window && (fl & FL_PROBE) && a.pw[ii]) {
@@ -638,7 +775,7 @@ __global__ __launch_bounds__(512) void k_adjoint_init(const Geo *__restrict__ ge
         if (p >= 0) {
             float g[Q];
 #pragma unroll
-            for (int i = 0; i < Q; ++i) g[i] = G.f[i * qs + c];
+            for (int i = 0; i < Q; ++i) g[i] = gp(G.f)[i * qs + c];
             const Macro m = macro_of(g);
             src = (float)(a.pw[ii][p] * a.inv_count) / m.rho;
             ux = m.ux;
@@ -653,30 +790,50 @@ __global__ __launch_bounds__(512) void k_adjoint_init(const Geo *__restrict__ ge
 
 static inline int grid_of(int32_t n_tiles) { return ((n_tiles + 7) / 8) * 8; }
 
-template <int BS, int MODEL>
-static void step_bs(int parity, const Geo *geo, const int32_t *ti, int32_t nt, const StepArgs &a, int32_t *h,
-                    hipStream_t s)
+template <int BS, int CPT, bool NT, int MODEL>
+static void step_v(int parity, const Geo *geo, const int32_t *ti, int32_t nt, const StepArgs &a, int32_t *h,
+                   hipStream_t s)
 {
     const dim3 grid(grid_of(nt)), block(BS);
-    if (parity == 0) hipLaunchKernelGGL((k_step<BS, MODEL, 0>), grid, block, 0, s, geo, ti, nt, a, h);
-    else hipLaunchKernelGGL((k_step<BS, MODEL, 1>), grid, block, 0, s, geo, ti, nt, a, h);
+    if (parity == 0) hipLaunchKernelGGL((k_step<BS, CPT, NT, MODEL, 0>), grid, block, 0, s, geo, ti, nt, a, h);
+    else hipLaunchKernelGGL((k_step<BS, CPT, NT, MODEL, 1>), grid, block, 0, s, geo, ti, nt, a, h);
 }
 
-int launch_step(int block, int model, int parity, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
+template <int BS, int CPT, bool NT>
+static void step_m(int model, int parity, const Geo *geo, const int32_t *ti, int32_t nt, const StepArgs &a,
+                   int32_t *h, hipStream_t s)
+{
+    if (model == 0) step_v<BS, CPT, NT, 0>(parity, geo, ti, nt, a, h, s);
+    else step_v<BS, CPT, NT, 1>(parity, geo, ti, nt, a, h, s);
+}
+
+template <int BS, int CPT>
+static void step_n(const Variant &v, int model, int parity, const Geo *geo, const int32_t *ti, int32_t nt,
+                   const StepArgs &a, int32_t *h, hipStream_t s)
+{
+    if (v.nt) step_m<BS, CPT, true>(model, parity, geo, ti, nt, a, h, s);
+    else step_m<BS, CPT, false>(model, parity, geo, ti, nt, a, h, s);
+}
+
+bool variant_ok(const Variant &v)
+{
+    return (v.bs == 128 || v.bs == 256 || v.bs == 512) && (v.cpt == 1 || v.cpt == 2) && (v.nt == 0 || v.nt == 1);
+}
+
+int launch_step(const Variant &v, int model, int parity, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
                 const StepArgs &a, int32_t *health, hipStream_t s)
 {
     if (n_tiles <= 0) return 0;
-    if (block == 128) {
-        if (model == 0) step_bs<128, 0>(parity, geo, tile_inst, n_tiles, a, health, s);
-        else step_bs<128, 1>(parity, geo, tile_inst, n_tiles, a, health, s);
-    } else if (block == 512) {
-        if (model == 0) step_bs<512, 0>(parity, geo, tile_inst, n_tiles, a, health, s);
-        else step_bs<512, 1>(parity, geo, tile_inst, n_tiles, a, health, s);
-    } else if (block == 256) {
-        if (model == 0) step_bs<256, 0>(parity, geo, tile_inst, n_tiles, a, health, s);
-        else step_bs<256, 1>(parity, geo, tile_inst, n_tiles, a, health, s);
+    if (!variant_ok(v)) return -1;
+    if (v.bs == 128) {
+        if (v.cpt == 1) step_n<128, 1>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
+        else step_n<128, 2>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
+    } else if (v.bs == 256) {
+        if (v.cpt == 1) step_n<256, 1>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
+        else step_n<256, 2>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
     } else {
-        return -1;
+        if (v.cpt == 1) step_n<512, 1>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
+        else step_n<512, 2>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
     }
     return (int)hipGetLastError();
 }
@@ -744,21 +901,14 @@ int launch_moments(const float *q, const double *w, int32_t nq, int64_t n, doubl
     return (int)hipGetLastError();
 }
 
-template <int BS>
-static void adjoint_bs(int model, const Geo *geo, const int32_t *ti, int32_t nt, const AdjArgs &a, hipStream_t s)
-{
-    const dim3 grid(grid_of(nt)), block(BS);
-    if (model == 0) hipLaunchKernelGGL((k_adjoint<BS, 0>), grid, block, 0, s, geo, ti, nt, a);
-    else hipLaunchKernelGGL((k_adjoint<BS, 1>), grid, block, 0, s, geo, ti, nt, a);
-}
-
-int launch_adjoint(int block, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, const AdjArgs &a,
+int launch_adjoint(int tile_cells, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, const AdjArgs &a,
                    hipStream_t s)
 {
-    if (block == 128) adjoint_bs<128>(a.model, geo, tile_inst, n_tiles, a, s);
-    else if (block == 512) adjoint_bs<512>(a.model, geo, tile_inst, n_tiles, a, s);
-    else if (block == 256) adjoint_bs<256>(a.model, geo, tile_inst, n_tiles, a, s);
-    else return -1;
+    constexpr int BS = 128;
+    if (tile_cells % BS) return -1;
+    const dim3 grid(grid_of(n_tiles)), block(BS);
+    if (a.model == 0) hipLaunchKernelGGL((k_adjoint<BS, 0>), grid, block, 0, s, geo, tile_inst, n_tiles, tile_cells, a);
+    else hipLaunchKernelGGL((k_adjoint<BS, 1>), grid, block, 0, s, geo, tile_inst, n_tiles, tile_cells, a);
     return (int)hipGetLastError();
 }
 

@@ -61,8 +61,9 @@ int check_domain(const lbm_domain *d)
     if (!d) return fail(LBM_E_INVALID, "domain is NULL");
     if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(LBM_E_INVALID, "non-positive box size");
     const int64_t n = ncells_of(d);
-    if (n > (int64_t)INT32_MAX || 19 * stride_of(n) > (int64_t)INT32_MAX)
-        return fail(LBM_E_INVALID, "box of %lld cells exceeds the 32-bit index range", (long long)n);
+    // kernels address a population array with 32-bit byte offsets
+    if (n > (int64_t)INT32_MAX || 19 * stride_of(n) >= ((int64_t)1 << 30))
+        return fail(LBM_E_INVALID, "box of %lld cells exceeds the 32-bit byte-offset range", (long long)n);
     const int *f = d->face;
     for (int k = 0; k < 6; ++k)
         if (f[k] < LBM_WALL || f[k] > LBM_PERIODIC) return fail(LBM_E_INVALID, "face %d has unknown kind %d", k, f[k]);
@@ -128,7 +129,7 @@ int check_device()
 struct lbm_plan {
     int n_inst = 0;
     int model = 0;
-    int block = 256;
+    Variant v{256, 1, 0};
     std::vector<lbm_instance> inst;
     std::vector<Geo> geo_h;
     Geo *geo_d = nullptr;
@@ -154,7 +155,7 @@ int build_tiles(lbm_plan *p)
     for (int i = 0; i < p->n_inst; ++i) {
         Geo &g = p->geo_h[i];
         g.tile0 = (int32_t)tiles.size();
-        const int64_t nt = (g.ncells + p->block - 1) / p->block;
+        const int64_t nt = (g.ncells + p->v.tile() - 1) / p->v.tile();
         if ((int64_t)tiles.size() + nt > (int64_t)INT32_MAX / 2) return fail(LBM_E_INVALID, "too many tiles");
         for (int64_t t = 0; t < nt; ++t) tiles.push_back(i);
     }
@@ -209,7 +210,7 @@ bool step_accumulates(const lbm_plan *p, int64_t n) { return p->avg_begin < n &&
 
 int flush(lbm_plan *p, hipStream_t s)
 {
-    if (launch_flush(p->block, p->geo_d, p->tiles_d, p->n_tiles, s)) return fail(LBM_E_HIP, "flush launch failed");
+    if (launch_flush(p->v.tile(), p->geo_d, p->tiles_d, p->n_tiles, s)) return fail(LBM_E_HIP, "flush launch failed");
     p->pending = 0;
     return LBM_OK;
 }
@@ -223,8 +224,8 @@ int ensure_graph(lbm_plan *p)
     a.step = (p->ramp_max + 1) / 2 * 2 + 2;
     HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < p->graph_pairs; ++k) {
-        launch_step(p->block, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, cap);
-        launch_step(p->block, p->model, 1, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, cap);
+        launch_step(p->v, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, cap);
+        launch_step(p->v, p->model, 1, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, cap);
     }
     hipGraph_t g;
     HIPCHK(hipStreamEndCapture(cap, &g));
@@ -268,14 +269,14 @@ int run_steps(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_d, i
         a.record = kind;
         a.rec = rec_d;
         a.rec_slot = kind ? (n % n_slots) : 0;
-        if (launch_step(p->block, p->model, (int)(n & 1), p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s))
+        if (launch_step(p->v, p->model, (int)(n & 1), p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s))
             return fail(LBM_E_HIP, "step launch failed: %s", hipGetErrorString(hipGetLastError()));
         p->step = n + 1;
         --left;
         if (a.accumulate) ++p->pending;
         if (kind == 0 && p->avg_end > p->avg_begin && p->step == p->avg_end && p->step > p->avg_begin) {
             // the last state of the window is never collided inside the window
-            if (launch_capture(p->block, (int)(p->step & 1), p->geo_d, p->tiles_d, p->n_tiles, p->step,
+            if (launch_capture(p->v.tile(), (int)(p->step & 1), p->geo_d, p->tiles_d, p->n_tiles, p->step,
                                p->health_d, s))
                 return fail(LBM_E_HIP, "capture launch failed");
             ++p->pending;
@@ -466,11 +467,16 @@ int lbm_plan_create(const lbm_instance *inst, int32_t n_inst, const lbm_plan_opt
     *plan_out = nullptr;
     int r = check_device();
     if (r) return r;
-    const int block = opts && opts->block ? opts->block : 256;
-    if (block != 128 && block != 256 && block != 512) return fail(LBM_E_INVALID, "block must be 128, 256 or 512");
+    Variant v{256, 1, 0};
+    if (opts && opts->block) v.bs = opts->block;
+    if (opts && opts->cells_per_thread) v.cpt = opts->cells_per_thread;
+    if (opts) v.nt = opts->nontemporal;
+    if (!variant_ok(v))
+        return fail(LBM_E_INVALID, "launch shape: block must be 128, 256 or 512, cells per thread 1 or 2, "
+                                   "non-temporal 0 or 1");
     lbm_plan *p = new lbm_plan();
     p->n_inst = n_inst;
-    p->block = block;
+    p->v = v;
     p->inst.assign(inst, inst + n_inst);
     p->model = inst[0].model;
     if (opts) {
@@ -712,7 +718,7 @@ int lbm_adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float
     a.in_window = (p->avg_begin < step && step <= p->avg_end) ? 1 : 0;
     a.inv_count = p->avg_end > p->avg_begin ? 1.0 / (double)(p->avg_end - p->avg_begin) : 0.0;
     a.grad = dJdtheta_dev;
-    if (launch_adjoint(p->block, p->geo_d, p->tiles_d, p->n_tiles, a, s))
+    if (launch_adjoint(p->v.tile(), p->geo_d, p->tiles_d, p->n_tiles, a, s))
         return fail(LBM_E_HIP, "adjoint launch failed: %s", hipGetErrorString(hipGetLastError()));
     return LBM_OK;
 }
@@ -733,12 +739,21 @@ int lbm_adjoint_init(lbm_plan *p, float *const *lam_out_host, const double *cons
     a.model = p->model;
     a.in_window = (p->avg_begin < p->step && p->step <= p->avg_end) ? 1 : 0;
     a.inv_count = p->avg_end > p->avg_begin ? 1.0 / (double)(p->avg_end - p->avg_begin) : 0.0;
-    if (launch_adjoint_init(p->block, p->geo_d, p->tiles_d, p->n_tiles, a, s))
+    if (launch_adjoint_init(p->v.tile(), p->geo_d, p->tiles_d, p->n_tiles, a, s))
         return fail(LBM_E_HIP, "adjoint init launch failed");
     return LBM_OK;
 }
 
-int lbm_plan_autotune(lbm_plan *p, hipStream_t s, int32_t *block_out)
+int lbm_plan_variant(const lbm_plan *p, int32_t variant_out[3])
+{
+    if (!p || !variant_out) return fail(LBM_E_INVALID, "bad arguments");
+    variant_out[0] = p->v.bs;
+    variant_out[1] = p->v.cpt;
+    variant_out[2] = p->v.nt;
+    return LBM_OK;
+}
+
+int lbm_plan_autotune(lbm_plan *p, hipStream_t s, int32_t variant_out[3])
 {
     int r = check_plan(p);
     if (r) return r;
@@ -746,11 +761,13 @@ int lbm_plan_autotune(lbm_plan *p, hipStream_t s, int32_t *block_out)
     const std::string key = tune_key(p);
     std::map<std::string, int> cache = read_tune_cache();
     auto it = cache.find(key);
-    int best = 0;
-    if (it != cache.end() && (it->second == 128 || it->second == 256 || it->second == 512)) {
-        best = it->second;
+    Variant best{0, 0, 0};
+    auto decode = [](int code) { return Variant{code & 0xffff, (code >> 16) & 0xff, (code >> 24) & 0xff}; };
+    auto encode = [](const Variant &v) { return v.bs | (v.cpt << 16) | (v.nt << 24); };
+    if (it != cache.end() && variant_ok(decode(it->second))) {
+        best = decode(it->second);
     } else {
-        // save the populations, time step pairs for each block size, restore
+        // save the populations, time step pairs for every launch shape, restore
         std::vector<size_t> bytes(p->n_inst);
         size_t total = 0;
         for (int i = 0; i < p->n_inst; ++i) total += (bytes[i] = sizeof(float) * 19 * (size_t)p->geo_h[i].qs);
@@ -766,34 +783,36 @@ int lbm_plan_autotune(lbm_plan *p, hipStream_t s, int32_t *block_out)
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         float best_ms = 1e30f;
-        const int cand[3] = {256, 128, 512};
-        const int saved_block = p->block;
-        for (int bs : cand) {
-            p->block = bs;
-            r = build_tiles(p);
-            if (r) break;
-            StepArgs a{};
-            a.step = p->ramp_max + 2;
-            for (int w = 0; w < 2; ++w) {
-                launch_step(bs, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
-                launch_step(bs, p->model, 1, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
-            }
-            HIPCHK(hipEventRecord(e0, s));
-            const int pairs = 6;
-            for (int w = 0; w < pairs; ++w) {
-                launch_step(bs, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
-                launch_step(bs, p->model, 1, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
-            }
-            HIPCHK(hipEventRecord(e1, s));
-            HIPCHK(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = bs;
-            }
-        }
-        if (!best) best = saved_block;
+        const Variant saved = p->v;
+        for (int bs : {128, 256, 512})
+            for (int cpt : {1, 2})
+                for (int nt : {0, 1}) {
+                    const Variant v{bs, cpt, nt};
+                    p->v = v;
+                    r = build_tiles(p);
+                    if (r) break;
+                    StepArgs a{};
+                    a.step = p->ramp_max + 2;
+                    for (int w = 0; w < 2; ++w) {
+                        launch_step(v, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
+                        launch_step(v, p->model, 1, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
+                    }
+                    HIPCHK(hipEventRecord(e0, s));
+                    const int pairs = 6;
+                    for (int w = 0; w < pairs; ++w) {
+                        launch_step(v, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
+                        launch_step(v, p->model, 1, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
+                    }
+                    HIPCHK(hipEventRecord(e1, s));
+                    HIPCHK(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = v;
+                    }
+                }
+        if (!best.bs) best = saved;
         off = 0;
         for (int i = 0; i < p->n_inst; ++i) {
             HIPCHK(hipMemcpyAsync(p->geo_h[i].f, save + off, bytes[i], hipMemcpyDeviceToDevice, s));
@@ -805,14 +824,13 @@ int lbm_plan_autotune(lbm_plan *p, hipStream_t s, int32_t *block_out)
         HIPCHK(hipEventDestroy(e0));
         HIPCHK(hipEventDestroy(e1));
         if (r) return r;
-        cache[key] = best;
+        cache[key] = encode(best);
         write_tune_cache(cache);
     }
-    p->block = best;
+    p->v = best;
     r = build_tiles(p);
     if (r) return r;
-    if (block_out) *block_out = best;
-    return LBM_OK;
+    return lbm_plan_variant(p, variant_out);
 }
 
 }  // extern "C"

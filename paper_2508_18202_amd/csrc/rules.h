@@ -146,6 +146,145 @@ LBM_HD void cell_flags(const Box &b, const uint8_t *solid, int x, int y, int z, 
     if (x == 0 && b.face[0] == FACE_INLET) fl |= FL_INLET;
 }
 
+// ---------------------------------------------------------------------------
+// The same rules in relative form, for one compile-time direction: the source
+// (gather) or destinations (scatter) as a population slot and a cell offset
+// from the current cell, chosen by selects on per-cell predicates instead of
+// branches.  Equal to pull_src / push_dsts for every link (checked on the
+// host), so a wavefront can evaluate them for all of its lanes at once.
+
+struct Preds {
+    bool xlo, xhi, ylo, yhi, zlo, zhi;   // cell on the -x, +x, ... face of the box
+};
+
+struct Shape {
+    int nx, ny, nz;
+    int offy, offz;                      // linear offsets of +y and +z neighbours
+    int face[6];
+};
+
+struct RelLink {
+    int slot;      // population slot read or written
+    int delta;     // cell offset from the current cell
+    bool inlet;    // add the moving-wall momentum of the link
+    bool valid;    // the link exists (scatter: a destination)
+};
+
+LBM_HD Preds preds_of(const Shape &s, int x, int y, int z)
+{
+    return Preds{x == 0, x == s.nx - 1, y == 0, y == s.ny - 1, z == 0, z == s.nz - 1};
+}
+
+// wrap correction of a periodic axis: moving by -1 from 0, or +1 from n-1
+LBM_HD int wrap_corr(bool periodic, bool below, bool above, int span)
+{
+    return periodic ? (below ? span : (above ? -span : 0)) : 0;
+}
+
+template <int I>
+LBM_HD RelLink gather_rel(const Shape &s, const Preds &p, uint32_t smask)
+{
+    constexpr int CX = cx(I), CY = cy(I), CZ = cz(I);
+    // source s = x - c leaves the box below/above along each axis
+    const bool xb = CX == 1 && p.xlo, xa = CX == -1 && p.xhi;
+    const bool yb = CY == 1 && p.ylo, ya = CY == -1 && p.yhi;
+    const bool zb = CZ == 1 && p.zlo, za = CZ == -1 && p.zhi;
+    const bool px = s.face[0] == FACE_PERIODIC, py = s.face[2] == FACE_PERIODIC, pz = s.face[4] == FACE_PERIODIC;
+    const bool outside = (!px && (xb || xa)) || (!py && (yb || ya)) || (!pz && (zb || za));
+    const bool wall = (xb && s.face[0] == FACE_WALL) || (xa && s.face[1] == FACE_WALL) ||
+                      (yb && s.face[2] == FACE_WALL) || (ya && s.face[3] == FACE_WALL) ||
+                      (zb && s.face[4] == FACE_WALL) || (za && s.face[5] == FACE_WALL);
+    const bool solid = !outside && ((smask >> I) & 1u);
+    const bool bounce = solid || wall;
+    const bool inlet = !bounce && xb && s.face[0] == FACE_INLET;
+    const bool fslip = !bounce && !inlet && za && s.face[5] == FACE_FREESLIP;
+    const bool outlet = !bounce && !inlet && !fslip && xa && s.face[1] == FACE_OUTLET;
+    const int wx = wrap_corr(px, xb, xa, s.nx);
+    const int wy = wrap_corr(py, yb, ya, s.ny) * s.offy;
+    const int wz = wrap_corr(pz, zb, za, s.nz) * s.offz;
+    const int stream_delta = -(CX + CY * s.offy + CZ * s.offz) + wx + wy + wz;
+    RelLink r;
+    r.valid = true;
+    r.inlet = inlet;
+    if (bounce || inlet) {
+        r.slot = I;
+        r.delta = 0;
+    } else if (fslip) {
+        // (x - c_x [nx clamped to nx-1], y - c_y, nz-1) with c_z mirrored
+        const bool clamp = xa && s.face[1] == FACE_OUTLET;
+        r.slot = opp(zflip(I));
+        r.delta = (clamp ? 0 : -CX + wx) - CY * s.offy + wy;
+    } else if (outlet) {
+        r.slot = opp(I);
+        r.delta = stream_delta - 1;
+    } else {
+        r.slot = opp(I);
+        r.delta = stream_delta;
+    }
+    return r;
+}
+
+// Destinations of the post-collision value of direction K: primary and extra.
+template <int K>
+LBM_HD void scatter_rel(const Shape &s, const Preds &p, uint32_t smask, RelLink &prim, RelLink &extra)
+{
+    constexpr int CX = cx(K), CY = cy(K), CZ = cz(K);
+    // destination d = x + c leaves the box below/above along each axis
+    const bool xb = CX == -1 && p.xlo, xa = CX == 1 && p.xhi;
+    const bool yb = CY == -1 && p.ylo, ya = CY == 1 && p.yhi;
+    const bool zb = CZ == -1 && p.zlo, za = CZ == 1 && p.zhi;
+    const bool px = s.face[0] == FACE_PERIODIC, py = s.face[2] == FACE_PERIODIC, pz = s.face[4] == FACE_PERIODIC;
+    const bool outside = (!px && (xb || xa)) || (!py && (yb || ya)) || (!pz && (zb || za));
+    const bool wall = (xb && s.face[0] == FACE_WALL) || (xa && s.face[1] == FACE_WALL) ||
+                      (yb && s.face[2] == FACE_WALL) || (ya && s.face[3] == FACE_WALL) ||
+                      (zb && s.face[4] == FACE_WALL) || (za && s.face[5] == FACE_WALL);
+    const bool solid = !outside && ((smask >> opp(K)) & 1u);
+    const int wx = wrap_corr(px, xa, xb, s.nx) * -1;
+    const int wy = wrap_corr(py, ya, yb, s.ny) * -s.offy;
+    const int wz = wrap_corr(pz, za, zb, s.nz) * -s.offz;
+    prim.inlet = false;
+    prim.valid = true;
+    extra.inlet = false;
+    extra.valid = false;
+    extra.slot = K;
+    extra.delta = 0;
+    if (!outside && !solid) {
+        prim.slot = K;
+        prim.delta = CX + CY * s.offy + CZ * s.offz + wx + wy + wz;
+    } else if (solid || wall) {
+        prim.slot = opp(K);
+        prim.delta = 0;
+    } else if (xb && s.face[0] == FACE_INLET) {
+        prim.slot = opp(K);
+        prim.delta = 0;
+        prim.inlet = true;
+    } else if (za && s.face[5] == FACE_FREESLIP && (px || !(xb || xa))) {
+        prim.slot = zflip(K);
+        prim.delta = CX + wx + CY * s.offy + wy;
+    } else {
+        prim.valid = false;
+        prim.slot = K;
+        prim.delta = 0;
+    }
+    // the outflow column also feeds the zero-gradient links of its neighbours
+    if (CX == -1 && p.xhi && s.face[1] == FACE_OUTLET) {
+        const bool tyo = !py && ((CY == -1 && p.ylo) || (CY == 1 && p.yhi));
+        const bool tzb = CZ == -1 && p.zlo, tza = CZ == 1 && p.zhi;
+        const bool tzo = !pz && (tzb || tza);
+        const int ey = wrap_corr(py, CY == 1 && p.yhi, CY == -1 && p.ylo, s.ny) * -s.offy;
+        const int ez = wrap_corr(pz, tza, tzb, s.nz) * -s.offz;
+        if (!tyo && !tzo) {
+            extra.valid = true;
+            extra.slot = K;
+            extra.delta = CY * s.offy + ey + CZ * s.offz + ez;
+        } else if (!tyo && tza && s.face[5] == FACE_FREESLIP) {
+            extra.valid = true;
+            extra.slot = zflip(K);
+            extra.delta = CY * s.offy + ey;
+        }
+    }
+}
+
 // Granlund-Montgomery division by a constant d >= 1 for 0 <= v < 2^31.
 struct FastDiv {
     uint32_t m;

@@ -70,7 +70,7 @@ class Ensemble:
 
     def __init__(self, cases: Sequence[CaseGeometry], thetas: Sequence[Sequence[Sequence[float]]],
                  avg_begin: int = 0, avg_end: int = 0, fields: bool = True, probe_sums: bool = True,
-                 use_graph: bool = True, block: int = 0):
+                 use_graph: bool = True, block: int = 0, variant: Optional[Sequence[int]] = None):
         self.cases = list(cases)
         self.index: List[Tuple[int, int]] = []
         self.f: List[torch.Tensor] = []
@@ -113,7 +113,8 @@ class Ensemble:
                 self.qsum.append(qsm)
                 self.psum.append(ps)
         self.instances = insts
-        self.plan = L.lbm_plan_create(insts, avg_begin, avg_end, use_graph, block)
+        bs, cpt, nt = tuple(variant) if variant is not None else (block, 0, 0)
+        self.plan = L.lbm_plan_create(insts, avg_begin, avg_end, use_graph, bs, cpt, nt)
         L.lbm_plan_reset_qoi(self.plan, stream_handle())
 
     def reset(self):
@@ -188,7 +189,7 @@ def moments(q: torch.Tensor, weights: np.ndarray, count_negative: bool = False):
 
 def run_sc(w: Workload, solid: np.ndarray, steps: Optional[int] = None, avg_start: Optional[int] = None,
            probes: Optional[np.ndarray] = None, use_graph: bool = True, block: int = 0,
-           check_every: int = 0):
+           check_every: int = 0, variant: Optional[Sequence[int]] = None):
     """One SC-LBM pass of one case: every collocation node advanced together,
     then the quadrature mean and variance of the QoI fields.
 
@@ -200,7 +201,7 @@ def run_sc(w: Workload, solid: np.ndarray, steps: Optional[int] = None, avg_star
     cg = make_geometry(w, solid, probes)
     window = avg_start < steps
     ens = Ensemble([cg], [th], avg_begin=avg_start if window else 0, avg_end=steps if window else 0,
-                   use_graph=use_graph, block=block)
+                   use_graph=use_graph, block=block, variant=variant)
     try:
         if check_every:
             done = 0

@@ -138,7 +138,7 @@ def _check(nx, ny, nz, faces, solid, block):
 
 
 @pytest.mark.parametrize("faces", FACE_SETS)
-@pytest.mark.parametrize("block", [128, 256, 512])
+@pytest.mark.parametrize("block", [128, 256, 512, 1024])
 def test_scatter_is_inverse_and_race_free(faces, block):
     for seed, (nx, ny, nz) in enumerate([(8, 6, 5), (12, 4, 7), (10, 9, 3), (16, 16, 4)]):
         solid = _random_solid(nx, ny, nz, faces, seed)
@@ -147,11 +147,26 @@ def test_scatter_is_inverse_and_race_free(faces, block):
         assert stats[0] > 0
 
 
+@pytest.mark.parametrize("faces", FACE_SETS)
+def test_relative_rules_equal_link_rules(faces):
+    """The per-direction predicated form the kernels evaluate wave-wide equals
+    the per-link rules at every fluid cell and direction."""
+    hostcheck().lbmhc_check_relative.restype = ctypes.c_int
+    for seed, (nx, ny, nz) in enumerate([(8, 6, 5), (12, 4, 7), (10, 9, 3), (2, 3, 2), (6, 1, 4)]):
+        if faces[1] == "outlet" and nx % 2:
+            continue
+        solid = _random_solid(nx, ny, nz, faces, 100 + seed)
+        face = (ctypes.c_int * 6)(*[L.FACES[f] for f in faces])
+        s = np.ascontiguousarray(solid, np.uint8)
+        rc = hostcheck().lbmhc_check_relative(nx, ny, nz, face, s.ctypes.data_as(ctypes.c_void_p))
+        assert rc == 0, (faces, nx, ny, nz, rc)
+
+
 @pytest.mark.parametrize("w", [inputs.small_block(), inputs.scaled(inputs.urban_les(), 64, 32, 24),
                                inputs.scaled(inputs.adjoint_case(), 64, 32, 24)])
 def test_workload_geometries_race_free(w):
     solid = inputs.solid_mask(w)
-    for block in (128, 256, 512):
+    for block in (128, 256, 512, 1024):
         rc, stats = _check(w.nx, w.ny, w.nz, w.faces, solid, block)
         assert rc == 0, (rc, stats)
     if w.faces[1] == "outlet":

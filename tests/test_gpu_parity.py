@@ -235,13 +235,15 @@ def test_batched_uneven_matches_one_at_a_time():
             i += 1
 
 
-@pytest.mark.parametrize("block", [128, 512])
-def test_block_sizes_and_graphs_bitwise(block):
+@pytest.mark.parametrize("variant", [(128, 1, 0), (512, 1, 1), (128, 2, 0), (256, 2, 1), (512, 2, 0)])
+def test_launch_shapes_and_graphs_bitwise(variant):
+    """Every launch shape (threads per workgroup, cells per thread,
+    non-temporal) and graph replay give the same populations bit for bit."""
     w = inputs.scaled(inputs.urban_les(), 64, 32, 24, ramp=4)
     solid = inputs.solid_mask(w)
     _, _, th = sc.collocation(w)
     outs = []
-    for kw in (dict(block=256, use_graph=False), dict(block=block, use_graph=True)):
+    for kw in (dict(variant=(256, 1, 0), use_graph=False), dict(variant=variant, use_graph=True)):
         ens, _ = _ensemble(w, solid, th[:3], **kw)
         try:
             ens.advance(57)
