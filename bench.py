@@ -41,7 +41,9 @@ def parse():
     ap.add_argument("--avg-len", type=int, default=5000, help="QoI averaging window")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0: autotuned shape)")
     ap.add_argument("--cells-per-thread", type=int, default=1)
-    ap.add_argument("--nontemporal", type=int, default=0)
+    ap.add_argument("--model", default="smagorinsky", help=argparse.SUPPRESS)
+    ap.add_argument("--nontemporal", type=int, default=1, help="mask: 1 even steps, 2 odd steps")
+    ap.add_argument("--xcd-order", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost leg")
     ap.add_argument("--no-uneven", action="store_true", help="skip the batched vs one-at-a-time leg")
@@ -154,7 +156,8 @@ def uneven_leg(variant, steps: int = 60):
         plans = []
         for k, inst in enumerate(ens.instances):
             plans.append(L.lbm_plan_create([inst], use_graph=False, block=variant[0],
-                                           cells_per_thread=variant[1], nontemporal=variant[2]))
+                                           cells_per_thread=variant[1], nontemporal=variant[2],
+                                           xcd_order=variant[3]))
             L.lbm_plan_set_step(plans[-1], ens.step)
         stream = sc.stream_handle()
         torch.cuda.synchronize()
@@ -193,6 +196,8 @@ def main():
     torch.cuda.set_device(0)
     lbm_steps = args.lbm_steps
     w = inputs.urban_les(steps=lbm_steps, avg_len=min(args.avg_len, lbm_steps))
+    if args.model != w.model:        # experiments only: the workload is Smagorinsky
+        w = inputs.scaled(w, w.nx, w.ny, w.nz, model=args.model, tau0=0.6, cs=0.0)
     solid = inputs.solid_mask(w)
     n_fluid = int((solid == 0).sum())
     ramp = min(w.ramp, w.avg_start)
@@ -201,7 +206,7 @@ def main():
     # launch shape (block, cells per thread, non-temporal) from the project's
     # autotuner, cached per architecture / model / box sizes
     if args.block:
-        variant = (args.block, args.cells_per_thread, args.nontemporal)
+        variant = (args.block, args.cells_per_thread, args.nontemporal, args.xcd_order)
     else:
         x, a, th = sc.collocation(w)
         cg = sc.make_geometry(w, solid)
@@ -274,7 +279,8 @@ def main():
             "lbm_steps": lbm_steps,
             "instances": n_inst,
             "fluid_cells_per_instance": n_fluid,
-            "launch": {"block": variant[0], "cells_per_thread": variant[1], "nontemporal": variant[2]},
+            "launch": {"block": variant[0], "cells_per_thread": variant[1], "nontemporal": variant[2],
+                       "xcd_order": variant[3]},
             "parallelism": "batched instances, 1 GPU",
         },
         "roofline": {

@@ -112,7 +112,11 @@ typedef struct lbm_plan_opts {
     int32_t block;             /* threads per workgroup: 128, 256 or 512; 0 = default (256) */
     int32_t cells_per_thread;  /* 1 or 2; 0 = default (1).  A workgroup owns block *
                                   cells_per_thread consecutive cells of one instance */
-    int32_t nontemporal;       /* 1: streaming (non-temporal) population loads and stores */
+    int32_t nontemporal;       /* streaming (non-temporal) population loads and stores:
+                                  bit 0 in even steps, bit 1 in odd steps */
+    int32_t xcd_order;         /* 1: give each XCD a contiguous range of tiles.  The last
+                                  three fields apply only when block != 0; otherwise the
+                                  default shape (256, 1, even steps non-temporal, 0) */
 } lbm_plan_opts;
 
 typedef struct lbm_plan lbm_plan;
@@ -170,13 +174,13 @@ int lbm_sync(lbm_plan *plan, hipStream_t stream);
  * index through *bad_inst if any instance saw rho <= 0 or a non-finite rho. */
 int lbm_check_health(lbm_plan *plan, hipStream_t stream, int32_t *bad_inst);
 /* Launch shape of the step kernels: variant_out = {block, cells_per_thread,
- * nontemporal}.  lbm_plan_autotune times step pairs of every shape on the
+ * nontemporal, xcd_order}.  lbm_plan_autotune times step pairs of every shape on the
  * batch (populations, step counter and QoI sums are restored afterwards),
  * keeps the fastest and caches it in the JSON file named by LBMSC_TUNE_CACHE
  * (default ~/.cache/lbmsc_tune.json), keyed by architecture, model, instance
  * count and box sizes. */
-int lbm_plan_variant(const lbm_plan *plan, int32_t variant_out[3]);
-int lbm_plan_autotune(lbm_plan *plan, hipStream_t stream, int32_t variant_out[3]);
+int lbm_plan_variant(const lbm_plan *plan, int32_t variant_out[4]);
+int lbm_plan_autotune(lbm_plan *plan, hipStream_t stream, int32_t variant_out[4]);
 
 /* --------------------------------------------- collide and stream (a4/a6)
  * Advance every instance of the plan by n_steps time steps of Eq.

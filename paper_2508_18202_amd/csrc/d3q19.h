@@ -45,6 +45,16 @@ LBM_HD constexpr double wgt_d(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0
 enum : int { FACE_WALL = 0, FACE_INLET = 1, FACE_OUTLET = 2, FACE_FREESLIP = 3, FACE_PERIODIC = 4 };
 
 // per-cell flag bits
-enum : uint8_t { FL_SOLID = 1, FL_NEAR = 2, FL_PROBE = 4, FL_INLET = 8 };
+//   SOLID    solid cell
+//   NEAR     some link of the cell is not plain in-box streaming
+//   PROBE    probe cell
+//   INLET    on the inflow face (x = 0 with an INLET face)
+//   GENERAL  NEAR for a reason other than being in the x = 0 or x = nx-1
+//            column of non-periodic x faces (solid neighbour, y or z face,
+//            periodic wrap, sky layer)
+//   XLO/XHI  x = 0 / x = nx-1
+enum : uint8_t {
+    FL_SOLID = 1, FL_NEAR = 2, FL_PROBE = 4, FL_INLET = 8, FL_GENERAL = 16, FL_XLO = 32, FL_XHI = 64
+};
 
 }  // namespace lbmsc

@@ -231,6 +231,36 @@ int check_rel_one(const Geo3 &g, const Shape &s, int x, int y, int z)
     return 0;
 }
 
+// cells flagged NEAR but not GENERAL: the x-column form (y/z predicates and
+// the solid mask dropped) must give the full form's links
+template <int I>
+int check_xpath_one(const Geo3 &g, const Shape &s, int x, int y, int z)
+{
+    const int64_t c = g.cell(x, y, z);
+    const uint8_t fl = g.fl[c];
+    if (!(fl & FL_NEAR) || (fl & FL_GENERAL)) return 0;
+    const Preds p = preds_of(s, x, y, z);
+    const Preds px{(fl & FL_XLO) != 0, (fl & FL_XHI) != 0, false, false, false, false};
+    if (p.ylo || p.yhi || p.zlo || p.zhi || g.m[c]) return 30;
+    const RelLink a = gather_rel<I>(s, p, g.m[c]), b = gather_rel<I>(s, px, 0u);
+    if (a.slot != b.slot || a.delta != b.delta || a.inlet != b.inlet) return 31;
+    RelLink pa, pe, qa, qe;
+    scatter_rel<I>(s, p, g.m[c], pa, pe);
+    scatter_rel<I>(s, px, 0u, qa, qe);
+    if (pa.valid != qa.valid || pe.valid != qe.valid) return 32;
+    if (pa.valid && (pa.slot != qa.slot || pa.delta != qa.delta || pa.inlet != qa.inlet)) return 33;
+    if (pe.valid && (pe.slot != qe.slot || pe.delta != qe.delta)) return 34;
+    return 0;
+}
+
+template <int... Is>
+int check_xpath_all(const Geo3 &g, const Shape &s, int x, int y, int z, std::integer_sequence<int, Is...>)
+{
+    int r = 0;
+    ((r = r ? r : check_xpath_one<Is>(g, s, x, y, z)), ...);
+    return r;
+}
+
 template <int... Is>
 int check_rel_all(const Geo3 &g, const Shape &s, int x, int y, int z, std::integer_sequence<int, Is...>)
 {
@@ -250,7 +280,8 @@ extern "C" int lbmhc_check_relative(int nx, int ny, int nz, const int *face, con
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 if (g.fl[g.cell(x, y, z)] & FL_SOLID) continue;
-                const int r = check_rel_all(g, s, x, y, z, std::make_integer_sequence<int, Q>{});
+                int r = check_rel_all(g, s, x, y, z, std::make_integer_sequence<int, Q>{});
+                if (!r) r = check_xpath_all(g, s, x, y, z, std::make_integer_sequence<int, Q>{});
                 if (r) return r;
             }
     return 0;

@@ -37,17 +37,19 @@ struct StepArgs {
     int64_t step;              // time index n of the state being collided
     int32_t accumulate;        // add this state's QoIs to the window sums
     int32_t record;            // 0 none, 1 (rho,u), 2 populations
+    int32_t xcd_remap;         // tiles in contiguous ranges per XCD (set from the variant)
     float *const *rec;         // device array [n_inst] of record buffer bases
     int64_t rec_slot;          // slot index n % n_slots
 };
 
 // Launch shape of the step kernels: threads per workgroup, cells per
 // thread (a tile holds bs * cpt consecutive cells) and non-temporal
-// population loads/stores.
+// population loads/stores (mask: bit 0 even steps, bit 1 odd steps).
 struct Variant {
     int bs;
     int cpt;
     int nt;
+    int xcd;                   // 1: XCD-contiguous tile order
     int tile() const { return bs * cpt; }
 };
 

@@ -64,8 +64,10 @@ __device__ __forceinline__ void stg(GLOBAL_AS T *base, uint32_t idx, T v)
     else *p = v;
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous range of tiles so neighbouring tiles share one L2.
+// Workgroups are dispatched round-robin over the 8 XCDs.  xcd_tile() gives
+// each XCD a contiguous range of tiles (neighbouring tiles then share one L2);
+// measured on the streaming step kernels, the plain round-robin order keeps
+// HBM busier, so the step kernels take the remap only as a tunable option.
 __device__ __forceinline__ int xcd_tile()
 {
     const int G8 = gridDim.x >> 3;
@@ -204,39 +206,64 @@ struct Macro {
     float drho, rho, ux, uy, uz;
 };
 
-__device__ __forceinline__ Macro macro_of(const float g[Q])
+// Opposite directions come in pairs (2k+1, 2k+2), k = 0..8: their sums carry
+// the even moments (density, stress), their differences the odd ones
+// (momentum), which halves the additions of the moment sums.
+struct PairSums {
+    float s[9], d[9];
+};
+
+__device__ __forceinline__ PairSums pair_sums(const float g[Q])
+{
+    PairSums p;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        p.s[k] = g[2 * k + 1] + g[2 * k + 2];
+        p.d[k] = g[2 * k + 1] - g[2 * k + 2];
+    }
+    return p;
+}
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+__device__ __forceinline__ Macro macro_of(const float g[Q], const PairSums &p)
 {
     Macro m;
-    float d = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+    float d = g[0], jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        d += g[i];
-        if (cx(i)) jx += cx(i) * g[i];
-        if (cy(i)) jy += cy(i) * g[i];
-        if (cz(i)) jz += cz(i) * g[i];
+    for (int k = 0; k < 9; ++k) {
+        const int i = 2 * k + 1;
+        d += p.s[k];
+        if (cx(i)) jx += cx(i) * p.d[k];
+        if (cy(i)) jy += cy(i) * p.d[k];
+        if (cz(i)) jz += cz(i) * p.d[k];
     }
     m.drho = d;
     m.rho = 1.0f + d;
-    const float inv = 1.0f / m.rho;
+    const float inv = fast_rcp(m.rho);
     m.ux = jx * inv;
     m.uy = jy * inv;
     m.uz = jz * inv;
     return m;
 }
 
+__device__ __forceinline__ Macro macro_of(const float g[Q]) { return macro_of(g, pair_sums(g)); }
+
 // Non-equilibrium stress Pi = sum c c (f - f_eq) from the shifted populations:
 // sum c c g - (drho/3) I - rho u u.  Order: xx, yy, zz, xy, xz, yz.
-__device__ __forceinline__ void neq_stress(const float g[Q], const Macro &m, float P[6])
+__device__ __forceinline__ void neq_stress(const PairSums &p, const Macro &m, float P[6])
 {
     float xx = 0.f, yy = 0.f, zz = 0.f, xy = 0.f, xz = 0.f, yz = 0.f;
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        if (cx(i)) xx += g[i];
-        if (cy(i)) yy += g[i];
-        if (cz(i)) zz += g[i];
-        if (cx(i) && cy(i)) xy += cx(i) * cy(i) * g[i];
-        if (cx(i) && cz(i)) xz += cx(i) * cz(i) * g[i];
-        if (cy(i) && cz(i)) yz += cy(i) * cz(i) * g[i];
+    for (int k = 0; k < 9; ++k) {
+        const int i = 2 * k + 1;
+        if (cx(i)) xx += p.s[k];
+        if (cy(i)) yy += p.s[k];
+        if (cz(i)) zz += p.s[k];
+        if (cx(i) && cy(i)) xy += cx(i) * cy(i) * p.s[k];
+        if (cx(i) && cz(i)) xz += cx(i) * cz(i) * p.s[k];
+        if (cy(i) && cz(i)) yz += cy(i) * cz(i) * p.s[k];
     }
     const float d3 = m.drho * (1.0f / 3.0f);
     P[0] = xx - d3 - m.rho * m.ux * m.ux;
@@ -247,20 +274,25 @@ __device__ __forceinline__ void neq_stress(const float g[Q], const Macro &m, flo
     P[5] = yz - m.rho * m.uy * m.uz;
 }
 
+__device__ __forceinline__ void neq_stress(const float g[Q], const Macro &m, float P[6])
+{
+    neq_stress(pair_sums(g), m, P);
+}
+
 __device__ __forceinline__ float stress_norm(const float P[6])
 {
-    return sqrtf(P[0] * P[0] + P[1] * P[1] + P[2] * P[2] +
-                 2.0f * (P[3] * P[3] + P[4] * P[4] + P[5] * P[5]));
+    return fast_sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2] +
+                     2.0f * (P[3] * P[3] + P[4] * P[4] + P[5] * P[5]));
 }
 
 template <int MODEL>
-__device__ __forceinline__ float tau_of(const Geo &G, const float g[Q], const Macro &m)
+__device__ __forceinline__ float tau_of(const Geo &G, const PairSums &p, const Macro &m)
 {
     if (MODEL == 0) return G.tau0;
     float P[6];
-    neq_stress(g, m, P);
+    neq_stress(p, m, P);
     const float q = stress_norm(P);
-    return 0.5f * (G.tau0 + sqrtf(G.tau0 * G.tau0 + G.kcs * q / m.rho));
+    return 0.5f * (G.tau0 + fast_sqrt(G.tau0 * G.tau0 + G.kcs * q * fast_rcp(m.rho)));
 }
 
 // shifted equilibrium f_eq - w
@@ -270,13 +302,24 @@ __device__ __forceinline__ float geq(int i, const Macro &m, float usq15)
     return wgt(i) * (m.drho + m.rho * (3.0f * cu + 4.5f * cu * cu - usq15));
 }
 
+// f* = f - omega (f - f_eq), the equilibrium of each opposite pair split into
+// its symmetric part w (drho + rho (4.5 (c.u)^2 - 1.5 u.u)) and its
+// antisymmetric part 3 w rho c.u.
 template <int MODEL>
-__device__ __forceinline__ void collide(const Geo &G, float g[Q], const Macro &m)
+__device__ __forceinline__ void collide(const Geo &G, float g[Q], const Macro &m, const PairSums &p)
 {
-    const float om = 1.0f / tau_of<MODEL>(G, g, m);
+    const float om = fast_rcp(tau_of<MODEL>(G, p, m));
     const float usq15 = 1.5f * (m.ux * m.ux + m.uy * m.uy + m.uz * m.uz);
+    g[0] = g[0] - om * (g[0] - wgt(0) * (m.drho - m.rho * usq15));
 #pragma unroll
-    for (int i = 0; i < Q; ++i) g[i] = g[i] - om * (g[i] - geq(i, m, usq15));
+    for (int k = 0; k < 9; ++k) {
+        const int i = 2 * k + 1;
+        const float cu = cx(i) * m.ux + cy(i) * m.uy + cz(i) * m.uz;
+        const float sym = wgt(i) * (m.drho + m.rho * (4.5f * cu * cu - usq15));
+        const float asym = 3.0f * wgt(i) * m.rho * cu;
+        g[i] = g[i] - om * (g[i] - (sym + asym));
+        g[i + 1] = g[i + 1] - om * (g[i + 1] - (sym - asym));
+    }
 }
 
 __device__ __forceinline__ void accumulate_qoi(const Geo &G, uint32_t c, uint8_t fl, const Macro &m)
@@ -301,7 +344,7 @@ template <int BS, int CPT, bool NT, int MODEL, int PARITY>
 __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
                                              int32_t n_tiles, StepArgs a, int32_t *__restrict__ health)
 {
-    const int tile = xcd_tile();
+    const int tile = a.xcd_remap ? xcd_tile() : (int)blockIdx.x;
     if (tile >= n_tiles) return;
     const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
     const Geo &G = geo[ii];
@@ -311,7 +354,7 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
 
     uint32_t c[CPT];
     uint8_t fl[CPT];
-    bool fluid[CPT], near_wave[CPT];
+    bool fluid[CPT], near_wave[CPT], general_wave[CPT];
     Preds pr[CPT];
     uint32_t sm[CPT];
     float U[CPT];
@@ -325,18 +368,25 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
         c[j] = active ? (uint32_t)lc : 0u;
         fl[j] = active ? gp(G.flags)[c[j]] : (uint8_t)FL_SOLID;
         fluid[j] = !(fl[j] & FL_SOLID);
-        // odd steps: wavefronts without boundary cells take the plain stencil,
-        // the others evaluate the boundary rules for all of their lanes at once
+        // odd steps: wavefronts without boundary cells take the plain stencil;
+        // wavefronts whose boundary cells only sit in the inflow/outflow
+        // columns evaluate the x rules for all lanes; the others evaluate the
+        // full rules for all lanes
         near_wave[j] = PARITY == 1 && __any(fluid[j] && (fl[j] & FL_NEAR));
+        general_wave[j] = PARITY == 1 && __any(fluid[j] && (fl[j] & FL_GENERAL));
         pr[j] = Preds{false, false, false, false, false, false};
         sm[j] = 0;
         U[j] = 0.0f;
-        if (near_wave[j] && fluid[j]) {
+        if (general_wave[j] && fluid[j]) {
             int x, y, z;
             coords(G, c[j], x, y, z);
             pr[j] = preds_of(S, x, y, z);
             sm[j] = gp(G.smask)[c[j]];
             U[j] = (fl[j] & FL_INLET) ? inflow_speed(G, z) : 0.0f;
+        } else if (near_wave[j] && fluid[j]) {
+            pr[j].xlo = fl[j] & FL_XLO;
+            pr[j].xhi = fl[j] & FL_XHI;
+            if (fl[j] & FL_INLET) U[j] = inflow_speed(G, (int)fdiv(c[j], G.dxy));
         }
     }
 #pragma unroll
@@ -348,14 +398,18 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
         } else if (!near_wave[j]) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) g[j][i] = ldg<NT>(f + (size_t)opp(i) * qs - off_of(G, i), c[j]);
-        } else {
+        } else if (general_wave[j]) {
             gather_all<NT>(G, S, pr[j], sm[j], c[j], U[j], ramp_factor(G, a.step - 1), g[j], Dirs{});
+        } else {
+            const Preds px{pr[j].xlo, pr[j].xhi, false, false, false, false};
+            gather_all<NT>(G, S, px, 0u, c[j], U[j], ramp_factor(G, a.step - 1), g[j], Dirs{});
         }
     }
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         if (!fluid[j]) continue;
-        const Macro m = macro_of(g[j]);
+        const PairSums ps = pair_sums(g[j]);
+        const Macro m = macro_of(g[j], ps);
         if (!(m.rho > 0.0f) || !isfinite(m.rho)) atomicOr(health + ii, 1);
         if (a.accumulate) accumulate_qoi(G, c[j], fl[j], m);
         if (a.record == 1) {
@@ -369,7 +423,7 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
 #pragma unroll
             for (int i = 0; i < Q; ++i) stg(r + (size_t)i * qs, c[j], g[j][i]);
         }
-        collide<MODEL>(G, g[j], m);
+        collide<MODEL>(G, g[j], m, ps);
     }
     if (PARITY == 1) __syncthreads();
 #pragma unroll
@@ -381,8 +435,11 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
         } else if (!near_wave[j]) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) stg<NT>(f + (size_t)i * qs + off_of(G, i), c[j], g[j][i]);
-        } else {
+        } else if (general_wave[j]) {
             scatter_all<NT>(G, S, pr[j], sm[j], c[j], U[j], ramp_factor(G, a.step), g[j], Dirs{});
+        } else {
+            const Preds px{pr[j].xlo, pr[j].xhi, false, false, false, false};
+            scatter_all<NT>(G, S, px, 0u, c[j], U[j], ramp_factor(G, a.step), g[j], Dirs{});
         }
     }
 }
@@ -671,19 +728,20 @@ __device__ __forceinline__ void adjoint_cell(const Geo &G, int ii, int32_t first
             uz = s.w;
             om = 1.0f / G.tau0;
         } else {
-            const float *rp = a.rec[ii] + (size_t)a.rec_slot * (size_t)Q * G.qs;
+            const GLOBAL_AS float *rp = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)Q * G.qs;
             float g[Q];
 #pragma unroll
-            for (int i = 0; i < Q; ++i) g[i] = rp[i * qs + c];
-            const Macro m = macro_of(g);
+            for (int i = 0; i < Q; ++i) g[i] = ldg(rp + (size_t)i * qs, c);
+            const PairSums ps = pair_sums(g);
+            const Macro m = macro_of(g, ps);
             rho = m.rho;
             ux = m.ux;
             uy = m.uy;
             uz = m.uz;
             if (MODEL == 1) {
-                neq_stress(g, m, P);
+                neq_stress(ps, m, P);
                 qn = stress_norm(P);
-                tau = 0.5f * (G.tau0 + sqrtf(G.tau0 * G.tau0 + G.kcs * qn / m.rho));
+                tau = tau_of<1>(G, ps, m);
                 const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
 #pragma unroll
                 for (int i = 0; i < Q; ++i) A += mu[i] * (g[i] - geq(i, m, usq15));
@@ -807,24 +865,28 @@ static void step_m(int model, int parity, const Geo *geo, const int32_t *ti, int
     else step_v<BS, CPT, NT, 1>(parity, geo, ti, nt, a, h, s);
 }
 
+// v.nt is a mask: bit 0 non-temporal accesses in even steps, bit 1 in odd steps
 template <int BS, int CPT>
 static void step_n(const Variant &v, int model, int parity, const Geo *geo, const int32_t *ti, int32_t nt,
                    const StepArgs &a, int32_t *h, hipStream_t s)
 {
-    if (v.nt) step_m<BS, CPT, true>(model, parity, geo, ti, nt, a, h, s);
+    if ((v.nt >> parity) & 1) step_m<BS, CPT, true>(model, parity, geo, ti, nt, a, h, s);
     else step_m<BS, CPT, false>(model, parity, geo, ti, nt, a, h, s);
 }
 
 bool variant_ok(const Variant &v)
 {
-    return (v.bs == 128 || v.bs == 256 || v.bs == 512) && (v.cpt == 1 || v.cpt == 2) && (v.nt == 0 || v.nt == 1);
+    return (v.bs == 128 || v.bs == 256 || v.bs == 512) && (v.cpt == 1 || v.cpt == 2) && v.nt >= 0 && v.nt <= 3 &&
+           (v.xcd == 0 || v.xcd == 1);
 }
 
 int launch_step(const Variant &v, int model, int parity, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
-                const StepArgs &a, int32_t *health, hipStream_t s)
+                const StepArgs &a0, int32_t *health, hipStream_t s)
 {
     if (n_tiles <= 0) return 0;
     if (!variant_ok(v)) return -1;
+    StepArgs a = a0;
+    a.xcd_remap = v.xcd;
     if (v.bs == 128) {
         if (v.cpt == 1) step_n<128, 1>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
         else step_n<128, 2>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);

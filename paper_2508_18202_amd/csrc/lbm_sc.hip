@@ -129,7 +129,7 @@ int check_device()
 struct lbm_plan {
     int n_inst = 0;
     int model = 0;
-    Variant v{256, 1, 0};
+    Variant v{256, 1, 1, 0};
     std::vector<lbm_instance> inst;
     std::vector<Geo> geo_h;
     Geo *geo_d = nullptr;
@@ -310,7 +310,9 @@ std::string tune_key(const lbm_plan *p)
     }
     std::sort(dims.begin(), dims.end());
     std::ostringstream os;
-    os << std::string(prop.gcnArchName).substr(0, 6) << "|m" << p->model << "|n" << p->n_inst;
+    // the build stamp keeps results of an older kernel build from being reused
+    os << std::string(prop.gcnArchName).substr(0, 6) << "|" << __DATE__ << " " << __TIME__ << "|m" << p->model
+       << "|n" << p->n_inst;
     // run-length encoded multiset of box sizes
     for (size_t i = 0; i < dims.size();) {
         size_t j = i;
@@ -467,13 +469,14 @@ int lbm_plan_create(const lbm_instance *inst, int32_t n_inst, const lbm_plan_opt
     *plan_out = nullptr;
     int r = check_device();
     if (r) return r;
-    Variant v{256, 1, 0};
+    Variant v{256, 1, 1, 0};
     if (opts && opts->block) v.bs = opts->block;
     if (opts && opts->cells_per_thread) v.cpt = opts->cells_per_thread;
-    if (opts) v.nt = opts->nontemporal;
+    if (opts && opts->block) v.nt = opts->nontemporal;
+    if (opts && opts->block) v.xcd = opts->xcd_order;
     if (!variant_ok(v))
         return fail(LBM_E_INVALID, "launch shape: block must be 128, 256 or 512, cells per thread 1 or 2, "
-                                   "non-temporal 0 or 1");
+                                   "non-temporal mask 0..3, XCD order 0 or 1");
     lbm_plan *p = new lbm_plan();
     p->n_inst = n_inst;
     p->v = v;
@@ -744,16 +747,17 @@ int lbm_adjoint_init(lbm_plan *p, float *const *lam_out_host, const double *cons
     return LBM_OK;
 }
 
-int lbm_plan_variant(const lbm_plan *p, int32_t variant_out[3])
+int lbm_plan_variant(const lbm_plan *p, int32_t variant_out[4])
 {
     if (!p || !variant_out) return fail(LBM_E_INVALID, "bad arguments");
     variant_out[0] = p->v.bs;
     variant_out[1] = p->v.cpt;
     variant_out[2] = p->v.nt;
+    variant_out[3] = p->v.xcd;
     return LBM_OK;
 }
 
-int lbm_plan_autotune(lbm_plan *p, hipStream_t s, int32_t variant_out[3])
+int lbm_plan_autotune(lbm_plan *p, hipStream_t s, int32_t variant_out[4])
 {
     int r = check_plan(p);
     if (r) return r;
@@ -761,9 +765,11 @@ int lbm_plan_autotune(lbm_plan *p, hipStream_t s, int32_t variant_out[3])
     const std::string key = tune_key(p);
     std::map<std::string, int> cache = read_tune_cache();
     auto it = cache.find(key);
-    Variant best{0, 0, 0};
-    auto decode = [](int code) { return Variant{code & 0xffff, (code >> 16) & 0xff, (code >> 24) & 0xff}; };
-    auto encode = [](const Variant &v) { return v.bs | (v.cpt << 16) | (v.nt << 24); };
+    Variant best{0, 0, 0, 0};
+    auto decode = [](int code) {
+        return Variant{code & 0xffff, (code >> 16) & 0xf, (code >> 20) & 0xf, (code >> 24) & 0xf};
+    };
+    auto encode = [](const Variant &v) { return v.bs | (v.cpt << 16) | (v.nt << 20) | (v.xcd << 24); };
     if (it != cache.end() && variant_ok(decode(it->second))) {
         best = decode(it->second);
     } else {
@@ -786,8 +792,9 @@ int lbm_plan_autotune(lbm_plan *p, hipStream_t s, int32_t variant_out[3])
         const Variant saved = p->v;
         for (int bs : {128, 256, 512})
             for (int cpt : {1, 2})
-                for (int nt : {0, 1}) {
-                    const Variant v{bs, cpt, nt};
+                for (int nt : {0, 1, 2, 3})
+                    for (int xcd : {0, 1}) {
+                    const Variant v{bs, cpt, nt, xcd};
                     p->v = v;
                     r = build_tiles(p);
                     if (r) break;

@@ -129,20 +129,27 @@ LBM_HD void cell_flags(const Box &b, const uint8_t *solid, int x, int y, int z, 
         return;
     }
     bool near = (x == b.nx - 1) || (z == b.nz - 1);
+    bool general = z == b.nz - 1;
     for (int i = 1; i < Q; ++i) {
         int sx = x - cx(i), sy = y - cy(i), sz = z - cz(i);
         bool wrapped = false;
         if (b.face[0] == FACE_PERIODIC && (sx < 0 || sx >= b.nx)) { sx = wrap1(sx, b.nx); wrapped = true; }
         if (b.face[2] == FACE_PERIODIC && (sy < 0 || sy >= b.ny)) { sy = wrap1(sy, b.ny); wrapped = true; }
         if (b.face[4] == FACE_PERIODIC && (sz < 0 || sz >= b.nz)) { sz = wrap1(sz, b.nz); wrapped = true; }
-        const bool inside = sx >= 0 && sx < b.nx && sy >= 0 && sy < b.ny && sz >= 0 && sz < b.nz;
+        const bool yz_out = sy < 0 || sy >= b.ny || sz < 0 || sz >= b.nz;
+        const bool inside = sx >= 0 && sx < b.nx && !yz_out;
         if (!inside || wrapped) near = true;
+        if (wrapped || yz_out) general = true;
         if (inside && solid[((int64_t)sz * b.ny + sy) * b.nx + sx]) {
             m |= 1u << i;
             near = true;
+            general = true;
         }
     }
     if (near) fl |= FL_NEAR;
+    if (near && general) fl |= FL_GENERAL;
+    if (x == 0) fl |= FL_XLO;
+    if (x == b.nx - 1) fl |= FL_XHI;
     if (x == 0 && b.face[0] == FACE_INLET) fl |= FL_INLET;
 }
 

@@ -51,7 +51,8 @@ class lbm_instance(ctypes.Structure):
 class lbm_plan_opts(ctypes.Structure):
     _fields_ = [("avg_begin", ctypes.c_int64), ("avg_end", ctypes.c_int64),
                 ("use_graph", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("cells_per_thread", ctypes.c_int32), ("nontemporal", ctypes.c_int32)]
+                ("cells_per_thread", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
+                ("xcd_order", ctypes.c_int32)]
 
 
 _lib = None
@@ -77,8 +78,8 @@ _SIGS = [
     ("lbm_plan_reset_qoi", ctypes.c_int, [_P, _P]),
     ("lbm_sync", ctypes.c_int, [_P, _P]),
     ("lbm_check_health", ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int32)]),
-    ("lbm_plan_variant", ctypes.c_int, [_P, ctypes.c_int32 * 3]),
-    ("lbm_plan_autotune", ctypes.c_int, [_P, _P, ctypes.c_int32 * 3]),
+    ("lbm_plan_variant", ctypes.c_int, [_P, ctypes.c_int32 * 4]),
+    ("lbm_plan_autotune", ctypes.c_int, [_P, _P, ctypes.c_int32 * 4]),
     ("lbm_collide_stream", ctypes.c_int, [_P, ctypes.c_int32, _P]),
     ("lbm_collide_stream_record", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P,
                                                  ctypes.c_int32, _P]),
@@ -179,11 +180,11 @@ def lbm_init_geometry(dom: lbm_domain, solid: np.ndarray, probes: np.ndarray, ge
 
 def lbm_plan_create(instances: Sequence[lbm_instance], avg_begin: int = 0, avg_end: int = 0,
                     use_graph: bool = False, block: int = 0, cells_per_thread: int = 0,
-                    nontemporal: int = 0):
+                    nontemporal: int = 0, xcd_order: int = 0):
     arr = (lbm_instance * len(instances))(*instances)
     o = lbm_plan_opts()
     o.avg_begin, o.avg_end, o.use_graph, o.block = avg_begin, avg_end, int(use_graph), block
-    o.cells_per_thread, o.nontemporal = cells_per_thread, nontemporal
+    o.cells_per_thread, o.nontemporal, o.xcd_order = cells_per_thread, nontemporal, xcd_order
     h = ctypes.c_void_p()
     _check(lib().lbm_plan_create(arr, len(instances), ctypes.byref(o), ctypes.byref(h)))
     return h
@@ -223,15 +224,15 @@ def lbm_check_health(plan, stream: int) -> int:
 
 
 def lbm_plan_variant(plan):
-    """(block, cells_per_thread, nontemporal) of a plan."""
-    v = (ctypes.c_int32 * 3)()
+    """(block, cells_per_thread, nontemporal, xcd_order) of a plan."""
+    v = (ctypes.c_int32 * 4)()
     _check(lib().lbm_plan_variant(plan, v))
     return tuple(v)
 
 
 def lbm_plan_autotune(plan, stream: int):
-    """Fastest (block, cells_per_thread, nontemporal) for the plan's batch."""
-    v = (ctypes.c_int32 * 3)()
+    """Fastest (block, cells_per_thread, nontemporal, xcd_order) for the plan's batch."""
+    v = (ctypes.c_int32 * 4)()
     _check(lib().lbm_plan_autotune(plan, stream, v))
     return tuple(v)
 

@@ -113,8 +113,9 @@ class Ensemble:
                 self.qsum.append(qsm)
                 self.psum.append(ps)
         self.instances = insts
-        bs, cpt, nt = tuple(variant) if variant is not None else (block, 0, 0)
-        self.plan = L.lbm_plan_create(insts, avg_begin, avg_end, use_graph, bs, cpt, nt)
+        v = tuple(variant) if variant is not None else (block, 0, 1, 0)
+        v = v + (0,) * (4 - len(v))
+        self.plan = L.lbm_plan_create(insts, avg_begin, avg_end, use_graph, *v)
         L.lbm_plan_reset_qoi(self.plan, stream_handle())
 
     def reset(self):

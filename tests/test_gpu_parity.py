@@ -235,7 +235,7 @@ def test_batched_uneven_matches_one_at_a_time():
             i += 1
 
 
-@pytest.mark.parametrize("variant", [(128, 1, 0), (512, 1, 1), (128, 2, 0), (256, 2, 1), (512, 2, 0)])
+@pytest.mark.parametrize("variant", [(128, 1, 0, 0), (512, 1, 1, 1), (128, 2, 2, 0), (256, 2, 3, 1), (512, 2, 0, 0)])
 def test_launch_shapes_and_graphs_bitwise(variant):
     """Every launch shape (threads per workgroup, cells per thread,
     non-temporal) and graph replay give the same populations bit for bit."""
@@ -243,7 +243,7 @@ def test_launch_shapes_and_graphs_bitwise(variant):
     solid = inputs.solid_mask(w)
     _, _, th = sc.collocation(w)
     outs = []
-    for kw in (dict(variant=(256, 1, 0), use_graph=False), dict(variant=variant, use_graph=True)):
+    for kw in (dict(variant=(256, 1, 0, 0), use_graph=False), dict(variant=variant, use_graph=True)):
         ens, _ = _ensemble(w, solid, th[:3], **kw)
         try:
             ens.advance(57)
