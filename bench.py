@@ -29,7 +29,11 @@ METRIC = "aggregate MLUPS (batched vs one-at-a-time) + %HBM roofline; adjoint/fo
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL_UPDATE = 152          # 19 FP32 populations read + written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_stream_urban_les.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2508_18202_amd", "csrc", "kernels.hip")
+# every source that shapes the step kernels' code: a change to any of them
+# invalidates the committed counter summary
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2508_18202_amd", *p) for p in
+               (("csrc", "kernels.hip"), ("csrc", "kernels.h"), ("csrc", "rules.h"), ("csrc", "d3q19.h"),
+                ("build.py",))]
 
 
 def parse():
@@ -54,8 +58,11 @@ def parse():
 
 
 def kernel_sha() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(launch_bytes_alg: float):
