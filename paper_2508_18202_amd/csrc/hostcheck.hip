@@ -68,14 +68,15 @@ void lbmhc_rules(int nx, int ny, int nz, const int *face, const uint8_t *solid, 
             }
 }
 
-// Returns 0 when all properties hold, otherwise a code; stats[0..5] =
+// Returns 0 when all properties hold, otherwise a code; stats[0..6] =
 // fluid links, links through a non-plain rule, values with two destinations,
-// shared slots, shared slots spanning two workgroups, slots written twice.
+// shared slots, shared slots spanning two workgroups, slots written twice,
+// fill writes of solid cells.
 int lbmhc_check(int nx, int ny, int nz, const int *face, const uint8_t *solid, int block, int64_t *stats)
 {
     Geo3 g;
     build(g, nx, ny, nz, face, solid);
-    for (int k = 0; k < 6; ++k) stats[k] = 0;
+    for (int k = 0; k < 7; ++k) stats[k] = 0;
     // 1. inverse property
     std::vector<int8_t> hit((size_t)Q * g.n, 0);
     for (int z = 0; z < nz; ++z)
@@ -145,6 +146,26 @@ int lbmhc_check(int nx, int ny, int nz, const int *face, const uint8_t *solid, i
                 }
             }
     if (stats[5]) return 9;
+    // fill writes of solid cells: into solid cells' slots only, one writer
+    // each, never touched by a fluid cell
+    std::unordered_map<int64_t, int> fills;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int64_t c = g.cell(x, y, z);
+                if (!(g.fl[c] & FL_SOLID)) continue;
+                for (int k = 1; k < Q; ++k) {
+                    if (!((g.m[c] >> k) & 1u)) continue;
+                    const int dx = x + cx(k), dy = y + cy(k), dz = z + cz(k);
+                    if (dx < 0 || dx >= nx || dy < 0 || dy >= ny || dz < 0 || dz >= nz) return 11;
+                    const int64_t dc = g.cell(dx, dy, dz);
+                    if (!(g.fl[dc] & FL_SOLID)) return 11;
+                    const int64_t s = slot(k, dc);
+                    if (touch.count(s)) return 12;
+                    if (fills[s]++) return 13;
+                    ++stats[6];
+                }
+            }
     for (auto &kv : touch) {
         const std::vector<int64_t> &v = kv.second;
         bool shared = false, cross = false;

@@ -354,7 +354,7 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
 
     uint32_t c[CPT];
     uint8_t fl[CPT];
-    bool fluid[CPT], near_wave[CPT], general_wave[CPT];
+    bool act[CPT], fluid[CPT], near_wave[CPT], general_wave[CPT];
     Preds pr[CPT];
     uint32_t sm[CPT];
     float U[CPT];
@@ -365,7 +365,18 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
     for (int j = 0; j < CPT; ++j) {
         const int32_t lc = base + j * BS;
         const bool active = lc < G.ncells;
+        act[j] = active;
         c[j] = active ? (uint32_t)lc : 0u;
+        // Even steps touch only the cell's own 19 slots.  The slots of a solid
+        // cell are never read or written by any other cell (every link into a
+        // solid cell resolves to a rule on the fluid side's own slots), so the
+        // even step swaps them like a fluid cell's, without collision: the
+        // loads do not wait for the flag byte and every wavefront writes whole
+        // cache lines instead of lines with holes at solid cells.
+        if (PARITY == 0 && active) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) g[j][i] = ldg<NT>(f + (size_t)i * qs, c[j]);
+        }
         fl[j] = active ? gp(G.flags)[c[j]] : (uint8_t)FL_SOLID;
         fluid[j] = !(fl[j] & FL_SOLID);
         // odd steps: wavefronts without boundary cells take the plain stencil;
@@ -383,6 +394,8 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
             pr[j] = preds_of(S, x, y, z);
             sm[j] = gp(G.smask)[c[j]];
             U[j] = (fl[j] & FL_INLET) ? inflow_speed(G, z) : 0.0f;
+        } else if (general_wave[j] && act[j]) {
+            sm[j] = gp(G.smask)[c[j]];   // solid cell: its fill links
         } else if (near_wave[j] && fluid[j]) {
             pr[j].xlo = fl[j] & FL_XLO;
             pr[j].xhi = fl[j] & FL_XHI;
@@ -391,11 +404,8 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
     }
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
-        if (!fluid[j]) continue;
-        if (PARITY == 0) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) g[j][i] = ldg<NT>(f + (size_t)i * qs, c[j]);
-        } else if (!near_wave[j]) {
+        if (!fluid[j] || PARITY == 0) continue;
+        if (!near_wave[j]) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) g[j][i] = ldg<NT>(f + (size_t)opp(i) * qs - off_of(G, i), c[j]);
         } else if (general_wave[j]) {
@@ -428,11 +438,24 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
     if (PARITY == 1) __syncthreads();
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
-        if (!fluid[j]) continue;
         if (PARITY == 0) {
+            if (!act[j]) continue;
 #pragma unroll
             for (int i = 0; i < Q; ++i) stg<NT>(f + (size_t)opp(i) * qs, c[j], g[j][i]);
-        } else if (!near_wave[j]) {
+            continue;
+        }
+        if (!fluid[j]) {
+            // solid cells of boundary wavefronts write zero into the slots of
+            // their solid-to-solid links, which only they own, so that the
+            // wavefront's stores cover whole lines around the solid body
+            if (general_wave[j] && act[j]) {
+#pragma unroll
+                for (int k = 1; k < Q; ++k)
+                    if ((sm[j] >> k) & 1u) stg<NT>(f + (size_t)k * qs + off_of(G, k), c[j], 0.0f);
+            }
+            continue;
+        }
+        if (!near_wave[j]) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) stg<NT>(f + (size_t)i * qs + off_of(G, i), c[j], g[j][i]);
         } else if (general_wave[j]) {

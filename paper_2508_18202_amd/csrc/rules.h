@@ -120,12 +120,24 @@ LBM_HD int push_dsts(const Box &b, int x, int y, int z, int k, uint32_t smask, L
 // (solid or wrapped neighbours, box faces, the outflow column and the sky
 // layer, which also write extra links); the kernels take the general rule
 // path only for those.
+// Per-cell flags and mask.  Fluid cell: bit i of m = the (wrapped) neighbour
+// x - c_i lies in the box and is solid.  Solid cell: bit k of m = the
+// neighbour x + c_k lies in the box without wrapping and is solid; the slot
+// (k, x + c_k) of such a link is touched by no fluid cell's rules (links into
+// solid cells resolve to the fluid side's own slots), so the odd step may
+// fill it to keep whole cache lines written.
 LBM_HD void cell_flags(const Box &b, const uint8_t *solid, int x, int y, int z, uint8_t &fl, uint32_t &m)
 {
     fl = 0;
     m = 0;
     if (solid[((int64_t)z * b.ny + y) * b.nx + x]) {
         fl = FL_SOLID;
+        for (int k = 1; k < Q; ++k) {
+            const int dx = x + cx(k), dy = y + cy(k), dz = z + cz(k);
+            if (dx >= 0 && dx < b.nx && dy >= 0 && dy < b.ny && dz >= 0 && dz < b.nz &&
+                solid[((int64_t)dz * b.ny + dy) * b.nx + dx])
+                m |= 1u << k;
+        }
         return;
     }
     bool near = (x == b.nx - 1) || (z == b.nz - 1);

@@ -131,7 +131,7 @@ def _random_solid(nx, ny, nz, faces, seed):
 
 def _check(nx, ny, nz, faces, solid, block):
     face = (ctypes.c_int * 6)(*[L.FACES[f] for f in faces])
-    stats = (ctypes.c_int64 * 6)()
+    stats = (ctypes.c_int64 * 7)()
     s = np.ascontiguousarray(solid, np.uint8)
     rc = hostcheck().lbmhc_check(nx, ny, nz, face, s.ctypes.data_as(ctypes.c_void_p), block, stats)
     return rc, list(stats)
@@ -144,7 +144,7 @@ def test_scatter_is_inverse_and_race_free(faces, block):
         solid = _random_solid(nx, ny, nz, faces, seed)
         rc, stats = _check(nx, ny, nz, faces, solid, block)
         assert rc == 0, (faces, nx, ny, nz, rc, stats)
-        assert stats[0] > 0
+        assert stats[0] > 0 and stats[6] > 0     # fill writes of solid cells exist and are exclusive
 
 
 @pytest.mark.parametrize("faces", FACE_SETS)

@@ -67,6 +67,10 @@ def test_step_by_step_populations(model):
                 done += 1
             g = ens.populations(0).cpu().numpy().astype(np.float64)
             ref = f - wl[:, None]
+            # the raw slots of solid cells (swapped by even steps, filled by
+            # odd steps) carry no state and stay at zero
+            raw = ens.f[0].view(19, cg.qs)[:, : cg.ncells].cpu().numpy()
+            assert not np.any(raw[:, ~fluid]), target
             err = np.abs(g[:, fluid] - ref[:, fluid]).max()
             scale = np.abs(ref[:, fluid]).max()
             assert err <= 1e-5 * scale + 1e-9, (target, err, scale)
