@@ -109,8 +109,8 @@ typedef struct lbm_plan_opts {
     int64_t avg_begin;         /* QoI window: states f^n with avg_begin < n <= avg_end */
     int64_t avg_end;           /* avg_end <= avg_begin disables accumulation */
     int32_t use_graph;         /* replay step pairs from captured HIP graphs where possible */
-    int32_t block;             /* threads per workgroup: 128, 256 or 512; 0 = default (256) */
-    int32_t cells_per_thread;  /* 1 or 2; 0 = default (1).  A workgroup owns block *
+    int32_t block;             /* threads per workgroup: 64, 128, 256 or 512; 0 = default (256) */
+    int32_t cells_per_thread;  /* 1, 2 or 4; 0 = default (1).  A workgroup owns block *
                                   cells_per_thread consecutive cells of one instance */
     int32_t nontemporal;       /* streaming (non-temporal) population loads and stores:
                                   bit 0 in even steps, bit 1 in odd steps */

@@ -322,14 +322,19 @@ __device__ __forceinline__ void collide(const Geo &G, float g[Q], const Macro &m
     }
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 partial sums (ux, uy, uz, |u|) of one cell: one 16-byte load and store
 __device__ __forceinline__ void accumulate_qoi(const Geo &G, uint32_t c, uint8_t fl, const Macro &m)
 {
     if (G.qpart) {
-        GLOBAL_AS float *p = gp(G.qpart) + 4 * (size_t)c;
-        p[0] += m.ux;
-        p[1] += m.uy;
-        p[2] += m.uz;
-        p[3] += sqrtf(m.ux * m.ux + m.uy * m.uy + m.uz * m.uz);
+        GLOBAL_AS f32x4 *p = (GLOBAL_AS f32x4 *)gp(G.qpart) + c;
+        f32x4 v = *p;
+        v.x += m.ux;
+        v.y += m.uy;
+        v.z += m.uz;
+        v.w += sqrtf(m.ux * m.ux + m.uy * m.uy + m.uz * m.uz);
+        *p = v;
     }
     if ((fl & FL_PROBE) && G.psum) {
         const int p = probe_index(G, (int32_t)c);
@@ -417,7 +422,12 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
     }
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
-        if (!fluid[j]) continue;
+        if (!fluid[j]) {
+            // the partial sums of solid cells stay zero; writing them keeps
+            // the wavefront's partial-sum stores on whole lines
+            if (a.accumulate && act[j] && G.qpart) ((GLOBAL_AS f32x4 *)gp(G.qpart))[c[j]] = f32x4{0.f, 0.f, 0.f, 0.f};
+            continue;
+        }
         const PairSums ps = pair_sums(g[j]);
         const Macro m = macro_of(g[j], ps);
         if (!(m.rho > 0.0f) || !isfinite(m.rho)) atomicOr(health + ii, 1);
@@ -899,8 +909,17 @@ static void step_n(const Variant &v, int model, int parity, const Geo *geo, cons
 
 bool variant_ok(const Variant &v)
 {
-    return (v.bs == 128 || v.bs == 256 || v.bs == 512) && (v.cpt == 1 || v.cpt == 2) && v.nt >= 0 && v.nt <= 3 &&
-           (v.xcd == 0 || v.xcd == 1);
+    return (v.bs == 64 || v.bs == 128 || v.bs == 256 || v.bs == 512) && (v.cpt == 1 || v.cpt == 2 || v.cpt == 4) &&
+           v.nt >= 0 && v.nt <= 3 && (v.xcd == 0 || v.xcd == 1);
+}
+
+template <int BS>
+static void step_c(const Variant &v, int model, int parity, const Geo *geo, const int32_t *ti, int32_t nt,
+                   const StepArgs &a, int32_t *h, hipStream_t s)
+{
+    if (v.cpt == 1) step_n<BS, 1>(v, model, parity, geo, ti, nt, a, h, s);
+    else if (v.cpt == 2) step_n<BS, 2>(v, model, parity, geo, ti, nt, a, h, s);
+    else step_n<BS, 4>(v, model, parity, geo, ti, nt, a, h, s);
 }
 
 int launch_step(const Variant &v, int model, int parity, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
@@ -910,16 +929,10 @@ int launch_step(const Variant &v, int model, int parity, const Geo *geo, const i
     if (!variant_ok(v)) return -1;
     StepArgs a = a0;
     a.xcd_remap = v.xcd;
-    if (v.bs == 128) {
-        if (v.cpt == 1) step_n<128, 1>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
-        else step_n<128, 2>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
-    } else if (v.bs == 256) {
-        if (v.cpt == 1) step_n<256, 1>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
-        else step_n<256, 2>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
-    } else {
-        if (v.cpt == 1) step_n<512, 1>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
-        else step_n<512, 2>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
-    }
+    if (v.bs == 64) step_c<64>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
+    else if (v.bs == 128) step_c<128>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
+    else if (v.bs == 256) step_c<256>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
+    else step_c<512>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
     return (int)hipGetLastError();
 }
 

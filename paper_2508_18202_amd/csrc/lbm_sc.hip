@@ -475,7 +475,7 @@ int lbm_plan_create(const lbm_instance *inst, int32_t n_inst, const lbm_plan_opt
     if (opts && opts->block) v.nt = opts->nontemporal;
     if (opts && opts->block) v.xcd = opts->xcd_order;
     if (!variant_ok(v))
-        return fail(LBM_E_INVALID, "launch shape: block must be 128, 256 or 512, cells per thread 1 or 2, "
+        return fail(LBM_E_INVALID, "launch shape: block must be 64, 128, 256 or 512, cells per thread 1, 2 or 4, "
                                    "non-temporal mask 0..3, XCD order 0 or 1");
     lbm_plan *p = new lbm_plan();
     p->n_inst = n_inst;
@@ -788,37 +788,54 @@ int lbm_plan_autotune(lbm_plan *p, hipStream_t s, int32_t variant_out[4])
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
-        float best_ms = 1e30f;
         const Variant saved = p->v;
-        for (int bs : {128, 256, 512})
-            for (int cpt : {1, 2})
+        // time `pairs` step pairs (after two untimed ones) of shape v
+        auto time_pairs = [&](const Variant &v, int pairs, float &ms) -> int {
+            p->v = v;
+            int rc = build_tiles(p);
+            if (rc) return rc;
+            StepArgs a{};
+            a.step = p->ramp_max + 2;
+            for (int w = 0; w < 2 + pairs; ++w) {
+                if (w == 2) HIPCHK(hipEventRecord(e0, s));
+                launch_step(v, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
+                launch_step(v, p->model, 1, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
+            }
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            return 0;
+        };
+        // coarse pass over every shape, then the six fastest re-timed three
+        // times each (interleaved) and ranked by their best time
+        std::vector<std::pair<float, Variant>> coarse;
+        for (int bs : {64, 128, 256, 512})
+            for (int cpt : {1, 2, 4})
                 for (int nt : {0, 1, 2, 3})
                     for (int xcd : {0, 1}) {
-                    const Variant v{bs, cpt, nt, xcd};
-                    p->v = v;
-                    r = build_tiles(p);
-                    if (r) break;
-                    StepArgs a{};
-                    a.step = p->ramp_max + 2;
-                    for (int w = 0; w < 2; ++w) {
-                        launch_step(v, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
-                        launch_step(v, p->model, 1, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
+                        const Variant v{bs, cpt, nt, xcd};
+                        float ms = 0.f;
+                        if (!r) r = time_pairs(v, 4, ms);
+                        coarse.push_back({ms, v});
                     }
-                    HIPCHK(hipEventRecord(e0, s));
-                    const int pairs = 6;
-                    for (int w = 0; w < pairs; ++w) {
-                        launch_step(v, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
-                        launch_step(v, p->model, 1, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
-                    }
-                    HIPCHK(hipEventRecord(e1, s));
-                    HIPCHK(hipEventSynchronize(e1));
-                    float ms = 0.f;
-                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                    if (ms < best_ms) {
-                        best_ms = ms;
-                        best = v;
-                    }
-                }
+        std::stable_sort(coarse.begin(), coarse.end(),
+                         [](const std::pair<float, Variant> &x, const std::pair<float, Variant> &y) {
+                             return x.first < y.first;
+                         });
+        const size_t n_fine = std::min<size_t>(6, coarse.size());
+        std::vector<float> fine(n_fine, 1e30f);
+        for (int rep = 0; rep < 3 && !r; ++rep)
+            for (size_t k = 0; k < n_fine && !r; ++k) {
+                float ms = 0.f;
+                r = time_pairs(coarse[k].second, 8, ms);
+                fine[k] = std::min(fine[k], ms);
+            }
+        float best_ms = 1e30f;
+        for (size_t k = 0; k < n_fine; ++k)
+            if (fine[k] < best_ms) {
+                best_ms = fine[k];
+                best = coarse[k].second;
+            }
         if (!best.bs) best = saved;
         off = 0;
         for (int i = 0; i < p->n_inst; ++i) {

@@ -138,7 +138,7 @@ def _check(nx, ny, nz, faces, solid, block):
 
 
 @pytest.mark.parametrize("faces", FACE_SETS)
-@pytest.mark.parametrize("block", [128, 256, 512, 1024])
+@pytest.mark.parametrize("block", [64, 128, 256, 512, 1024, 2048])
 def test_scatter_is_inverse_and_race_free(faces, block):
     for seed, (nx, ny, nz) in enumerate([(8, 6, 5), (12, 4, 7), (10, 9, 3), (16, 16, 4)]):
         solid = _random_solid(nx, ny, nz, faces, seed)
@@ -166,7 +166,7 @@ def test_relative_rules_equal_link_rules(faces):
                                inputs.scaled(inputs.adjoint_case(), 64, 32, 24)])
 def test_workload_geometries_race_free(w):
     solid = inputs.solid_mask(w)
-    for block in (128, 256, 512, 1024):
+    for block in (64, 128, 256, 512, 1024, 2048):
         rc, stats = _check(w.nx, w.ny, w.nz, w.faces, solid, block)
         assert rc == 0, (rc, stats)
     if w.faces[1] == "outlet":

@@ -239,7 +239,41 @@ def test_batched_uneven_matches_one_at_a_time():
             i += 1
 
 
-@pytest.mark.parametrize("variant", [(128, 1, 0, 0), (512, 1, 1, 1), (128, 2, 2, 0), (256, 2, 3, 1), (512, 2, 0, 0)])
+def test_autotune_restores_state(tmp_path, monkeypatch):
+    """The launch-shape autotuner times every shape on the live batch and then
+    restores populations and step counter: continuing afterwards gives the
+    same populations bit for bit as a plan that was never tuned; the second
+    call is served from the cache file."""
+    monkeypatch.setenv("LBMSC_TUNE_CACHE", str(tmp_path / "tune.json"))
+    w = inputs.scaled(inputs.urban_les(), 64, 32, 24, ramp=4)
+    solid = inputs.solid_mask(w)
+    _, _, th = sc.collocation(w)
+    outs = []
+    for tune in (False, True):
+        ens, _ = _ensemble(w, solid, th[:3], variant=(256, 1, 0, 0), use_graph=tune)
+        try:
+            ens.advance(6)
+            before = [ens.populations(i).cpu().numpy() for i in range(3)]
+            if tune:
+                v = L.lbm_plan_autotune(ens.plan, sc.stream_handle())
+                assert v[0] in (64, 128, 256, 512) and v[1] in (1, 2, 4) and 0 <= v[2] <= 3 and v[3] in (0, 1)
+                assert L.lbm_plan_variant(ens.plan) == v
+                assert L.lbm_plan_step(ens.plan) == 6
+                for a, b in zip(before, [ens.populations(i).cpu().numpy() for i in range(3)]):
+                    assert np.array_equal(a, b)
+                assert L.lbm_plan_autotune(ens.plan, sc.stream_handle()) == v     # cached
+                assert (tmp_path / "tune.json").exists()
+            ens.advance(31)
+            assert ens.health() < 0
+            outs.append([ens.populations(i).cpu().numpy() for i in range(3)])
+        finally:
+            ens.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("variant", [(128, 1, 0, 0), (512, 1, 1, 1), (128, 2, 2, 0), (256, 2, 3, 1), (512, 2, 0, 0),
+                                     (64, 1, 1, 0), (64, 4, 2, 0), (128, 4, 3, 1), (512, 4, 1, 0)])
 def test_launch_shapes_and_graphs_bitwise(variant):
     """Every launch shape (threads per workgroup, cells per thread,
     non-temporal) and graph replay give the same populations bit for bit."""
@@ -291,3 +325,7 @@ def test_rejections():
     good = sc.make_geometry(inputs.scaled(w, w.nx, w.ny, w.nz, tau0=0.5), inputs.solid_mask(w))
     with pytest.raises(L.LbmError):               # tau0 <= 1/2
         sc.Ensemble([good], [[(0.05, 0.0, 0.0)]])
+    ok = sc.make_geometry(w, inputs.solid_mask(w))
+    for v in ((96, 1, 0, 0), (1024, 1, 0, 0), (128, 3, 0, 0), (128, 1, 4, 0), (128, 1, 0, 2)):
+        with pytest.raises(L.LbmError):           # launch shapes outside the compiled set
+            sc.Ensemble([ok], [[(0.05, 0.0, 0.0)]], variant=v)
