@@ -238,7 +238,10 @@ int lbm_sc_moments(const float *q_dev, const double *w_host, int32_t n_nodes, in
  * [19][stride] floats; rec, the state recorded by
  * lbm_collide_stream_record for step n (kind 1 for BGK, 2 for Smagorinsky,
  * slot n % n_slots); pw, [n_probes] FP64 probe weights or NULL;
- * dJdtheta_dev, [n_inst][3] FP64 accumulated in place. */
+ * dJdtheta_dev, [n_inst][3] FP64 accumulated in place, in a fixed summation
+ * order (per-tile partials in a plan-owned buffer, then one sum per
+ * instance), so repeated sweeps give identical gradients.  lam^n of solid
+ * cells is written as zero. */
 int lbm_adjoint_step(lbm_plan *plan, int64_t step, float *const *lam_in_host,
                      float *const *lam_out_host, float *const *rec_host, int32_t record_kind,
                      int32_t n_slots, const double *const *pw_host, double *dJdtheta_dev,

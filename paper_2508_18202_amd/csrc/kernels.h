@@ -80,10 +80,14 @@ struct AdjArgs {
     int64_t rec_slot;          // slot index n % n_slots
     const double *const *pw;   // [n_inst] probe weights (entries may be null)
     double *grad;              // [n_inst][3]
+    double *part;              // [n_tiles][3] per-tile gradient partials of this step
 };
 
-int launch_adjoint(int tile_cells, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
+int launch_adjoint(const Variant &v, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
                    const AdjArgs &a, hipStream_t s);
+// grad[i][k] += sum over instance i's tiles of part[tile][k], in a fixed order
+int launch_grad_reduce(int tile_cells, const Geo *geo_h, int32_t n_inst, const Geo *geo, const double *part,
+                       double *grad, hipStream_t s);
 int launch_adjoint_init(int tcells, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
                         const AdjArgs &a, hipStream_t s);
 

@@ -707,64 +707,98 @@ __device__ __forceinline__ void adjoint_gather(const Geo &G, const Shape &S, con
         ...);
 }
 
-template <int MODEL>
-__device__ __forceinline__ void adjoint_cell(const Geo &G, int ii, int32_t first, const AdjArgs &a);
-
-// One adjoint step of the cells of one tile (tile_cells a multiple of BS).
-template <int BS, int MODEL>
+// One adjoint step of every instance, with the tiling of the step kernels:
+// a workgroup of BS threads owns BS * CPT consecutive cells of one instance.
+// Gather: wavefronts without boundary cells read lambda^{n+1} with the plain
+// shifted pattern; wavefronts whose boundary cells only sit in the inflow /
+// outflow columns evaluate the transposed x rules for all lanes; the others
+// the full transposed rules.  Then per cell the transposed collision and the
+// probe source; solid cells write zero (their lambda is never read) so the
+// stores cover whole lines.
+template <int BS, int CPT, int MODEL>
 __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
-                                                int32_t n_tiles, int32_t tile_cells, AdjArgs a)
+                                                int32_t n_tiles, int32_t xcd_remap, AdjArgs a)
 {
-    const int tile = xcd_tile();
+    const int tile = xcd_remap ? xcd_tile() : (int)blockIdx.x;
     if (tile >= n_tiles) return;
     const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
     const Geo &G = geo[ii];
-    for (int32_t sub = 0; sub < tile_cells; sub += BS) adjoint_cell<MODEL>(G, ii, (tile - G.tile0) * tile_cells + sub, a);
-}
-
-template <int MODEL>
-__device__ __forceinline__ void adjoint_cell(const Geo &G, int ii, int32_t first, const AdjArgs &a)
-{
-    const int32_t lc = first + (int32_t)threadIdx.x;
-    const bool active = lc < G.ncells;
-    const uint32_t c = active ? (uint32_t)lc : 0u;
-    const uint8_t fl = active ? gp(G.flags)[c] : (uint8_t)FL_SOLID;
-    const bool fluid = !(fl & FL_SOLID);
     const uint32_t qs = (uint32_t)G.qs;
+    const GLOBAL_AS float *__restrict__ lin = gp(a.lam_in[ii]);
+    GLOBAL_AS float *__restrict__ lout = gp(a.lam_out[ii]);
+    const int32_t base = (tile - G.tile0) * (BS * CPT) + (int32_t)threadIdx.x;
+    const float r = ramp_factor(G, a.step);
     double gr0 = 0.0, gr1 = 0.0, gr2 = 0.0;
-    if (fluid) {
-        const GLOBAL_AS float *__restrict__ lin = gp(a.lam_in[ii]);
-        GLOBAL_AS float *__restrict__ lout = gp(a.lam_out[ii]);
-        // mu = P^T lam^{n+1}: sum over the destination links of each post-collision value
-        float mu[Q];
-        if (!(fl & FL_NEAR)) {
+    bool inlet_lane = false;
+
+    uint32_t c[CPT];
+    uint8_t fl[CPT];
+    bool act[CPT], fluid[CPT], near_wave[CPT], general_wave[CPT];
+    float mu[CPT][Q];
+    f32x4 st[CPT];                 // (rho, ux, uy, uz) of a kind-1 record
+    float gs[CPT][Q];              // populations of a kind-2 record
+    const Shape S = shape_of(G);
+    // flags and records of all of the thread's cells first: loads retire in
+    // order, so no cell's classification may wait behind another's gather
 #pragma unroll
-            for (int k = 0; k < Q; ++k) mu[k] = ldg(lin + (size_t)k * qs + off_of(G, k), c);
-        } else {
+    for (int j = 0; j < CPT; ++j) {
+        const int32_t lc = base + j * BS;
+        act[j] = lc < G.ncells;
+        c[j] = act[j] ? (uint32_t)lc : 0u;
+        fl[j] = act[j] ? gp(G.flags)[c[j]] : (uint8_t)FL_SOLID;
+        if (a.record == 1 && act[j])
+            st[j] = ((const GLOBAL_AS f32x4 *)gp(a.rec[ii]))[(size_t)a.rec_slot * (size_t)G.ncells + c[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        fluid[j] = !(fl[j] & FL_SOLID);
+        if (fluid[j] && (fl[j] & FL_INLET)) inlet_lane = true;
+        near_wave[j] = __any(fluid[j] && (fl[j] & FL_NEAR));
+        general_wave[j] = __any(fluid[j] && (fl[j] & FL_GENERAL));
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        if (!fluid[j]) continue;
+        // mu = P^T lam^{n+1}: sum over the destination links of each post-collision value
+        if (!near_wave[j]) {
+#pragma unroll
+            for (int k = 0; k < Q; ++k) mu[j][k] = ldg(lin + (size_t)k * qs + off_of(G, k), c[j]);
+        } else if (general_wave[j]) {
             int x, y, z;
-            coords(G, c, x, y, z);
-            const Shape S = shape_of(G);
+            coords(G, c[j], x, y, z);
             const Preds pr = preds_of(S, x, y, z);
-            const uint32_t sm = gp(G.smask)[c];
-            const float r = ramp_factor(G, a.step);
-            adjoint_gather(G, S, pr, sm, c, z, r, lin, mu, gr0, gr1, gr2, Dirs{});
+            const uint32_t sm = gp(G.smask)[c[j]];
+            adjoint_gather(G, S, pr, sm, c[j], z, r, lin, mu[j], gr0, gr1, gr2, Dirs{});
+        } else {
+            const Preds px{(fl[j] & FL_XLO) != 0, (fl[j] & FL_XHI) != 0, false, false, false, false};
+            const int z = (fl[j] & FL_INLET) ? (int)fdiv(c[j], G.dxy) : 0;
+            adjoint_gather(G, S, px, 0u, c[j], z, r, lin, mu[j], gr0, gr1, gr2, Dirs{});
+        }
+        if (a.record != 1) {
+            const GLOBAL_AS float *rp = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)Q * G.qs;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) gs[j][i] = ldg(rp + (size_t)i * qs, c[j]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        if (!act[j]) continue;
+        if (!fluid[j]) {
+#pragma unroll
+            for (int k = 0; k < Q; ++k) stg(lout + (size_t)k * qs, c[j], 0.0f);
+            continue;
         }
         // state of step n
         float rho, ux, uy, uz, om;
         float A = 0.0f, P[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, qn = 0.0f, tau = G.tau0;
         if (a.record == 1) {
-            const float4 s =
-                reinterpret_cast<const float4 *>(a.rec[ii])[(size_t)a.rec_slot * (size_t)G.ncells + c];
-            rho = s.x;
-            ux = s.y;
-            uy = s.z;
-            uz = s.w;
+            rho = st[j].x;
+            ux = st[j].y;
+            uy = st[j].z;
+            uz = st[j].w;
             om = 1.0f / G.tau0;
         } else {
-            const GLOBAL_AS float *rp = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)Q * G.qs;
-            float g[Q];
-#pragma unroll
-            for (int i = 0; i < Q; ++i) g[i] = ldg(rp + (size_t)i * qs, c);
+            const float *g = gs[j];
             const PairSums ps = pair_sums(g);
             const Macro m = macro_of(g, ps);
             rho = m.rho;
@@ -777,7 +811,7 @@ __device__ __forceinline__ void adjoint_cell(const Geo &G, int ii, int32_t first
                 tau = tau_of<1>(G, ps, m);
                 const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
 #pragma unroll
-                for (int i = 0; i < Q; ++i) A += mu[i] * (g[i] - geq(i, m, usq15));
+                for (int i = 0; i < Q; ++i) A += mu[j][i] * (g[i] - geq(i, m, usq15));
             }
             om = 1.0f / tau;
         }
@@ -786,7 +820,7 @@ __device__ __forceinline__ void adjoint_cell(const Geo &G, int ii, int32_t first
         float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const float wm = wgt(i) * mu[i];
+            const float wm = wgt(i) * mu[j][i];
             m0 += wm;
             if (cx(i)) { m1x += cx(i) * wm; mxx += wm; }
             if (cy(i)) { m1y += cy(i) * wm; myy += wm; }
@@ -814,14 +848,14 @@ __device__ __forceinline__ void adjoint_cell(const Geo &G, int ii, int32_t first
         }
         // objective source at the probes: pw_p / count * (c_kx - u_x) / rho
         float src = 0.0f;
-        if (a.in_window && (fl & FL_PROBE) && a.pw[ii]) {
-            const int p = probe_index(G, (int32_t)c);
+        if (a.in_window && (fl[j] & FL_PROBE) && a.pw[ii]) {
+            const int p = probe_index(G, (int32_t)c[j]);
             if (p >= 0) src = (float)(a.pw[ii][p] * a.inv_count) / rho;
         }
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
             const float ex = cx(k) - ux, ey = cy(k) - uy, ez = cz(k) - uz;
-            float lk = (1.0f - om) * mu[k] + om * (srho + ex * tx + ey * ty + ez * tz);
+            float lk = (1.0f - om) * mu[j][k] + om * (srho + ex * tx + ey * ty + ez * tz);
             if (MODEL == 1) {
                 const float quad = ex * (P[0] * ex + P[3] * ey + P[4] * ez) +
                                    ey * (P[3] * ex + P[1] * ey + P[5] * ez) +
@@ -829,21 +863,58 @@ __device__ __forceinline__ void adjoint_cell(const Geo &G, int ii, int32_t first
                 lk += sa * quad + sb;
             }
             lk += src * ex;
-            stg(lout + (size_t)k * qs, c, lk);
+            stg(lout + (size_t)k * qs, c[j], lk);
         }
     }
-    // gradient: wave reduction, one FP64 atomic per wave that touched an inlet
-    const bool any_inlet = __any(fluid && (fl & FL_INLET));
-    if (any_inlet) {
+    // gradient: wavefront sums, then one partial per tile (the per-instance
+    // sums are formed afterwards in a fixed order, without atomics)
+    __shared__ double red[BS / 64][3];
+    const int wv = threadIdx.x >> 6;
+    if (__any(inlet_lane)) {
         gr0 = wave_sum(gr0);
         gr1 = wave_sum(gr1);
         gr2 = wave_sum(gr2);
-        if ((threadIdx.x & 63) == 0) {
-            atomicAdd(a.grad + 3 * ii + 0, gr0);
-            atomicAdd(a.grad + 3 * ii + 1, gr1);
-            atomicAdd(a.grad + 3 * ii + 2, gr2);
-        }
     }
+    if ((threadIdx.x & 63) == 0) {
+        red[wv][0] = gr0;
+        red[wv][1] = gr1;
+        red[wv][2] = gr2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < BS / 64; ++w) t += red[w][threadIdx.x];
+        a.part[3 * (size_t)tile + threadIdx.x] = t;
+    }
+}
+
+// grad[i][k] += sum of part[tile][k] over instance i's tiles: one workgroup
+// per instance, strided partial sums then a tree in shared memory.
+__global__ __launch_bounds__(256) void k_grad_reduce(const Geo *__restrict__ geo, int32_t tile_cells,
+                                                     const double *__restrict__ part, double *__restrict__ grad)
+{
+    const int ii = blockIdx.x;
+    const Geo &G = geo[ii];
+    const int32_t nt = (G.ncells + tile_cells - 1) / tile_cells;
+    __shared__ double sh[3][256];
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+    for (int32_t t = threadIdx.x; t < nt; t += 256) {
+        const double *q = part + 3 * (size_t)(G.tile0 + t);
+        t0 += q[0];
+        t1 += q[1];
+        t2 += q[2];
+    }
+    sh[0][threadIdx.x] = t0;
+    sh[1][threadIdx.x] = t1;
+    sh[2][threadIdx.x] = t2;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) grad[3 * ii + threadIdx.x] += sh[threadIdx.x][0];
 }
 
 // lam^N = dj_N / df^N from the (even, naturally stored) current state.
@@ -999,14 +1070,42 @@ int launch_moments(const float *q, const double *w, int32_t nq, int64_t n, doubl
     return (int)hipGetLastError();
 }
 
-int launch_adjoint(int tile_cells, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, const AdjArgs &a,
+template <int BS>
+static void adjoint_c(const Variant &v, const Geo *geo, const int32_t *ti, int32_t nt, const AdjArgs &a,
+                      hipStream_t s)
+{
+    const dim3 grid(grid_of(nt)), block(BS);
+    const int32_t xr = v.xcd;
+#define LBM_ADJ(C, M) hipLaunchKernelGGL((k_adjoint<BS, C, M>), grid, block, 0, s, geo, ti, nt, xr, a)
+    if (a.model == 0) {
+        if (v.cpt == 1) LBM_ADJ(1, 0);
+        else if (v.cpt == 2) LBM_ADJ(2, 0);
+        else LBM_ADJ(4, 0);
+    } else {
+        if (v.cpt == 1) LBM_ADJ(1, 1);
+        else if (v.cpt == 2) LBM_ADJ(2, 1);
+        else LBM_ADJ(4, 1);
+    }
+#undef LBM_ADJ
+}
+
+int launch_adjoint(const Variant &v, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, const AdjArgs &a,
                    hipStream_t s)
 {
-    constexpr int BS = 128;
-    if (tile_cells % BS) return -1;
-    const dim3 grid(grid_of(n_tiles)), block(BS);
-    if (a.model == 0) hipLaunchKernelGGL((k_adjoint<BS, 0>), grid, block, 0, s, geo, tile_inst, n_tiles, tile_cells, a);
-    else hipLaunchKernelGGL((k_adjoint<BS, 1>), grid, block, 0, s, geo, tile_inst, n_tiles, tile_cells, a);
+    if (n_tiles <= 0) return 0;
+    if (!variant_ok(v)) return -1;
+    if (v.bs == 64) adjoint_c<64>(v, geo, tile_inst, n_tiles, a, s);
+    else if (v.bs == 128) adjoint_c<128>(v, geo, tile_inst, n_tiles, a, s);
+    else if (v.bs == 256) adjoint_c<256>(v, geo, tile_inst, n_tiles, a, s);
+    else adjoint_c<512>(v, geo, tile_inst, n_tiles, a, s);
+    return (int)hipGetLastError();
+}
+
+int launch_grad_reduce(int tile_cells, const Geo *, int32_t n_inst, const Geo *geo, const double *part,
+                       double *grad, hipStream_t s)
+{
+    if (n_inst <= 0) return 0;
+    hipLaunchKernelGGL(k_grad_reduce, dim3(n_inst), dim3(256), 0, s, geo, tile_cells, part, grad);
     return (int)hipGetLastError();
 }
 

@@ -145,6 +145,8 @@ struct lbm_plan {
     hipGraphExec_t gexec = nullptr;
     int graph_pairs = 8;
     std::map<std::vector<uintptr_t>, void *> tables;
+    double *gpart_d = nullptr;   // per-tile adjoint gradient partials [gpart_tiles][3]
+    int32_t gpart_tiles = 0;
 };
 
 namespace {
@@ -556,6 +558,7 @@ void lbm_plan_destroy(lbm_plan *p)
     if (p->geo_d) (void)hipFree(p->geo_d);
     if (p->tiles_d) (void)hipFree(p->tiles_d);
     if (p->health_d) (void)hipFree(p->health_d);
+    if (p->gpart_d) (void)hipFree(p->gpart_d);
     delete p;
 }
 
@@ -721,7 +724,16 @@ int lbm_adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float
     a.in_window = (p->avg_begin < step && step <= p->avg_end) ? 1 : 0;
     a.inv_count = p->avg_end > p->avg_begin ? 1.0 / (double)(p->avg_end - p->avg_begin) : 0.0;
     a.grad = dJdtheta_dev;
-    if (launch_adjoint(p->v.tile(), p->geo_d, p->tiles_d, p->n_tiles, a, s))
+    if (p->gpart_tiles < p->n_tiles) {
+        if (p->gpart_d) HIPCHK(hipFree(p->gpart_d));
+        p->gpart_d = nullptr;
+        p->gpart_tiles = 0;
+        HIPCHK(hipMalloc(&p->gpart_d, sizeof(double) * 3 * (size_t)p->n_tiles));
+        p->gpart_tiles = p->n_tiles;
+    }
+    a.part = p->gpart_d;
+    if (launch_adjoint(p->v, p->geo_d, p->tiles_d, p->n_tiles, a, s) ||
+        launch_grad_reduce(p->v.tile(), p->geo_h.data(), p->n_inst, p->geo_d, p->gpart_d, dJdtheta_dev, s))
         return fail(LBM_E_HIP, "adjoint launch failed: %s", hipGetErrorString(hipGetLastError()));
     return LBM_OK;
 }
