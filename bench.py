@@ -100,6 +100,25 @@ def cpu_baseline(w, solid, theta, seconds: float):
                       f"{n} time steps past the inflow ramp, {dt:.1f} s"}
 
 
+def copy_ceiling(nbytes: int = 2 << 30, reps: int = 5) -> float:
+    """Read + write rate of a plain device-to-device copy on this GPU (GB/s)."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del src, dst
+    return 2 * nbytes / best / 1e9
+
+
 def adjoint_leg(variant, steps: int = 2000, avg_len: int = 500, ckpt: int = 100):
     """Forward sweep (with snapshots) vs checkpointed adjoint sweep of the
     adjoint workload: 13 Smolyak nodes of 128x64x48, BGK, probe-plane QoI."""
@@ -265,6 +284,8 @@ def main():
     launch_bytes = BYTES_PER_CELL_UPDATE * n_inst * n_fluid
     achieved = launch_bytes / avg_launch_s / 1e9 if launches else float("nan")
     traffic = load_traffic(launch_bytes)
+    copy_gbs = copy_ceiling()
+    props = torch.cuda.get_device_properties(0)
 
     out = {
         "metric": METRIC,
@@ -289,6 +310,9 @@ def main():
             "launch": {"block": variant[0], "cells_per_thread": variant[1], "nontemporal": variant[2],
                        "xcd_order": variant[3]},
             "parallelism": "batched instances, 1 GPU",
+            "device": {"name": props.name, "arch": getattr(props, "gcnArchName", ""),
+                       "compute_units": props.multi_processor_count,
+                       "hbm_gib": round(props.total_memory / 2 ** 30, 1)},
         },
         "roofline": {
             "bound": "hbm",
@@ -300,6 +324,9 @@ def main():
             "traffic": traffic,
             "avg_launch_us": round(avg_launch_s * 1e6, 2),
             "algorithmic_bytes_per_launch": launch_bytes,
+            "copy_ceiling": {"value": round(copy_gbs, 1), "unit": "GB/s",
+                             "kernel": "hipMemcpyAsync device to device, 2 GiB, best of 5",
+                             "frac": round(achieved / copy_gbs, 4)},
         },
         "kernel_mlups": round(n_inst * n_fluid / avg_launch_s / 1e6, 1),
     }

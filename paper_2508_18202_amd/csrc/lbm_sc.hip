@@ -732,7 +732,13 @@ int lbm_adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float
         p->gpart_tiles = p->n_tiles;
     }
     a.part = p->gpart_d;
-    if (launch_adjoint(p->v, p->geo_d, p->tiles_d, p->n_tiles, a, s) ||
+    // the adjoint keeps more live state per cell than a step: it runs one
+    // cell per thread over the same tiles (whole tile per workgroup, up to
+    // 512 threads), which holds more wavefronts per SIMD in flight
+    Variant va = p->v;
+    va.bs = std::min(p->v.tile(), 512);
+    va.cpt = p->v.tile() / va.bs;
+    if (launch_adjoint(va, p->geo_d, p->tiles_d, p->n_tiles, a, s) ||
         launch_grad_reduce(p->v.tile(), p->geo_h.data(), p->n_inst, p->geo_d, p->gpart_d, dJdtheta_dev, s))
         return fail(LBM_E_HIP, "adjoint launch failed: %s", hipGetErrorString(hipGetLastError()));
     return LBM_OK;
