@@ -114,8 +114,9 @@ typedef struct lbm_plan_opts {
                                   cells_per_thread consecutive cells of one instance */
     int32_t nontemporal;       /* streaming (non-temporal) population loads and stores:
                                   bit 0 in even steps, bit 1 in odd steps */
-    int32_t xcd_order;         /* 1: give each XCD a contiguous range of tiles.  The last
-                                  three fields apply only when block != 0; otherwise the
+    int32_t xcd_order;         /* order of the tiles over the 8 XCDs: 0 hardware round
+                                  robin, 1 a contiguous range per XCD.  The last three
+                                  fields apply only when block != 0; otherwise the
                                   default shape (256, 1, even steps non-temporal, 0) */
 } lbm_plan_opts;
 

@@ -180,6 +180,12 @@ int lbmhc_check(int nx, int ny, int nz, const int *face, const uint8_t *solid, i
     return 0;
 }
 
+// Tile order of a launch: out[p] = tile_order(p, grid, mode) for p < grid.
+void lbmhc_tile_order(int grid, int mode, int32_t *out)
+{
+    for (int p = 0; p < grid; ++p) out[p] = tile_order(p, grid, mode);
+}
+
 // Fast division: checks v / d against fdiv for the given values.
 int lbmhc_fastdiv(uint32_t d, const uint32_t *v, int64_t n)
 {

@@ -37,7 +37,7 @@ struct StepArgs {
     int64_t step;              // time index n of the state being collided
     int32_t accumulate;        // add this state's QoIs to the window sums
     int32_t record;            // 0 none, 1 (rho,u), 2 populations
-    int32_t xcd_remap;         // tiles in contiguous ranges per XCD (set from the variant)
+    int32_t xcd_remap;         // tile order over the XCDs (set from the variant, see tile_of)
     float *const *rec;         // device array [n_inst] of record buffer bases
     int64_t rec_slot;          // slot index n % n_slots
 };
@@ -49,7 +49,7 @@ struct Variant {
     int bs;
     int cpt;
     int nt;
-    int xcd;                   // 1: XCD-contiguous tile order
+    int xcd;                   // tile order: 0 hardware round robin, 1 contiguous per XCD
     int tile() const { return bs * cpt; }
 };
 

@@ -64,16 +64,10 @@ __device__ __forceinline__ void stg(GLOBAL_AS T *base, uint32_t idx, T v)
     else *p = v;
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs.  xcd_tile() gives
-// each XCD a contiguous range of tiles (neighbouring tiles then share one L2);
-// measured on the streaming step kernels, the plain round-robin order keeps
-// HBM busier, so the step kernels take the remap only as a tunable option.
-__device__ __forceinline__ int xcd_tile()
-{
-    const int G8 = gridDim.x >> 3;
-    const int p = blockIdx.x;
-    return (p & 7) * G8 + (p >> 3);
-}
+// Workgroups are dispatched round-robin over the 8 XCDs; tile_order() (see
+// rules.h) chooses which tile each block index takes.
+__device__ __forceinline__ int xcd_tile() { return tile_order((int)blockIdx.x, (int)gridDim.x, 1); }
+__device__ __forceinline__ int tile_of(int mode) { return tile_order((int)blockIdx.x, (int)gridDim.x, mode); }
 
 __device__ __forceinline__ float ramp_factor(const Geo &G, int64_t n)
 {
@@ -349,7 +343,7 @@ template <int BS, int CPT, bool NT, int MODEL, int PARITY>
 __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
                                              int32_t n_tiles, StepArgs a, int32_t *__restrict__ health)
 {
-    const int tile = a.xcd_remap ? xcd_tile() : (int)blockIdx.x;
+    const int tile = tile_of(a.xcd_remap);
     if (tile >= n_tiles) return;
     const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
     const Geo &G = geo[ii];
@@ -719,7 +713,7 @@ template <int BS, int CPT, int MODEL>
 __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
                                                 int32_t n_tiles, int32_t xcd_remap, AdjArgs a)
 {
-    const int tile = xcd_remap ? xcd_tile() : (int)blockIdx.x;
+    const int tile = tile_of(xcd_remap);
     if (tile >= n_tiles) return;
     const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
     const Geo &G = geo[ii];

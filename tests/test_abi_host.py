@@ -222,3 +222,15 @@ def test_kernel_lattice_matches_oracle():
     for i in range(19):
         zi = list(z)[i]
         assert (co[zi] == co[i] * np.array([1, 1, -1])).all()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_tile_orders_are_permutations(mode):
+    """Both XCD tile orders map the blocks of a launch grid (a multiple of 8)
+    one to one onto tiles."""
+    hostcheck().lbmhc_tile_order.restype = None
+    for n_tiles in (1, 7, 8, 9, 100, 1000, 1536, 8192, 19968):
+        grid = (n_tiles + 7) // 8 * 8
+        out = np.empty(grid, np.int32)
+        hostcheck().lbmhc_tile_order(grid, mode, out.ctypes.data_as(ctypes.c_void_p))
+        assert np.array_equal(np.sort(out), np.arange(grid)), (mode, n_tiles)

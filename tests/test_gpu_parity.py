@@ -326,6 +326,6 @@ def test_rejections():
     with pytest.raises(L.LbmError):               # tau0 <= 1/2
         sc.Ensemble([good], [[(0.05, 0.0, 0.0)]])
     ok = sc.make_geometry(w, inputs.solid_mask(w))
-    for v in ((96, 1, 0, 0), (1024, 1, 0, 0), (128, 3, 0, 0), (128, 1, 4, 0), (128, 1, 0, 2)):
+    for v in ((96, 1, 0, 0), (1024, 1, 0, 0), (128, 3, 0, 0), (128, 1, 4, 0), (128, 1, 0, 2), (128, 1, 0, -1)):
         with pytest.raises(L.LbmError):           # launch shapes outside the compiled set
             sc.Ensemble([ok], [[(0.05, 0.0, 0.0)]], variant=v)
