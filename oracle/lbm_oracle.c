@@ -15,6 +15,11 @@
  *   - effective relaxation time of Eq. (tauEff) with the Smagorinsky-Lilly
  *     eddy viscosity of Eq. (turbVisc), |S| evaluated from the local
  *     non-equilibrium stress;
+ *   - the regularised collision of Eq. (deterministicLBE) as printed: the
+ *     equilibrium expanded to third order and f^(1) = f - f^eq replaced by
+ *     its expansion to third order with the Hermite coefficients of
+ *     Eq. (hermiteCoeff), in the Hermite polynomials that are orthogonal on
+ *     D3Q19 (model M_RR3, with the Smagorinsky tau_eff);
  *   - bounce-back walls/ground, a local velocity (moving-wall bounce-back)
  *     inflow, a zero-gradient outflow and a free-slip sky (Sec. 2.2 boundary
  *     list), plus periodic faces;
@@ -32,7 +37,7 @@
 #define NQ 19
 
 enum { F_WALL = 0, F_INLET = 1, F_OUTLET = 2, F_FREESLIP = 3, F_PERIODIC = 4 };
-enum { M_BGK = 0, M_SMAG = 1 };
+enum { M_BGK = 0, M_SMAG = 1, M_RR3 = 2 };
 enum { IN_UNIFORM = 0, IN_LOGLAW = 1 };
 
 typedef struct {
@@ -141,10 +146,135 @@ static double neq_norm(const double *f, const double *feq, double pi[3][3])
     return sqrt(s);
 }
 
-/* Local collision of one fluid cell: f* = f - (1/tau_eff)(f - f_eq) [+ Guo force term]. */
+/* ---- Regularised third-order collision (Sec. 2.2, Eq. (deterministicLBE),
+ * Eq. (hermiteCoeff)).
+ *
+ * Basis: the Hermite polynomials in c_i up to third order that are mutually
+ * orthogonal on D3Q19 under sum_i w_i P(c_i) Q(c_i):
+ *   order 0: 1;  order 1: c_a;  order 2: H_aa = c_a^2 - cs2, H_ab = c_a c_b;
+ *   order 3: H_xxy +- H_yzz, H_xzz +- H_xyy, H_yyz +- H_xxz, with
+ *   H_aab = c_b (c_a^2 - cs2).  (H_aaa and H_xyz vanish on D3Q19, and the six
+ *   mixed third-order polynomials are orthogonal only in these sums and
+ *   differences.)
+ * Each basis polynomial P_k is paired with the Maxwellian's Hermite
+ * coefficient in the same combination, per unit density: A_k(u) = 1, u_a,
+ * u_a u_b, u_x^2 u_y +- u_y u_z^2, ...  With the norms
+ * N_k = sum_i w_i P_k(c_i)^2 of the velocity set:
+ *   f_eq_i   = w_i rho sum_k P_k(c_i) A_k(u) / N_k            (orders 0..3)
+ *   a1_k     = sum_i P_k(c_i) (f_i - f_eq_i)                    (orders 2, 3)
+ *   f1_reg_i = w_i sum_k P_k(c_i) a1_k / N_k                   (orders 2, 3)
+ *   f*_i     = f_eq_i + (1 - 1/tau_eff) f1_reg_i. */
+#define NB 16
+static int basis_order(int k) { return k == 0 ? 0 : (k < 4 ? 1 : (k < 10 ? 2 : 3)); }
+
+static double basis_poly(int k, const double *c)
+{
+    const double s = 1.0 / 3.0;
+    const double x = c[0], y = c[1], z = c[2];
+    const double hxxy = y * (x * x - s), hyzz = y * (z * z - s);
+    const double hxzz = x * (z * z - s), hxyy = x * (y * y - s);
+    const double hyyz = z * (y * y - s), hxxz = z * (x * x - s);
+    switch (k) {
+    case 0: return 1.0;
+    case 1: return x;
+    case 2: return y;
+    case 3: return z;
+    case 4: return x * x - s;
+    case 5: return y * y - s;
+    case 6: return z * z - s;
+    case 7: return x * y;
+    case 8: return x * z;
+    case 9: return y * z;
+    case 10: return hxxy + hyzz;
+    case 11: return hxxy - hyzz;
+    case 12: return hxzz + hxyy;
+    case 13: return hxzz - hxyy;
+    case 14: return hyyz + hxxz;
+    default: return hyyz - hxxz;
+    }
+}
+
+/* Maxwellian Hermite coefficient of P_k per unit density: the same
+ * combination of the monomials u_a u_b (u_c). */
+static double basis_coef(int k, const double *u)
+{
+    const double x = u[0], y = u[1], z = u[2];
+    switch (k) {
+    case 0: return 1.0;
+    case 1: return x;
+    case 2: return y;
+    case 3: return z;
+    case 4: return x * x;
+    case 5: return y * y;
+    case 6: return z * z;
+    case 7: return x * y;
+    case 8: return x * z;
+    case 9: return y * z;
+    case 10: return x * x * y + y * z * z;
+    case 11: return x * x * y - y * z * z;
+    case 12: return x * z * z + x * y * y;
+    case 13: return x * z * z - x * y * y;
+    case 14: return y * y * z + x * x * z;
+    default: return y * y * z - x * x * z;
+    }
+}
+
+/* P[k][i] = P_k(c_i) and N[k] = sum_i w_i P_k(c_i)^2. */
+void orc_rr3_basis(double *P, double *N)
+{
+    for (int k = 0; k < NB; ++k) {
+        N[k] = 0.0;
+        for (int i = 0; i < NQ; ++i) {
+            double c[3] = {C[i][0], C[i][1], C[i][2]};
+            P[k * NQ + i] = basis_poly(k, c);
+            N[k] += weight(i) * P[k * NQ + i] * P[k * NQ + i];
+        }
+    }
+}
+
+/* Third-order equilibrium in the D3Q19-orthogonal Hermite basis. */
+void orc_equilibrium3(double rho, const double *u, double *feq)
+{
+    double P[NB * NQ], N[NB];
+    orc_rr3_basis(P, N);
+    for (int i = 0; i < NQ; ++i) {
+        double s = 0.0;
+        for (int k = 0; k < NB; ++k) s += P[k * NQ + i] * basis_coef(k, u) / N[k];
+        feq[i] = weight(i) * rho * s;
+    }
+}
+
+static void collide_rr3(const orc_case *k, const double *f, double *fstar)
+{
+    double rho, u[3], feq[NQ], f1[NQ], pi[3][3], P[NB * NQ], N[NB];
+    moments(k, f, &rho, u);
+    orc_equilibrium3(rho, u, feq);
+    for (int i = 0; i < NQ; ++i) f1[i] = f[i] - feq[i];
+    const double tau = orc_tau_eff(k->tau0, k->cs, rho, neq_norm(f, feq, pi));
+    orc_rr3_basis(P, N);
+    double a1[NB];
+    for (int b = 0; b < NB; ++b) {
+        a1[b] = 0.0;
+        if (basis_order(b) < 2) continue;
+        for (int i = 0; i < NQ; ++i) a1[b] += P[b * NQ + i] * f1[i];
+    }
+    for (int i = 0; i < NQ; ++i) {
+        double r = 0.0;
+        for (int b = 0; b < NB; ++b)
+            if (basis_order(b) >= 2) r += P[b * NQ + i] * a1[b] / N[b];
+        fstar[i] = feq[i] + (1.0 - 1.0 / tau) * weight(i) * r;
+    }
+}
+
+/* Local collision of one fluid cell: f* = f - (1/tau_eff)(f - f_eq) [+ Guo force term];
+ * the regularised model goes through collide_rr3. */
 void orc_collide_cell(const orc_case *k, const double *f, double *fstar)
 {
     double rho, u[3], feq[NQ], pi[3][3];
+    if (k->model == M_RR3) {
+        collide_rr3(k, f, fstar);
+        return;
+    }
     moments(k, f, &rho, u);
     orc_equilibrium(rho, u, feq);
     double tau = k->tau0;

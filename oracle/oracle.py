@@ -39,7 +39,7 @@ _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 NQ = 19
 FACE_CODES = {"wall": 0, "inlet": 1, "outlet": 2, "freeslip": 3, "periodic": 4}
-MODEL_CODES = {"bgk": 0, "smagorinsky": 1}
+MODEL_CODES = {"bgk": 0, "smagorinsky": 1, "rr3": 2}
 INFLOW_CODES = {"uniform": 0, "loglaw": 1}
 
 
@@ -73,6 +73,8 @@ def lib():
         dp = P(ctypes.c_double)
         L.orc_lattice.argtypes = [P(ctypes.c_int), dp, P(ctypes.c_int)]
         L.orc_equilibrium.argtypes = [ctypes.c_double, dp, dp]
+        L.orc_equilibrium3.argtypes = [ctypes.c_double, dp, dp]
+        L.orc_rr3_basis.argtypes = [dp, dp]
         L.orc_tau_eff.argtypes = [ctypes.c_double] * 4
         L.orc_tau_eff.restype = ctypes.c_double
         L.orc_check_case.argtypes = [P(_Case)]
@@ -109,6 +111,24 @@ def equilibrium(rho: float, u: Sequence[float]) -> np.ndarray:
     out = np.zeros(NQ)
     lib().orc_equilibrium(rho, _dp(uu), _dp(out))
     return out
+
+
+def equilibrium3(rho: float, u: Sequence[float]) -> np.ndarray:
+    """Third-order equilibrium in the Hermite polynomials orthogonal on D3Q19
+    (Sec. 2.2, the equilibrium expanded to order three)."""
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(NQ)
+    lib().orc_equilibrium3(rho, _dp(uu), _dp(out))
+    return out
+
+
+def rr3_basis():
+    """(P [16, 19], N [16]): the D3Q19-orthogonal Hermite polynomials up to
+    third order at the velocities, and their norms sum_i w_i P_k(c_i)^2."""
+    P = np.zeros(16 * NQ)
+    N = np.zeros(16)
+    lib().orc_rr3_basis(_dp(P), _dp(N))
+    return P.reshape(16, NQ), N
 
 
 def tau_eff(tau0: float, cs: float, rho: float, q: float) -> float:
@@ -293,12 +313,16 @@ class Case:
         return out
 
     def collision_jacobian(self, f19) -> np.ndarray:
+        if self.c.model == MODEL_CODES["rr3"]:
+            raise NotImplementedError("the oracle adjoint covers the BGK and Smagorinsky collisions")
         f = np.ascontiguousarray(f19, dtype=np.float64)
         J = np.zeros(NQ * NQ)
         lib().orc_collision_jacobian(ctypes.byref(self.c), _dp(f), _dp(J))
         return J.reshape(NQ, NQ)
 
     def adjoint_step(self, n: int, f_n, lam_next):
+        if self.c.model == MODEL_CODES["rr3"]:
+            raise NotImplementedError("the oracle adjoint covers the BGK and Smagorinsky collisions")
         lam = np.empty_like(lam_next)
         g = np.zeros(3)
         lib().orc_adjoint_step(ctypes.byref(self.c), n, _dp(f_n), _dp(lam_next), _dp(lam), _dp(g))
