@@ -67,10 +67,16 @@ enum {
 enum { LBM_WALL = 0, LBM_INLET = 1, LBM_OUTLET = 2, LBM_FREESLIP = 3, LBM_PERIODIC = 4 };
 
 /* Collision models: BGK (Eq. deterministicLBE with an unprojected
- * non-equilibrium part) and BGK with the Smagorinsky-Lilly effective
- * relaxation time (Eqs. tauEff, turbVisc; |S| from the local non-equilibrium
- * stress). */
-enum { LBM_BGK = 0, LBM_SMAGORINSKY = 1 };
+ * non-equilibrium part); BGK with the Smagorinsky-Lilly effective relaxation
+ * time (Eqs. tauEff, turbVisc; |S| from the local non-equilibrium stress);
+ * and the regularised collision of Eq. (deterministicLBE) as printed, with
+ * the Smagorinsky tau_eff (cs = 0 gives tau0): equilibrium and
+ * non-equilibrium part expanded to third order (coefficients of
+ * Eq. hermiteCoeff) in the Hermite polynomials orthogonal on D3Q19, i.e. up
+ * to second order plus H_xxy +- H_yzz, H_xzz +- H_xyy, H_yyz +- H_xxz, each
+ * term divided by its norm on the velocity set.  The adjoint covers the first
+ * two models. */
+enum { LBM_BGK = 0, LBM_SMAGORINSKY = 1, LBM_RR3 = 2 };
 
 /* Inflow profiles (Sec. 3, log-law wind profile): theta = (speed, phi, z0).
  *   UNIFORM  u_in = speed (cos phi, sin phi, 0);
@@ -93,7 +99,7 @@ typedef struct lbm_instance {
     const void *geom_dev;    /* geometry buffer filled by lbm_init_geometry */
     int32_t n_probes;        /* probe count given to lbm_init_geometry */
     float *f_dev;            /* 19 * lbm_population_stride(dom) floats */
-    int32_t model;           /* LBM_BGK / LBM_SMAGORINSKY (uniform over a plan) */
+    int32_t model;           /* LBM_BGK / LBM_SMAGORINSKY / LBM_RR3 (uniform over a plan) */
     float tau0;              /* molecular relaxation time, > 1/2 */
     float cs;                /* Smagorinsky constant C_S */
     int32_t inflow;          /* LBM_INFLOW_* */

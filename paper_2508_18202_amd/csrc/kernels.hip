@@ -296,12 +296,91 @@ __device__ __forceinline__ float geq(int i, const Macro &m, float usq15)
     return wgt(i) * (m.drho + m.rho * (3.0f * cu + 4.5f * cu * cu - usq15));
 }
 
+// Third-order Hermite polynomials orthogonal on D3Q19 at velocity i, in the
+// order H_xxy + H_yzz, H_xxy - H_yzz, H_xzz + H_xyy, H_xzz - H_xyy,
+// H_yyz + H_xxz, H_yyz - H_xxz (H_aab = c_b (c_a^2 - 1/3)), and their inverse
+// norms on the velocity set: 1 / (2 cs^6) = 13.5 for the sums,
+// 1 / (6 cs^6) = 4.5 for the differences.  All fold to constants per
+// direction.
+__host__ __device__ constexpr float herm3(int k, int i)
+{
+    const float x = (float)cx(i), y = (float)cy(i), z = (float)cz(i), s = 1.0f / 3.0f;
+    const float hxxy = y * (x * x - s), hyzz = y * (z * z - s);
+    const float hxzz = x * (z * z - s), hxyy = x * (y * y - s);
+    const float hyyz = z * (y * y - s), hxxz = z * (x * x - s);
+    return k == 0 ? hxxy + hyzz : k == 1 ? hxxy - hyzz : k == 2 ? hxzz + hxyy
+         : k == 3 ? hxzz - hxyy : k == 4 ? hyyz + hxxz : hyyz - hxxz;
+}
+__host__ __device__ constexpr float herm3_inv_norm(int k) { return (k & 1) ? 4.5f : 13.5f; }
+
+// Regularised collision (Eq. deterministicLBE as printed), with the
+// Smagorinsky tau_eff:
+//   f* = f_eq3 + (1 - 1/tau) [w (H2 : Pi / (2 cs^4) + sum_k P_k a1_k / N_k)],
+// f_eq3 the equilibrium to third order and a1_k = sum_i P_k(c_i)(f_i - f_eq3_i)
+// for the six third-order polynomials P_k above.  The third-order terms are
+// odd in c, so per opposite pair they enter with opposite signs and only the
+// pair's antisymmetric part of f - f_eq3 projects onto them; they have no
+// second moment, so Pi and tau_eff are those of the second-order equilibrium.
+__device__ __forceinline__ void collide_rr3(const Geo &G, float g[Q], const Macro &m, const PairSums &p)
+{
+    float P[6];
+    neq_stress(p, m, P);
+    const float q = stress_norm(P);
+    const float tau = 0.5f * (G.tau0 + fast_sqrt(G.tau0 * G.tau0 + G.kcs * q * fast_rcp(m.rho)));
+    const float keep = 1.0f - fast_rcp(tau);
+    const float ux = m.ux, uy = m.uy, uz = m.uz;
+    const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
+    // Maxwellian coefficients of the six third-order polynomials (per unit density)
+    const float A[6] = {ux * ux * uy + uy * uz * uz, ux * ux * uy - uy * uz * uz,
+                        ux * uz * uz + ux * uy * uy, ux * uz * uz - ux * uy * uy,
+                        uy * uy * uz + ux * ux * uz, uy * uy * uz - ux * ux * uz};
+    const float trP = P[0] + P[1] + P[2];
+    float sym[9], asym[9], t3[9], a1[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int i = 2 * k + 1;
+        const float cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
+        sym[k] = wgt(i) * (m.drho + m.rho * (4.5f * cu * cu - usq15));
+        asym[k] = 3.0f * wgt(i) * m.rho * cu;
+        float t = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            if (herm3(j, i) != 0.0f) t += herm3(j, i) * herm3_inv_norm(j) * A[j];
+        t3[k] = wgt(i) * m.rho * t;
+        // (f - f_eq3)_i - (f - f_eq3)_opp(i)
+        const float D = p.d[k] - 2.0f * (asym[k] + t3[k]);
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            if (herm3(j, i) != 0.0f) a1[j] += herm3(j, i) * D;
+    }
+    g[0] = wgt(0) * (m.drho - m.rho * usq15) + keep * wgt(0) * (-1.5f * trP);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int i = 2 * k + 1;
+        const float X = (float)cx(i), Y = (float)cy(i), Z = (float)cz(i);
+        const float cpc = X * X * P[0] + Y * Y * P[1] + Z * Z * P[2] +
+                          2.0f * (X * Y * P[3] + X * Z * P[4] + Y * Z * P[5]);
+        const float r2 = wgt(i) * (4.5f * cpc - 1.5f * trP);
+        float r3 = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            if (herm3(j, i) != 0.0f) r3 += herm3(j, i) * herm3_inv_norm(j) * a1[j];
+        r3 *= wgt(i);
+        g[i] = sym[k] + asym[k] + t3[k] + keep * (r2 + r3);
+        g[i + 1] = sym[k] - asym[k] - t3[k] + keep * (r2 - r3);
+    }
+}
+
 // f* = f - omega (f - f_eq), the equilibrium of each opposite pair split into
 // its symmetric part w (drho + rho (4.5 (c.u)^2 - 1.5 u.u)) and its
 // antisymmetric part 3 w rho c.u.
 template <int MODEL>
 __device__ __forceinline__ void collide(const Geo &G, float g[Q], const Macro &m, const PairSums &p)
 {
+    if constexpr (MODEL == 2) {
+        collide_rr3(G, g, m, p);
+        return;
+    }
     const float om = fast_rcp(tau_of<MODEL>(G, p, m));
     const float usq15 = 1.5f * (m.ux * m.ux + m.uy * m.uy + m.uz * m.uz);
     g[0] = g[0] - om * (g[0] - wgt(0) * (m.drho - m.rho * usq15));
@@ -960,7 +1039,8 @@ static void step_m(int model, int parity, const Geo *geo, const int32_t *ti, int
                    int32_t *h, hipStream_t s)
 {
     if (model == 0) step_v<BS, CPT, NT, 0>(parity, geo, ti, nt, a, h, s);
-    else step_v<BS, CPT, NT, 1>(parity, geo, ti, nt, a, h, s);
+    else if (model == 1) step_v<BS, CPT, NT, 1>(parity, geo, ti, nt, a, h, s);
+    else step_v<BS, CPT, NT, 2>(parity, geo, ti, nt, a, h, s);
 }
 
 // v.nt is a mask: bit 0 non-temporal accesses in even steps, bit 1 in odd steps

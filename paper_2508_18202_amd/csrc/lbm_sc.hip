@@ -495,7 +495,8 @@ int lbm_plan_create(const lbm_instance *inst, int32_t n_inst, const lbm_plan_opt
         r = check_domain(&in.dom);
         if (!r && (!in.geom_dev || !in.f_dev)) r = fail(LBM_E_INVALID, "instance %d: NULL buffer", i);
         if (!r && in.model != p->model) r = fail(LBM_E_INVALID, "instance %d: all instances of a plan share one model", i);
-        if (!r && in.model != LBM_BGK && in.model != LBM_SMAGORINSKY) r = fail(LBM_E_INVALID, "instance %d: unknown model", i);
+        if (!r && in.model != LBM_BGK && in.model != LBM_SMAGORINSKY && in.model != LBM_RR3)
+            r = fail(LBM_E_INVALID, "instance %d: unknown model", i);
         if (!r && !(in.tau0 > 0.5f)) r = fail(LBM_E_INVALID, "instance %d: tau0 must exceed 1/2 (got %g)", i, in.tau0);
         if (!r && !(in.cs >= 0.0f)) r = fail(LBM_E_INVALID, "instance %d: negative Smagorinsky constant", i);
         if (!r && in.inflow != LBM_INFLOW_UNIFORM && in.inflow != LBM_INFLOW_LOGLAW)
@@ -529,7 +530,7 @@ int lbm_plan_create(const lbm_instance *inst, int32_t n_inst, const lbm_plan_opt
         g.dx = make_fastdiv((uint32_t)in.dom.nx);
         g.dxy = make_fastdiv((uint32_t)(in.dom.nx * in.dom.ny));
         g.tau0 = in.tau0;
-        g.kcs = in.model == LBM_SMAGORINSKY ? (float)(18.0 * std::sqrt(2.0) * in.cs * in.cs) : 0.0f;
+        g.kcs = in.model != LBM_BGK ? (float)(18.0 * std::sqrt(2.0) * in.cs * in.cs) : 0.0f;
         g.ramp = in.ramp;
         set_theta(g, in);
         p->ramp_max = std::max(p->ramp_max, in.ramp);
@@ -706,6 +707,7 @@ int lbm_adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float
     if (!lam_in_host || !lam_out_host || !rec_host || !pw_host || !dJdtheta_dev || n_slots < 1 || step < 0)
         return fail(LBM_E_INVALID, "bad adjoint arguments");
     if (kind != 1 && kind != 2) return fail(LBM_E_INVALID, "record kind must be 1 or 2");
+    if (p->model == LBM_RR3) return fail(LBM_E_UNSUPPORTED, "the adjoint covers the BGK and Smagorinsky models");
     if (p->model == LBM_SMAGORINSKY && kind != 2)
         return fail(LBM_E_INVALID, "the Smagorinsky adjoint needs recorded populations (kind 2)");
     for (int i = 0; i < p->n_inst; ++i)
@@ -749,6 +751,7 @@ int lbm_adjoint_init(lbm_plan *p, float *const *lam_out_host, const double *cons
     int r = check_plan(p);
     if (r) return r;
     if (!lam_out_host || !pw_host) return fail(LBM_E_INVALID, "bad adjoint arguments");
+    if (p->model == LBM_RR3) return fail(LBM_E_UNSUPPORTED, "the adjoint covers the BGK and Smagorinsky models");
     if (p->step & 1) return fail(LBM_E_INVALID, "the adjoint starts from an even step");
     for (int i = 0; i < p->n_inst; ++i)
         if (!lam_out_host[i]) return fail(LBM_E_INVALID, "instance %d: NULL adjoint buffer", i);

@@ -20,8 +20,8 @@ LIB_PATH = os.path.join(_HERE, "liblbmsc.so")
 LBM_OK, LBM_E_INVALID, LBM_E_HIP, LBM_E_UNSTABLE, LBM_E_UNSUPPORTED = 0, -1, -2, -3, -4
 WALL, INLET, OUTLET, FREESLIP, PERIODIC = 0, 1, 2, 3, 4
 FACES = {"wall": WALL, "inlet": INLET, "outlet": OUTLET, "freeslip": FREESLIP, "periodic": PERIODIC}
-BGK, SMAGORINSKY = 0, 1
-MODELS = {"bgk": BGK, "smagorinsky": SMAGORINSKY}
+BGK, SMAGORINSKY, RR3 = 0, 1, 2
+MODELS = {"bgk": BGK, "smagorinsky": SMAGORINSKY, "rr3": RR3}
 INFLOW_UNIFORM, INFLOW_LOGLAW = 0, 1
 INFLOWS = {"uniform": INFLOW_UNIFORM, "loglaw": INFLOW_LOGLAW}
 QUAD_GAUSS_LEGENDRE, QUAD_SMOLYAK_CC = 0, 1

@@ -112,3 +112,22 @@ def test_autograd_wrapper_matches_direct_adjoint():
         assert torch.equal(run.backward([wts, wts]).cpu(), gd)
     finally:
         ens.close()
+
+
+def test_adjoint_rejects_the_regularised_model():
+    """The adjoint kernels cover BGK and Smagorinsky; a plan of the
+    regularised model is refused with LBM_E_UNSUPPORTED before any launch."""
+    from paper_2508_18202_amd import lbmsc as L
+    w, solid = _small("rr3", "loglaw")
+    probes = _plane_probes(w, solid)
+    cg = sc.make_geometry(w, solid, probes)
+    ens = sc.Ensemble([cg], [[(0.012, 0.0, 0.5)]], avg_begin=10, avg_end=20, use_graph=False)
+    try:
+        run = CheckpointedAdjoint(ens, 20, 10)
+        run.forward()
+        pw = torch.full((len(probes),), 1.0 / len(probes), dtype=torch.float64, device="cuda")
+        with pytest.raises(L.LbmError) as e:
+            run.backward([pw])
+        assert e.value.code == L.LBM_E_UNSUPPORTED
+    finally:
+        ens.close()

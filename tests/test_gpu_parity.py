@@ -42,7 +42,7 @@ def _ensemble(w, solid, thetas, probes=None, **kw):
     return sc.Ensemble([cg], [thetas], **kw), cg
 
 
-@pytest.mark.parametrize("model", ["bgk", "smagorinsky"])
+@pytest.mark.parametrize("model", ["bgk", "smagorinsky", "rr3"])
 def test_step_by_step_populations(model):
     """Every step of a small case with all boundary kinds: populations after
     1, 2, 3, 4 and 9 steps (both storage parities) against the oracle."""
@@ -312,6 +312,55 @@ def test_unstable_instance_is_isolated():
     finally:
         ens.close()
         ref.close()
+
+
+def test_rr3_urban_short_horizon():
+    """The regularised third-order collision with the Smagorinsky tau_eff on
+    the urban recipe (64x32x24, 13 Smolyak nodes, log-law inflow), 200 steps,
+    time averages over the last 50, against the oracle: fields and moments."""
+    w = inputs.scaled(inputs.urban_les(steps=200, avg_len=50), 64, 32, 24, ramp=40, model="rr3")
+    solid = inputs.solid_mask(w)
+    _say("rr3 urban short: GPU")
+    r = sc.run_sc(w, solid)
+    ens = r["ensemble"]
+    try:
+        q = r["q"].cpu().numpy()
+        fluid = r["geometry"].fluid
+        x, a = orc.collocation(w)
+        qo = []
+        for j, xi in enumerate(x):
+            th = orc.node_params(w, xi)
+            res = orc.run(oracle_case(w, solid, th), w.steps, avg_start=w.avg_start)
+            qo.append(res["avg"])
+            errs = per_channel_rel(q[j], res["avg"], fluid)
+            assert max(errs) < FIELD_TOL, (j, errs)
+        eo, vo = orc.moments(np.stack(qo), a)
+        mean = r["mean"].cpu().numpy().T
+        var = r["var"].cpu().numpy().T
+        for k in range(4):
+            assert rel_l2(mean[k], eo[k], fluid) < MOMENT_TOL
+            assert rel_l2(np.sqrt(np.maximum(var[k], 0)), np.sqrt(np.maximum(vo[k], 0)), fluid) < MOMENT_TOL
+    finally:
+        ens.close()
+
+
+@pytest.mark.parametrize("variant", [(128, 2, 1, 0), (64, 4, 3, 1), (512, 1, 2, 0)])
+def test_rr3_launch_shapes_bitwise(variant):
+    """The regularised collision gives the same populations bit for bit in
+    every launch shape and under graph replay."""
+    w = inputs.scaled(inputs.urban_les(), 64, 32, 24, ramp=4, model="rr3")
+    solid = inputs.solid_mask(w)
+    _, _, th = sc.collocation(w)
+    outs = []
+    for kw in (dict(variant=(256, 1, 0, 0), use_graph=False), dict(variant=variant, use_graph=True)):
+        ens, _ = _ensemble(w, solid, th[:2], **kw)
+        try:
+            ens.advance(33)
+            outs.append([ens.populations(i).cpu().numpy() for i in range(2)])
+        finally:
+            ens.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
 
 
 def test_rejections():
