@@ -32,8 +32,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_stream_urban_les.
 # every source that shapes the step kernels' code: a change to any of them
 # invalidates the committed counter summary
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2508_18202_amd", *p) for p in
-               (("csrc", "kernels.hip"), ("csrc", "kernels.h"), ("csrc", "rules.h"), ("csrc", "d3q19.h"),
-                ("build.py",))]
+               (("csrc", "device.h"), ("csrc", "steps.hip"), ("csrc", "kernels.h"), ("csrc", "rules.h"),
+                ("csrc", "d3q19.h"), ("build.py",))]
 
 
 def parse():

@@ -12,6 +12,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -44,15 +45,35 @@ def _run(cmd):
     subprocess.check_call(cmd)
 
 
+# translation units of liblbmsc.so: (source, extra flags, object).  The step
+# kernels of the three collision models and the adjoint kernels are separate
+# units so that their many template instantiations compile in parallel.
+UNITS = [("steps.hip", ["-DLBM_STEP_MODEL=0"], "steps_m0.o"),
+         ("steps.hip", ["-DLBM_STEP_MODEL=1"], "steps_m1.o"),
+         ("steps.hip", ["-DLBM_STEP_MODEL=2"], "steps_m2.o"),
+         ("adjoint.hip", [], "adjoint.o"),
+         ("kernels.hip", [], "kernels.o"),
+         ("lbm_sc.hip", [], "lbm_sc.o"),
+         ("quadrature.cpp", [], "quadrature.o")]
+BUILD_DIR = os.path.join(PKG, "_build")
+
+
 def build(verbose: bool = True) -> None:
     hipcc = _hipcc()
-    srcs = [os.path.join(CSRC, f) for f in ("kernels.hip", "lbm_sc.hip", "quadrature.cpp")]
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    inc = [f"-I{INCLUDE}", f"-I{CSRC}"]
+    jobs = [[hipcc, *HIP_FLAGS, *extra, *inc, "-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD_DIR, obj)]
+            for src, extra, obj in UNITS]
+    tmp_hc = HOSTCHECK + ".tmp"
+    jobs.append([hipcc, *HIP_FLAGS, "-shared", f"-I{CSRC}", os.path.join(CSRC, "hostcheck.hip"), "-o", tmp_hc])
+    workers = max(1, min(len(jobs), os.cpu_count() or 4, 8))
+    with ThreadPoolExecutor(workers) as pool:
+        for f in [pool.submit(_run, j) for j in jobs]:
+            f.result()
     tmp = LIB + ".tmp"
-    _run([hipcc, *HIP_FLAGS, "-shared", f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-o", tmp])
+    _run([hipcc, *HIP_FLAGS, "-shared", *[os.path.join(BUILD_DIR, o) for _, _, o in UNITS], "-o", tmp])
     os.replace(tmp, LIB)
-    tmp = HOSTCHECK + ".tmp"
-    _run([hipcc, *HIP_FLAGS, "-shared", f"-I{CSRC}", os.path.join(CSRC, "hostcheck.hip"), "-o", tmp])
-    os.replace(tmp, HOSTCHECK)
+    os.replace(tmp_hc, HOSTCHECK)
 
 
 if __name__ == "__main__":

@@ -1,0 +1,41 @@
+// adjoint.hip -- launches of the adjoint step kernels (BGK and Smagorinsky,
+// every launch shape); the kernels themselves are in device.h.
+#include "device.h"
+
+namespace lbmsc {
+
+namespace {
+
+template <int BS>
+void adjoint_c(const Variant &v, const Geo *geo, const int32_t *ti, int32_t nt, const AdjArgs &a, hipStream_t s)
+{
+    const dim3 grid(grid_of(nt)), block(BS);
+    const int32_t xr = v.xcd;
+#define LBM_ADJ(C, M) hipLaunchKernelGGL((k_adjoint<BS, C, M>), grid, block, 0, s, geo, ti, nt, xr, a)
+    if (a.model == 0) {
+        if (v.cpt == 1) LBM_ADJ(1, 0);
+        else if (v.cpt == 2) LBM_ADJ(2, 0);
+        else LBM_ADJ(4, 0);
+    } else {
+        if (v.cpt == 1) LBM_ADJ(1, 1);
+        else if (v.cpt == 2) LBM_ADJ(2, 1);
+        else LBM_ADJ(4, 1);
+    }
+#undef LBM_ADJ
+}
+
+}  // namespace
+
+int launch_adjoint(const Variant &v, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, const AdjArgs &a,
+                   hipStream_t s)
+{
+    if (n_tiles <= 0) return 0;
+    if (!variant_ok(v)) return -1;
+    if (v.bs == 64) adjoint_c<64>(v, geo, tile_inst, n_tiles, a, s);
+    else if (v.bs == 128) adjoint_c<128>(v, geo, tile_inst, n_tiles, a, s);
+    else if (v.bs == 256) adjoint_c<256>(v, geo, tile_inst, n_tiles, a, s);
+    else adjoint_c<512>(v, geo, tile_inst, n_tiles, a, s);
+    return (int)hipGetLastError();
+}
+
+}  // namespace lbmsc

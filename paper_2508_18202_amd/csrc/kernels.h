@@ -54,6 +54,20 @@ struct Variant {
 };
 
 bool variant_ok(const Variant &v);
+// step-kernel launches of one collision model (0 BGK, 1 Smagorinsky,
+// 2 regularised), each compiled in its own translation unit
+template <int MODEL>
+int launch_step_model(const Variant &v, int parity, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
+                      const StepArgs &a, int32_t *health, hipStream_t s);
+template <>
+int launch_step_model<0>(const Variant &, int, const Geo *, const int32_t *, int32_t, const StepArgs &, int32_t *,
+                         hipStream_t);
+template <>
+int launch_step_model<1>(const Variant &, int, const Geo *, const int32_t *, int32_t, const StepArgs &, int32_t *,
+                         hipStream_t);
+template <>
+int launch_step_model<2>(const Variant &, int, const Geo *, const int32_t *, int32_t, const StepArgs &, int32_t *,
+                         hipStream_t);
 int launch_step(const Variant &v, int model, int parity, const Geo *geo, const int32_t *tile_inst,
                 int32_t n_tiles, const StepArgs &a, int32_t *health, hipStream_t s);
 int launch_init_geometry(const Box &b, const uint8_t *solid, uint8_t *flags, uint32_t *smask,

@@ -1,554 +1,11 @@
-// kernels.hip -- gfx950 kernels of the SC-LBM hot path.
-//
-// In-place AA streaming on one FP32 population array per instance (values
-// f_i - w_i):
-//   even step n (state stored naturally: slot i of cell x holds f_i^n(x))
-//     each cell reads its own 19 slots, collides, and writes f*_i into its own
-//     slot opp(i);
-//   odd step n (slots hold the swapped post-collision values of step n-1)
-//     each cell gathers f_i^n(x) through the link rules of rules.h, collides,
-//     and scatters f*_i(x) to every destination link of the next state, which
-//     is then stored naturally again.
-// Both steps move 19 floats in and 19 floats out per fluid cell.  In the odd
-// step the outflow column reads values that its upstream neighbour in the
-// same x-row overwrites, so each workgroup finishes all gathers before any
-// scatter (one barrier); a workgroup is a run of consecutive cells of one
-// instance, which never separates cells nx-2 and nx-1 of a row when nx is even.
-//
-// Collision (Sec. 2.2, Eq. deterministicLBE with an unprojected
-// non-equilibrium part): f* = f - omega (f - f_eq), second-order
-// equilibrium; Smagorinsky omega = 1 / tau_eff with
-// tau_eff = (tau0 + sqrt(tau0^2 + 18 sqrt(2) Cs^2 Q / rho)) / 2,
-// Q = |Pi_neq| (Eqs. tauEff, turbVisc with |S| from the local
-// non-equilibrium stress).
-#include <utility>
-
-#include "kernels.h"
+// kernels.hip -- gfx950 kernels other than the step and adjoint kernels
+// (captures, QoI flushes and averages, field read-out, geometry, moments,
+// adjoint initialisation and gradient reduction) and the launch dispatch.
+#include "device.h"
 
 namespace lbmsc {
 
 namespace {
-
-constexpr float KAPPA_INV = 1.0f / 0.41f;
-
-// Pointers taken from the instance table are generic; casting them to the
-// global address space lets the compiler emit global (not flat) memory
-// instructions with a scalar base and 32-bit lane offsets.
-#define GLOBAL_AS __attribute__((address_space(1)))
-template <class T>
-__device__ __forceinline__ GLOBAL_AS T *gp(T *p)
-{
-    return (GLOBAL_AS T *)p;
-}
-template <class T>
-__device__ __forceinline__ const GLOBAL_AS T *gp(const T *p)
-{
-    return (const GLOBAL_AS T *)p;
-}
-
-// Element idx of a uniform base through a 32-bit byte offset, so that the
-// access uses a scalar base address plus one 32-bit lane offset.  NT marks
-// streaming (non-temporal) accesses.
-template <bool NT = false, class T>
-__device__ __forceinline__ T ldg(const GLOBAL_AS T *base, uint32_t idx)
-{
-    const GLOBAL_AS T *p = (const GLOBAL_AS T *)((const GLOBAL_AS char *)base + idx * (uint32_t)sizeof(T));
-    if constexpr (NT) return __builtin_nontemporal_load(p);
-    else return *p;
-}
-template <bool NT = false, class T>
-__device__ __forceinline__ void stg(GLOBAL_AS T *base, uint32_t idx, T v)
-{
-    GLOBAL_AS T *p = (GLOBAL_AS T *)((GLOBAL_AS char *)base + idx * (uint32_t)sizeof(T));
-    if constexpr (NT) __builtin_nontemporal_store(v, p);
-    else *p = v;
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs; tile_order() (see
-// rules.h) chooses which tile each block index takes.
-__device__ __forceinline__ int xcd_tile() { return tile_order((int)blockIdx.x, (int)gridDim.x, 1); }
-__device__ __forceinline__ int tile_of(int mode) { return tile_order((int)blockIdx.x, (int)gridDim.x, mode); }
-
-__device__ __forceinline__ float ramp_factor(const Geo &G, int64_t n)
-{
-    if (G.ramp <= 0 || n >= G.ramp) return 1.0f;
-    return 0.5f * (1.0f - cosf(3.14159265358979323846f * (float)n / (float)G.ramp));
-}
-
-__device__ __forceinline__ float inflow_speed(const Geo &G, int z)
-{
-    if (G.inflow == 0) return G.speed;
-    return G.speed * KAPPA_INV * logf(((float)z + 0.5f) / G.z0);
-}
-
-// 6 w_i c_i . u_in, the moving-wall momentum of link i.
-__device__ __forceinline__ float inlet_term(int i, float U, const Geo &G, float r)
-{
-    return 6.0f * wgt(i) * U * r * ((float)cx(i) * G.cphi + (float)cy(i) * G.sphi);
-}
-
-__device__ __forceinline__ int probe_index(const Geo &G, int32_t c)
-{
-    int lo = 0, hi = G.n_probes - 1;
-    while (lo <= hi) {
-        int mid = (lo + hi) >> 1;
-        int v = gp(G.probes)[mid];
-        if (v == c) return mid;
-        if (v < c) lo = mid + 1; else hi = mid - 1;
-    }
-    return -1;
-}
-
-__device__ __forceinline__ void coords(const Geo &G, uint32_t c, int &x, int &y, int &z)
-{
-    const uint32_t zz = fdiv(c, G.dxy);
-    const uint32_t rem = c - zz * (uint32_t)(G.box.nx * G.box.ny);
-    const uint32_t yy = fdiv(rem, G.dx);
-    x = (int)(rem - yy * (uint32_t)G.box.nx);
-    y = (int)yy;
-    z = (int)zz;
-}
-
-__device__ __forceinline__ uint32_t cell_of(const Geo &G, const Link &l)
-{
-    return ((uint32_t)l.z * (uint32_t)G.box.ny + (uint32_t)l.y) * (uint32_t)G.box.nx + (uint32_t)l.x;
-}
-
-__device__ __forceinline__ int32_t off_of(const Geo &G, int i)
-{
-    return cx(i) + cy(i) * G.offy + cz(i) * G.offz;
-}
-
-__device__ __forceinline__ Shape shape_of(const Geo &G)
-{
-    Shape S;
-    S.nx = G.box.nx;
-    S.ny = G.box.ny;
-    S.nz = G.box.nz;
-    S.offy = G.offy;
-    S.offz = G.offz;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) S.face[k] = G.box.face[k];
-    return S;
-}
-
-// Boundary-aware gather of all 19 populations f^n(x) from the swapped
-// post-collision values of step n-1, one compile-time direction at a time.
-template <bool NT = false, int... Is>
-__device__ __forceinline__ void gather_all(const Geo &G, const Shape &S, const Preds &p, uint32_t sm, uint32_t c,
-                                           float U, float r, float g[Q], std::integer_sequence<int, Is...>)
-{
-    const GLOBAL_AS float *__restrict__ f = gp(G.f);
-    const uint32_t qs = (uint32_t)G.qs;
-    (
-        [&] {
-            const RelLink l = gather_rel<Is>(S, p, sm);
-            const float v = ldg<NT>(f, (uint32_t)l.slot * qs + (uint32_t)((int32_t)c + l.delta));
-            g[Is] = l.inlet ? v + inlet_term(Is, U, G, r) : v;
-        }(),
-        ...);
-}
-
-// Boundary-aware scatter of the post-collision values to every destination
-// link of the next (naturally stored) state.
-template <bool NT = false, int... Ks>
-__device__ __forceinline__ void scatter_all(const Geo &G, const Shape &S, const Preds &p, uint32_t sm, uint32_t c,
-                                            float U, float r, const float g[Q], std::integer_sequence<int, Ks...>)
-{
-    GLOBAL_AS float *__restrict__ f = gp(G.f);
-    const uint32_t qs = (uint32_t)G.qs;
-    (
-        [&] {
-            RelLink a, e;
-            scatter_rel<Ks>(S, p, sm, a, e);
-            if (a.valid) {
-                const float v = a.inlet ? g[Ks] + inlet_term(opp(Ks), U, G, r) : g[Ks];
-                stg<NT>(f, (uint32_t)a.slot * qs + (uint32_t)((int32_t)c + a.delta), v);
-            }
-            if (e.valid) stg<NT>(f, (uint32_t)e.slot * qs + (uint32_t)((int32_t)c + e.delta), g[Ks]);
-        }(),
-        ...);
-}
-
-using Dirs = std::make_integer_sequence<int, Q>;
-
-// Populations f^n(x) of a fluid cell in the current storage state.
-// parity 0: natural slots; parity 1: gathered from the swapped
-// post-collision values of step n-1 (inlet momentum uses r(n-1)).
-template <int PARITY>
-__device__ __forceinline__ void load_state(const Geo &G, uint32_t c, uint8_t fl, int x, int y, int z,
-                                           int64_t n, float g[Q])
-{
-    const GLOBAL_AS float *__restrict__ f = gp(G.f);
-    const uint32_t qs = (uint32_t)G.qs;
-    if (PARITY == 0) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) g[i] = ldg(f + (size_t)i * qs, c);
-    } else if (!(fl & FL_NEAR)) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) g[i] = ldg(f + (size_t)opp(i) * qs - off_of(G, i), c);
-    } else {
-        const Shape S = shape_of(G);
-        const Preds p = preds_of(S, x, y, z);
-        const uint32_t sm = gp(G.smask)[c];
-        const float U = (fl & FL_INLET) ? inflow_speed(G, z) : 0.0f;
-        gather_all(G, S, p, sm, c, U, ramp_factor(G, n - 1), g, Dirs{});
-    }
-}
-
-struct Macro {
-    float drho, rho, ux, uy, uz;
-};
-
-// Opposite directions come in pairs (2k+1, 2k+2), k = 0..8: their sums carry
-// the even moments (density, stress), their differences the odd ones
-// (momentum), which halves the additions of the moment sums.
-struct PairSums {
-    float s[9], d[9];
-};
-
-__device__ __forceinline__ PairSums pair_sums(const float g[Q])
-{
-    PairSums p;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        p.s[k] = g[2 * k + 1] + g[2 * k + 2];
-        p.d[k] = g[2 * k + 1] - g[2 * k + 2];
-    }
-    return p;
-}
-
-__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-
-__device__ __forceinline__ Macro macro_of(const float g[Q], const PairSums &p)
-{
-    Macro m;
-    float d = g[0], jx = 0.f, jy = 0.f, jz = 0.f;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const int i = 2 * k + 1;
-        d += p.s[k];
-        if (cx(i)) jx += cx(i) * p.d[k];
-        if (cy(i)) jy += cy(i) * p.d[k];
-        if (cz(i)) jz += cz(i) * p.d[k];
-    }
-    m.drho = d;
-    m.rho = 1.0f + d;
-    const float inv = fast_rcp(m.rho);
-    m.ux = jx * inv;
-    m.uy = jy * inv;
-    m.uz = jz * inv;
-    return m;
-}
-
-__device__ __forceinline__ Macro macro_of(const float g[Q]) { return macro_of(g, pair_sums(g)); }
-
-// Non-equilibrium stress Pi = sum c c (f - f_eq) from the shifted populations:
-// sum c c g - (drho/3) I - rho u u.  Order: xx, yy, zz, xy, xz, yz.
-__device__ __forceinline__ void neq_stress(const PairSums &p, const Macro &m, float P[6])
-{
-    float xx = 0.f, yy = 0.f, zz = 0.f, xy = 0.f, xz = 0.f, yz = 0.f;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const int i = 2 * k + 1;
-        if (cx(i)) xx += p.s[k];
-        if (cy(i)) yy += p.s[k];
-        if (cz(i)) zz += p.s[k];
-        if (cx(i) && cy(i)) xy += cx(i) * cy(i) * p.s[k];
-        if (cx(i) && cz(i)) xz += cx(i) * cz(i) * p.s[k];
-        if (cy(i) && cz(i)) yz += cy(i) * cz(i) * p.s[k];
-    }
-    const float d3 = m.drho * (1.0f / 3.0f);
-    P[0] = xx - d3 - m.rho * m.ux * m.ux;
-    P[1] = yy - d3 - m.rho * m.uy * m.uy;
-    P[2] = zz - d3 - m.rho * m.uz * m.uz;
-    P[3] = xy - m.rho * m.ux * m.uy;
-    P[4] = xz - m.rho * m.ux * m.uz;
-    P[5] = yz - m.rho * m.uy * m.uz;
-}
-
-__device__ __forceinline__ void neq_stress(const float g[Q], const Macro &m, float P[6])
-{
-    neq_stress(pair_sums(g), m, P);
-}
-
-__device__ __forceinline__ float stress_norm(const float P[6])
-{
-    return fast_sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2] +
-                     2.0f * (P[3] * P[3] + P[4] * P[4] + P[5] * P[5]));
-}
-
-template <int MODEL>
-__device__ __forceinline__ float tau_of(const Geo &G, const PairSums &p, const Macro &m)
-{
-    if (MODEL == 0) return G.tau0;
-    float P[6];
-    neq_stress(p, m, P);
-    const float q = stress_norm(P);
-    return 0.5f * (G.tau0 + fast_sqrt(G.tau0 * G.tau0 + G.kcs * q * fast_rcp(m.rho)));
-}
-
-// shifted equilibrium f_eq - w
-__device__ __forceinline__ float geq(int i, const Macro &m, float usq15)
-{
-    const float cu = cx(i) * m.ux + cy(i) * m.uy + cz(i) * m.uz;
-    return wgt(i) * (m.drho + m.rho * (3.0f * cu + 4.5f * cu * cu - usq15));
-}
-
-// Third-order Hermite polynomials orthogonal on D3Q19 at velocity i, in the
-// order H_xxy + H_yzz, H_xxy - H_yzz, H_xzz + H_xyy, H_xzz - H_xyy,
-// H_yyz + H_xxz, H_yyz - H_xxz (H_aab = c_b (c_a^2 - 1/3)), and their inverse
-// norms on the velocity set: 1 / (2 cs^6) = 13.5 for the sums,
-// 1 / (6 cs^6) = 4.5 for the differences.  All fold to constants per
-// direction.
-__host__ __device__ constexpr float herm3(int k, int i)
-{
-    const float x = (float)cx(i), y = (float)cy(i), z = (float)cz(i), s = 1.0f / 3.0f;
-    const float hxxy = y * (x * x - s), hyzz = y * (z * z - s);
-    const float hxzz = x * (z * z - s), hxyy = x * (y * y - s);
-    const float hyyz = z * (y * y - s), hxxz = z * (x * x - s);
-    return k == 0 ? hxxy + hyzz : k == 1 ? hxxy - hyzz : k == 2 ? hxzz + hxyy
-         : k == 3 ? hxzz - hxyy : k == 4 ? hyyz + hxxz : hyyz - hxxz;
-}
-__host__ __device__ constexpr float herm3_inv_norm(int k) { return (k & 1) ? 4.5f : 13.5f; }
-
-// Regularised collision (Eq. deterministicLBE as printed), with the
-// Smagorinsky tau_eff:
-//   f* = f_eq3 + (1 - 1/tau) [w (H2 : Pi / (2 cs^4) + sum_k P_k a1_k / N_k)],
-// f_eq3 the equilibrium to third order and a1_k = sum_i P_k(c_i)(f_i - f_eq3_i)
-// for the six third-order polynomials P_k above.  The third-order terms are
-// odd in c, so per opposite pair they enter with opposite signs and only the
-// pair's antisymmetric part of f - f_eq3 projects onto them; they have no
-// second moment, so Pi and tau_eff are those of the second-order equilibrium.
-__device__ __forceinline__ void collide_rr3(const Geo &G, float g[Q], const Macro &m, const PairSums &p)
-{
-    float P[6];
-    neq_stress(p, m, P);
-    const float q = stress_norm(P);
-    const float tau = 0.5f * (G.tau0 + fast_sqrt(G.tau0 * G.tau0 + G.kcs * q * fast_rcp(m.rho)));
-    const float keep = 1.0f - fast_rcp(tau);
-    const float ux = m.ux, uy = m.uy, uz = m.uz;
-    const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
-    // Maxwellian coefficients of the six third-order polynomials (per unit density)
-    const float A[6] = {ux * ux * uy + uy * uz * uz, ux * ux * uy - uy * uz * uz,
-                        ux * uz * uz + ux * uy * uy, ux * uz * uz - ux * uy * uy,
-                        uy * uy * uz + ux * ux * uz, uy * uy * uz - ux * ux * uz};
-    const float trP = P[0] + P[1] + P[2];
-    float sym[9], asym[9], t3[9], a1[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const int i = 2 * k + 1;
-        const float cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
-        sym[k] = wgt(i) * (m.drho + m.rho * (4.5f * cu * cu - usq15));
-        asym[k] = 3.0f * wgt(i) * m.rho * cu;
-        float t = 0.0f;
-#pragma unroll
-        for (int j = 0; j < 6; ++j)
-            if (herm3(j, i) != 0.0f) t += herm3(j, i) * herm3_inv_norm(j) * A[j];
-        t3[k] = wgt(i) * m.rho * t;
-        // (f - f_eq3)_i - (f - f_eq3)_opp(i)
-        const float D = p.d[k] - 2.0f * (asym[k] + t3[k]);
-#pragma unroll
-        for (int j = 0; j < 6; ++j)
-            if (herm3(j, i) != 0.0f) a1[j] += herm3(j, i) * D;
-    }
-    g[0] = wgt(0) * (m.drho - m.rho * usq15) + keep * wgt(0) * (-1.5f * trP);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const int i = 2 * k + 1;
-        const float X = (float)cx(i), Y = (float)cy(i), Z = (float)cz(i);
-        const float cpc = X * X * P[0] + Y * Y * P[1] + Z * Z * P[2] +
-                          2.0f * (X * Y * P[3] + X * Z * P[4] + Y * Z * P[5]);
-        const float r2 = wgt(i) * (4.5f * cpc - 1.5f * trP);
-        float r3 = 0.0f;
-#pragma unroll
-        for (int j = 0; j < 6; ++j)
-            if (herm3(j, i) != 0.0f) r3 += herm3(j, i) * herm3_inv_norm(j) * a1[j];
-        r3 *= wgt(i);
-        g[i] = sym[k] + asym[k] + t3[k] + keep * (r2 + r3);
-        g[i + 1] = sym[k] - asym[k] - t3[k] + keep * (r2 - r3);
-    }
-}
-
-// f* = f - omega (f - f_eq), the equilibrium of each opposite pair split into
-// its symmetric part w (drho + rho (4.5 (c.u)^2 - 1.5 u.u)) and its
-// antisymmetric part 3 w rho c.u.
-template <int MODEL>
-__device__ __forceinline__ void collide(const Geo &G, float g[Q], const Macro &m, const PairSums &p)
-{
-    if constexpr (MODEL == 2) {
-        collide_rr3(G, g, m, p);
-        return;
-    }
-    const float om = fast_rcp(tau_of<MODEL>(G, p, m));
-    const float usq15 = 1.5f * (m.ux * m.ux + m.uy * m.uy + m.uz * m.uz);
-    g[0] = g[0] - om * (g[0] - wgt(0) * (m.drho - m.rho * usq15));
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const int i = 2 * k + 1;
-        const float cu = cx(i) * m.ux + cy(i) * m.uy + cz(i) * m.uz;
-        const float sym = wgt(i) * (m.drho + m.rho * (4.5f * cu * cu - usq15));
-        const float asym = 3.0f * wgt(i) * m.rho * cu;
-        g[i] = g[i] - om * (g[i] - (sym + asym));
-        g[i + 1] = g[i + 1] - om * (g[i + 1] - (sym - asym));
-    }
-}
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-// FP32 partial sums (ux, uy, uz, |u|) of one cell: one 16-byte load and store
-__device__ __forceinline__ void accumulate_qoi(const Geo &G, uint32_t c, uint8_t fl, const Macro &m)
-{
-    if (G.qpart) {
-        GLOBAL_AS f32x4 *p = (GLOBAL_AS f32x4 *)gp(G.qpart) + c;
-        f32x4 v = *p;
-        v.x += m.ux;
-        v.y += m.uy;
-        v.z += m.uz;
-        v.w += sqrtf(m.ux * m.ux + m.uy * m.uy + m.uz * m.uz);
-        *p = v;
-    }
-    if ((fl & FL_PROBE) && G.psum) {
-        const int p = probe_index(G, (int32_t)c);
-        if (p >= 0) gp(G.psum)[p] += (double)m.ux;
-    }
-}
-
-// One time step of every instance.  A workgroup of BS threads owns a tile of
-// BS * CPT consecutive cells of one instance; thread t handles cells
-// t, t + BS, ... so every load and store instruction stays coalesced.
-template <int BS, int CPT, bool NT, int MODEL, int PARITY>
-__global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
-                                             int32_t n_tiles, StepArgs a, int32_t *__restrict__ health)
-{
-    const int tile = tile_of(a.xcd_remap);
-    if (tile >= n_tiles) return;
-    const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
-    const Geo &G = geo[ii];
-    GLOBAL_AS float *__restrict__ f = gp(G.f);
-    const uint32_t qs = (uint32_t)G.qs;
-    const int32_t base = (tile - G.tile0) * (BS * CPT) + (int32_t)threadIdx.x;
-
-    uint32_t c[CPT];
-    uint8_t fl[CPT];
-    bool act[CPT], fluid[CPT], near_wave[CPT], general_wave[CPT];
-    Preds pr[CPT];
-    uint32_t sm[CPT];
-    float U[CPT];
-    float g[CPT][Q];
-    Shape S;
-    if (PARITY == 1) S = shape_of(G);
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        const int32_t lc = base + j * BS;
-        const bool active = lc < G.ncells;
-        act[j] = active;
-        c[j] = active ? (uint32_t)lc : 0u;
-        // Even steps touch only the cell's own 19 slots.  The slots of a solid
-        // cell are never read or written by any other cell (every link into a
-        // solid cell resolves to a rule on the fluid side's own slots), so the
-        // even step swaps them like a fluid cell's, without collision: the
-        // loads do not wait for the flag byte and every wavefront writes whole
-        // cache lines instead of lines with holes at solid cells.
-        if (PARITY == 0 && active) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) g[j][i] = ldg<NT>(f + (size_t)i * qs, c[j]);
-        }
-        fl[j] = active ? gp(G.flags)[c[j]] : (uint8_t)FL_SOLID;
-        fluid[j] = !(fl[j] & FL_SOLID);
-        // odd steps: wavefronts without boundary cells take the plain stencil;
-        // wavefronts whose boundary cells only sit in the inflow/outflow
-        // columns evaluate the x rules for all lanes; the others evaluate the
-        // full rules for all lanes
-        near_wave[j] = PARITY == 1 && __any(fluid[j] && (fl[j] & FL_NEAR));
-        general_wave[j] = PARITY == 1 && __any(fluid[j] && (fl[j] & FL_GENERAL));
-        pr[j] = Preds{false, false, false, false, false, false};
-        sm[j] = 0;
-        U[j] = 0.0f;
-        if (general_wave[j] && fluid[j]) {
-            int x, y, z;
-            coords(G, c[j], x, y, z);
-            pr[j] = preds_of(S, x, y, z);
-            sm[j] = gp(G.smask)[c[j]];
-            U[j] = (fl[j] & FL_INLET) ? inflow_speed(G, z) : 0.0f;
-        } else if (general_wave[j] && act[j]) {
-            sm[j] = gp(G.smask)[c[j]];   // solid cell: its fill links
-        } else if (near_wave[j] && fluid[j]) {
-            pr[j].xlo = fl[j] & FL_XLO;
-            pr[j].xhi = fl[j] & FL_XHI;
-            if (fl[j] & FL_INLET) U[j] = inflow_speed(G, (int)fdiv(c[j], G.dxy));
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        if (!fluid[j] || PARITY == 0) continue;
-        if (!near_wave[j]) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) g[j][i] = ldg<NT>(f + (size_t)opp(i) * qs - off_of(G, i), c[j]);
-        } else if (general_wave[j]) {
-            gather_all<NT>(G, S, pr[j], sm[j], c[j], U[j], ramp_factor(G, a.step - 1), g[j], Dirs{});
-        } else {
-            const Preds px{pr[j].xlo, pr[j].xhi, false, false, false, false};
-            gather_all<NT>(G, S, px, 0u, c[j], U[j], ramp_factor(G, a.step - 1), g[j], Dirs{});
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        if (!fluid[j]) {
-            // the partial sums of solid cells stay zero; writing them keeps
-            // the wavefront's partial-sum stores on whole lines
-            if (a.accumulate && act[j] && G.qpart) ((GLOBAL_AS f32x4 *)gp(G.qpart))[c[j]] = f32x4{0.f, 0.f, 0.f, 0.f};
-            continue;
-        }
-        const PairSums ps = pair_sums(g[j]);
-        const Macro m = macro_of(g[j], ps);
-        if (!(m.rho > 0.0f) || !isfinite(m.rho)) atomicOr(health + ii, 1);
-        if (a.accumulate) accumulate_qoi(G, c[j], fl[j], m);
-        if (a.record == 1) {
-            GLOBAL_AS float *r = gp(a.rec[ii]) + 4 * ((size_t)a.rec_slot * (size_t)G.ncells + c[j]);
-            r[0] = m.rho;
-            r[1] = m.ux;
-            r[2] = m.uy;
-            r[3] = m.uz;
-        } else if (a.record == 2) {
-            GLOBAL_AS float *r = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)Q * G.qs;
-#pragma unroll
-            for (int i = 0; i < Q; ++i) stg(r + (size_t)i * qs, c[j], g[j][i]);
-        }
-        collide<MODEL>(G, g[j], m, ps);
-    }
-    if (PARITY == 1) __syncthreads();
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        if (PARITY == 0) {
-            if (!act[j]) continue;
-#pragma unroll
-            for (int i = 0; i < Q; ++i) stg<NT>(f + (size_t)opp(i) * qs, c[j], g[j][i]);
-            continue;
-        }
-        if (!fluid[j]) {
-            // solid cells of boundary wavefronts write zero into the slots of
-            // their solid-to-solid links, which only they own, so that the
-            // wavefront's stores cover whole lines around the solid body
-            if (general_wave[j] && act[j]) {
-#pragma unroll
-                for (int k = 1; k < Q; ++k)
-                    if ((sm[j] >> k) & 1u) stg<NT>(f + (size_t)k * qs + off_of(G, k), c[j], 0.0f);
-            }
-            continue;
-        }
-        if (!near_wave[j]) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) stg<NT>(f + (size_t)i * qs + off_of(G, i), c[j], g[j][i]);
-        } else if (general_wave[j]) {
-            scatter_all<NT>(G, S, pr[j], sm[j], c[j], U[j], ramp_factor(G, a.step), g[j], Dirs{});
-        } else {
-            const Preds px{pr[j].xlo, pr[j].xhi, false, false, false, false};
-            scatter_all<NT>(G, S, px, 0u, c[j], U[j], ramp_factor(G, a.step), g[j], Dirs{});
-        }
-    }
-}
 
 // QoIs of the current state f^n without advancing it.
 template <int PARITY>
@@ -719,249 +176,6 @@ __global__ __launch_bounds__(256) void k_moments_arg_shift(const float *__restri
     if (nneg && s < 0.0) atomicAdd(nneg, 1ull);
 }
 
-// ------------------------------------------------------------------ adjoint
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// d u_in / d theta_t . c for link i at height z: (c . dir) dU/dtheta_t for
-// speed and z0, U (c . d dir / d phi) for the direction.
-__device__ __forceinline__ void inflow_dtheta(const Geo &G, int z, int i, float out[3])
-{
-    const float cd = (float)cx(i) * G.cphi + (float)cy(i) * G.sphi;
-    const float cdd = -(float)cx(i) * G.sphi + (float)cy(i) * G.cphi;
-    if (G.inflow == 0) {
-        out[0] = cd;
-        out[1] = G.speed * cdd;
-        out[2] = 0.0f;
-    } else {
-        const float L = logf(((float)z + 0.5f) / G.z0);
-        const float U = G.speed * KAPPA_INV * L;
-        out[0] = KAPPA_INV * L * cd;
-        out[1] = U * cdd;
-        out[2] = -G.speed * KAPPA_INV / G.z0 * cd;
-    }
-}
-
-// mu_k = sum of lam^{n+1} over the destination links of direction k, and the
-// inflow-parameter gradient of the moving-wall links among them.
-template <int... Ks>
-__device__ __forceinline__ void adjoint_gather(const Geo &G, const Shape &S, const Preds &p, uint32_t sm, uint32_t c,
-                                               int z, float r, const GLOBAL_AS float *__restrict__ lin, float mu[Q],
-                                               double &gr0,
-                                               double &gr1, double &gr2, std::integer_sequence<int, Ks...>)
-{
-    const uint32_t qs = (uint32_t)G.qs;
-    (
-        [&] {
-            RelLink a, e;
-            scatter_rel<Ks>(S, p, sm, a, e);
-            float s = 0.0f;
-            if (e.valid) s += ldg(lin, (uint32_t)e.slot * qs + (uint32_t)((int32_t)c + e.delta));
-            if (a.valid) {
-                const float l = ldg(lin, (uint32_t)a.slot * qs + (uint32_t)((int32_t)c + a.delta));
-                s += l;
-                if (a.inlet) {
-                    float dt[3];
-                    constexpr int q = opp(Ks);
-                    inflow_dtheta(G, z, q, dt);
-                    const double f6 = 6.0 * (double)wgt(q) * (double)r * (double)l;
-                    gr0 += f6 * dt[0];
-                    gr1 += f6 * dt[1];
-                    gr2 += f6 * dt[2];
-                }
-            }
-            mu[Ks] = s;
-        }(),
-        ...);
-}
-
-// One adjoint step of every instance, with the tiling of the step kernels:
-// a workgroup of BS threads owns BS * CPT consecutive cells of one instance.
-// Gather: wavefronts without boundary cells read lambda^{n+1} with the plain
-// shifted pattern; wavefronts whose boundary cells only sit in the inflow /
-// outflow columns evaluate the transposed x rules for all lanes; the others
-// the full transposed rules.  Then per cell the transposed collision and the
-// probe source; solid cells write zero (their lambda is never read) so the
-// stores cover whole lines.
-template <int BS, int CPT, int MODEL>
-__global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
-                                                int32_t n_tiles, int32_t xcd_remap, AdjArgs a)
-{
-    const int tile = tile_of(xcd_remap);
-    if (tile >= n_tiles) return;
-    const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
-    const Geo &G = geo[ii];
-    const uint32_t qs = (uint32_t)G.qs;
-    const GLOBAL_AS float *__restrict__ lin = gp(a.lam_in[ii]);
-    GLOBAL_AS float *__restrict__ lout = gp(a.lam_out[ii]);
-    const int32_t base = (tile - G.tile0) * (BS * CPT) + (int32_t)threadIdx.x;
-    const float r = ramp_factor(G, a.step);
-    double gr0 = 0.0, gr1 = 0.0, gr2 = 0.0;
-    bool inlet_lane = false;
-
-    uint32_t c[CPT];
-    uint8_t fl[CPT];
-    bool act[CPT], fluid[CPT], near_wave[CPT], general_wave[CPT];
-    float mu[CPT][Q];
-    f32x4 st[CPT];                 // (rho, ux, uy, uz) of a kind-1 record
-    float gs[CPT][Q];              // populations of a kind-2 record
-    const Shape S = shape_of(G);
-    // flags and records of all of the thread's cells first: loads retire in
-    // order, so no cell's classification may wait behind another's gather
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        const int32_t lc = base + j * BS;
-        act[j] = lc < G.ncells;
-        c[j] = act[j] ? (uint32_t)lc : 0u;
-        fl[j] = act[j] ? gp(G.flags)[c[j]] : (uint8_t)FL_SOLID;
-        if (a.record == 1 && act[j])
-            st[j] = ((const GLOBAL_AS f32x4 *)gp(a.rec[ii]))[(size_t)a.rec_slot * (size_t)G.ncells + c[j]];
-    }
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        fluid[j] = !(fl[j] & FL_SOLID);
-        if (fluid[j] && (fl[j] & FL_INLET)) inlet_lane = true;
-        near_wave[j] = __any(fluid[j] && (fl[j] & FL_NEAR));
-        general_wave[j] = __any(fluid[j] && (fl[j] & FL_GENERAL));
-    }
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        if (!fluid[j]) continue;
-        // mu = P^T lam^{n+1}: sum over the destination links of each post-collision value
-        if (!near_wave[j]) {
-#pragma unroll
-            for (int k = 0; k < Q; ++k) mu[j][k] = ldg(lin + (size_t)k * qs + off_of(G, k), c[j]);
-        } else if (general_wave[j]) {
-            int x, y, z;
-            coords(G, c[j], x, y, z);
-            const Preds pr = preds_of(S, x, y, z);
-            const uint32_t sm = gp(G.smask)[c[j]];
-            adjoint_gather(G, S, pr, sm, c[j], z, r, lin, mu[j], gr0, gr1, gr2, Dirs{});
-        } else {
-            const Preds px{(fl[j] & FL_XLO) != 0, (fl[j] & FL_XHI) != 0, false, false, false, false};
-            const int z = (fl[j] & FL_INLET) ? (int)fdiv(c[j], G.dxy) : 0;
-            adjoint_gather(G, S, px, 0u, c[j], z, r, lin, mu[j], gr0, gr1, gr2, Dirs{});
-        }
-        if (a.record != 1) {
-            const GLOBAL_AS float *rp = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)Q * G.qs;
-#pragma unroll
-            for (int i = 0; i < Q; ++i) gs[j][i] = ldg(rp + (size_t)i * qs, c[j]);
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        if (!act[j]) continue;
-        if (!fluid[j]) {
-#pragma unroll
-            for (int k = 0; k < Q; ++k) stg(lout + (size_t)k * qs, c[j], 0.0f);
-            continue;
-        }
-        // state of step n
-        float rho, ux, uy, uz, om;
-        float A = 0.0f, P[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, qn = 0.0f, tau = G.tau0;
-        if (a.record == 1) {
-            rho = st[j].x;
-            ux = st[j].y;
-            uy = st[j].z;
-            uz = st[j].w;
-            om = 1.0f / G.tau0;
-        } else {
-            const float *g = gs[j];
-            const PairSums ps = pair_sums(g);
-            const Macro m = macro_of(g, ps);
-            rho = m.rho;
-            ux = m.ux;
-            uy = m.uy;
-            uz = m.uz;
-            if (MODEL == 1) {
-                neq_stress(ps, m, P);
-                qn = stress_norm(P);
-                tau = tau_of<1>(G, ps, m);
-                const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) A += mu[j][i] * (g[i] - geq(i, m, usq15));
-            }
-            om = 1.0f / tau;
-        }
-        // BGK part: (1 - om) mu_k + om [s_rho + (c_k - u) . t]
-        float m0 = 0.f, m1x = 0.f, m1y = 0.f, m1z = 0.f;
-        float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const float wm = wgt(i) * mu[j][i];
-            m0 += wm;
-            if (cx(i)) { m1x += cx(i) * wm; mxx += wm; }
-            if (cy(i)) { m1y += cy(i) * wm; myy += wm; }
-            if (cz(i)) { m1z += cz(i) * wm; mzz += wm; }
-            if (cx(i) && cy(i)) mxy += cx(i) * cy(i) * wm;
-            if (cx(i) && cz(i)) mxz += cx(i) * cz(i) * wm;
-            if (cy(i) && cz(i)) myz += cy(i) * cz(i) * wm;
-        }
-        const float usq = ux * ux + uy * uy + uz * uz;
-        const float m2ux = mxx * ux + mxy * uy + mxz * uz;
-        const float m2uy = mxy * ux + myy * uy + myz * uz;
-        const float m2uz = mxz * ux + myz * uy + mzz * uz;
-        const float srho = m0 * (1.0f - 1.5f * usq) + 3.0f * (m1x * ux + m1y * uy + m1z * uz) +
-                           4.5f * (ux * m2ux + uy * m2uy + uz * m2uz);
-        const float tx = 3.0f * m1x + 9.0f * m2ux - 3.0f * ux * m0;
-        const float ty = 3.0f * m1y + 9.0f * m2uy - 3.0f * uy * m0;
-        const float tz = 3.0f * m1z + 9.0f * m2uz - 3.0f * uz * m0;
-        // Smagorinsky: + (A / tau^2) dtau/df_k
-        float sa = 0.0f, sb = 0.0f;
-        if (MODEL == 1 && qn > 0.0f) {
-            const float R = sqrtf(G.tau0 * G.tau0 + G.kcs * qn / rho);
-            const float pre = A / (tau * tau) * G.kcs / (4.0f * R);
-            sa = pre / (rho * qn);
-            sb = -pre * qn / (rho * rho) - sa * (P[0] + P[1] + P[2]) * (1.0f / 3.0f);
-        }
-        // objective source at the probes: pw_p / count * (c_kx - u_x) / rho
-        float src = 0.0f;
-        if (a.in_window && (fl[j] & FL_PROBE) && a.pw[ii]) {
-            const int p = probe_index(G, (int32_t)c[j]);
-            if (p >= 0) src = (float)(a.pw[ii][p] * a.inv_count) / rho;
-        }
-#pragma unroll
-        for (int k = 0; k < Q; ++k) {
-            const float ex = cx(k) - ux, ey = cy(k) - uy, ez = cz(k) - uz;
-            float lk = (1.0f - om) * mu[j][k] + om * (srho + ex * tx + ey * ty + ez * tz);
-            if (MODEL == 1) {
-                const float quad = ex * (P[0] * ex + P[3] * ey + P[4] * ez) +
-                                   ey * (P[3] * ex + P[1] * ey + P[5] * ez) +
-                                   ez * (P[4] * ex + P[5] * ey + P[2] * ez);
-                lk += sa * quad + sb;
-            }
-            lk += src * ex;
-            stg(lout + (size_t)k * qs, c[j], lk);
-        }
-    }
-    // gradient: wavefront sums, then one partial per tile (the per-instance
-    // sums are formed afterwards in a fixed order, without atomics)
-    __shared__ double red[BS / 64][3];
-    const int wv = threadIdx.x >> 6;
-    if (__any(inlet_lane)) {
-        gr0 = wave_sum(gr0);
-        gr1 = wave_sum(gr1);
-        gr2 = wave_sum(gr2);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        red[wv][0] = gr0;
-        red[wv][1] = gr1;
-        red[wv][2] = gr2;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        double t = 0.0;
-#pragma unroll
-        for (int w = 0; w < BS / 64; ++w) t += red[w][threadIdx.x];
-        a.part[3 * (size_t)tile + threadIdx.x] = t;
-    }
-}
-
 // grad[i][k] += sum of part[tile][k] over instance i's tiles: one workgroup
 // per instance, strided partial sums then a tree in shared memory.
 __global__ __launch_bounds__(256) void k_grad_reduce(const Geo *__restrict__ geo, int32_t tile_cells,
@@ -1023,48 +237,10 @@ __global__ __launch_bounds__(1024) void k_adjoint_init(const Geo *__restrict__ g
 
 // ------------------------------------------------------------------ launches
 
-static inline int grid_of(int32_t n_tiles) { return ((n_tiles + 7) / 8) * 8; }
-
-template <int BS, int CPT, bool NT, int MODEL>
-static void step_v(int parity, const Geo *geo, const int32_t *ti, int32_t nt, const StepArgs &a, int32_t *h,
-                   hipStream_t s)
-{
-    const dim3 grid(grid_of(nt)), block(BS);
-    if (parity == 0) hipLaunchKernelGGL((k_step<BS, CPT, NT, MODEL, 0>), grid, block, 0, s, geo, ti, nt, a, h);
-    else hipLaunchKernelGGL((k_step<BS, CPT, NT, MODEL, 1>), grid, block, 0, s, geo, ti, nt, a, h);
-}
-
-template <int BS, int CPT, bool NT>
-static void step_m(int model, int parity, const Geo *geo, const int32_t *ti, int32_t nt, const StepArgs &a,
-                   int32_t *h, hipStream_t s)
-{
-    if (model == 0) step_v<BS, CPT, NT, 0>(parity, geo, ti, nt, a, h, s);
-    else if (model == 1) step_v<BS, CPT, NT, 1>(parity, geo, ti, nt, a, h, s);
-    else step_v<BS, CPT, NT, 2>(parity, geo, ti, nt, a, h, s);
-}
-
-// v.nt is a mask: bit 0 non-temporal accesses in even steps, bit 1 in odd steps
-template <int BS, int CPT>
-static void step_n(const Variant &v, int model, int parity, const Geo *geo, const int32_t *ti, int32_t nt,
-                   const StepArgs &a, int32_t *h, hipStream_t s)
-{
-    if ((v.nt >> parity) & 1) step_m<BS, CPT, true>(model, parity, geo, ti, nt, a, h, s);
-    else step_m<BS, CPT, false>(model, parity, geo, ti, nt, a, h, s);
-}
-
 bool variant_ok(const Variant &v)
 {
     return (v.bs == 64 || v.bs == 128 || v.bs == 256 || v.bs == 512) && (v.cpt == 1 || v.cpt == 2 || v.cpt == 4) &&
            v.nt >= 0 && v.nt <= 3 && (v.xcd == 0 || v.xcd == 1);
-}
-
-template <int BS>
-static void step_c(const Variant &v, int model, int parity, const Geo *geo, const int32_t *ti, int32_t nt,
-                   const StepArgs &a, int32_t *h, hipStream_t s)
-{
-    if (v.cpt == 1) step_n<BS, 1>(v, model, parity, geo, ti, nt, a, h, s);
-    else if (v.cpt == 2) step_n<BS, 2>(v, model, parity, geo, ti, nt, a, h, s);
-    else step_n<BS, 4>(v, model, parity, geo, ti, nt, a, h, s);
 }
 
 int launch_step(const Variant &v, int model, int parity, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
@@ -1074,11 +250,9 @@ int launch_step(const Variant &v, int model, int parity, const Geo *geo, const i
     if (!variant_ok(v)) return -1;
     StepArgs a = a0;
     a.xcd_remap = v.xcd;
-    if (v.bs == 64) step_c<64>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
-    else if (v.bs == 128) step_c<128>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
-    else if (v.bs == 256) step_c<256>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
-    else step_c<512>(v, model, parity, geo, tile_inst, n_tiles, a, health, s);
-    return (int)hipGetLastError();
+    if (model == 0) return launch_step_model<0>(v, parity, geo, tile_inst, n_tiles, a, health, s);
+    if (model == 1) return launch_step_model<1>(v, parity, geo, tile_inst, n_tiles, a, health, s);
+    return launch_step_model<2>(v, parity, geo, tile_inst, n_tiles, a, health, s);
 }
 
 int launch_init_geometry(const Box &b, const uint8_t *solid, uint8_t *flags, uint32_t *smask, const int32_t *probes,
@@ -1141,37 +315,6 @@ int launch_moments(const float *q, const double *w, int32_t nq, int64_t n, doubl
     else if (nq <= 16) hipLaunchKernelGGL(k_moments_arg<16>, grid, block, 0, s, q, nq, n, W, mean, var, nneg);
     else if (nq <= 32) hipLaunchKernelGGL(k_moments_arg<32>, grid, block, 0, s, q, nq, n, W, mean, var, nneg);
     else hipLaunchKernelGGL(k_moments_arg_shift, grid, block, 0, s, q, nq, n, W, mean, var, nneg);
-    return (int)hipGetLastError();
-}
-
-template <int BS>
-static void adjoint_c(const Variant &v, const Geo *geo, const int32_t *ti, int32_t nt, const AdjArgs &a,
-                      hipStream_t s)
-{
-    const dim3 grid(grid_of(nt)), block(BS);
-    const int32_t xr = v.xcd;
-#define LBM_ADJ(C, M) hipLaunchKernelGGL((k_adjoint<BS, C, M>), grid, block, 0, s, geo, ti, nt, xr, a)
-    if (a.model == 0) {
-        if (v.cpt == 1) LBM_ADJ(1, 0);
-        else if (v.cpt == 2) LBM_ADJ(2, 0);
-        else LBM_ADJ(4, 0);
-    } else {
-        if (v.cpt == 1) LBM_ADJ(1, 1);
-        else if (v.cpt == 2) LBM_ADJ(2, 1);
-        else LBM_ADJ(4, 1);
-    }
-#undef LBM_ADJ
-}
-
-int launch_adjoint(const Variant &v, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, const AdjArgs &a,
-                   hipStream_t s)
-{
-    if (n_tiles <= 0) return 0;
-    if (!variant_ok(v)) return -1;
-    if (v.bs == 64) adjoint_c<64>(v, geo, tile_inst, n_tiles, a, s);
-    else if (v.bs == 128) adjoint_c<128>(v, geo, tile_inst, n_tiles, a, s);
-    else if (v.bs == 256) adjoint_c<256>(v, geo, tile_inst, n_tiles, a, s);
-    else adjoint_c<512>(v, geo, tile_inst, n_tiles, a, s);
     return (int)hipGetLastError();
 }
 
