@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--xcd-order", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost leg")
+    ap.add_argument("--no-rr3", action="store_true", help="skip the regularised-collision leg")
     ap.add_argument("--no-uneven", action="store_true", help="skip the batched vs one-at-a-time leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-calib", action="store_true",
@@ -117,6 +118,39 @@ def copy_ceiling(nbytes: int = 2 << 30, reps: int = 5) -> float:
         best = min(best, e0.elapsed_time(e1) / 1e3)
     del src, dst
     return 2 * nbytes / best / 1e9
+
+
+def rr3_leg(variant, steps: int = 1000):
+    """The regularised third-order collision (with the Smagorinsky tau_eff) on
+    the same 13-node urban batch: launch time of the step pair after the ramp."""
+    import torch
+    from paper_2508_18202_amd import inputs, sc
+    w = inputs.scaled(inputs.urban_les(), 256, 128, 64, model="rr3")
+    solid = inputs.solid_mask(w)
+    n_fluid = int((solid == 0).sum())
+    x, a, th = sc.collocation(w)
+    cg = sc.make_geometry(w, solid)
+    ens = sc.Ensemble([cg], [th], use_graph=True, variant=variant)
+    try:
+        ens.advance(w.ramp)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ens.advance(steps)
+        e1.record()
+        e1.synchronize()
+        if ens.health() >= 0:
+            raise RuntimeError("regularised leg went unstable")
+        t = e0.elapsed_time(e1) / 1e3 / steps
+        launch_bytes = BYTES_PER_CELL_UPDATE * len(ens) * n_fluid
+        return {"workload": "13 Smolyak nodes x 256x128x64 urban LES, regularised third-order collision, "
+                            f"Smagorinsky Cs=0.1, {steps} steps after the ramp",
+                "avg_launch_us": round(t * 1e6, 2), "kernel_mlups": round(len(ens) * n_fluid / t / 1e6, 1),
+                "achieved_gbs": round(launch_bytes / t / 1e9, 1),
+                "frac": round(launch_bytes / t / 1e9 / HBM_PEAK_GBS, 4)}
+    finally:
+        ens.close()
 
 
 def adjoint_leg(variant, steps: int = 2000, avg_len: int = 500, ckpt: int = 100):
@@ -330,6 +364,8 @@ def main():
         },
         "kernel_mlups": round(n_inst * n_fluid / avg_launch_s / 1e6, 1),
     }
+    if not args.no_rr3:
+        out["regularised_collision"] = rr3_leg(variant)
     if not args.no_adjoint:
         out["adjoint_vs_forward"] = adjoint_leg(variant)
     if not args.no_uneven:
