@@ -38,7 +38,7 @@
 
 enum { F_WALL = 0, F_INLET = 1, F_OUTLET = 2, F_FREESLIP = 3, F_PERIODIC = 4 };
 enum { M_BGK = 0, M_SMAG = 1, M_RR3 = 2 };
-enum { IN_UNIFORM = 0, IN_LOGLAW = 1 };
+enum { IN_UNIFORM = 0, IN_LOGLAW = 1, IN_SERIES = 2 };
 
 typedef struct {
     int nx, ny, nz;
@@ -50,6 +50,12 @@ typedef struct {
     double theta[3];             /* uniform: (U, phi, -); log-law: (u*, phi, z0) */
     int ramp;                    /* inflow ramp length in steps (0 = none) */
     double force[3];             /* uniform body force (Guo); zero in the workloads */
+    /* measured-series inflow (IN_SERIES): hourly reference speed and direction
+     * (rad) as series[2 h], series[2 h + 1], h < series_len; theta = (zeta1
+     * speed multiplier, zeta2 direction offset in rad, z0) */
+    const double *series;
+    int series_len, hour_steps, blend_steps;
+    double ref_height;           /* H of the normalised log profile (cells) */
 } orc_case;
 
 /* D3Q19 velocities in the canonical order: rest, 6 faces (+x,-x,+y,-y,+z,-z),
@@ -299,37 +305,77 @@ static double ramp_factor(const orc_case *k, long n)
     return 0.5 * (1.0 - cos(M_PI * (double)n / (double)k->ramp));
 }
 
-/* Inflow velocity and its derivatives w.r.t. theta at height index z (cell
- * centre z + 1/2 above the half-way ground).  Log-law: U(z) = (u_star / 0.41) ln(z/z0),
- * direction (cos phi, sin phi, 0).  dudth[3][3]: d u_a / d theta_k. */
-static void inflow(const orc_case *k, int z, double u[3], double dudth[3][3])
+/* Reference speed and direction of the measured series at step n (Sec. 3):
+ * hour h starts at step ramp + h * hour_steps; during its first blend_steps
+ * steps the values move from those of hour h-1 to those of hour h with the
+ * weight (1 - cos(pi t / blend_steps)) / 2, the direction along the shorter
+ * arc; afterwards they are held.  Before and during the ramp the values of
+ * hour 0 apply; past the last hour its values are held. */
+static void series_at(const orc_case *k, long n, double *U, double *D)
+{
+    long t = n - k->ramp;
+    if (t < 0) t = 0;
+    long h = t / k->hour_steps, tp = t - h * k->hour_steps;
+    if (h >= k->series_len) {
+        h = k->series_len - 1;
+        tp = k->hour_steps;
+    }
+    *U = k->series[2 * h];
+    *D = k->series[2 * h + 1];
+    if (h > 0 && tp < k->blend_steps) {
+        double s = 0.5 * (1.0 - cos(M_PI * (double)tp / (double)k->blend_steps));
+        double U0 = k->series[2 * h - 2], D0 = k->series[2 * h - 1];
+        double dD = remainder(*D - D0, 2.0 * M_PI);   /* shorter arc, in [-pi, pi] */
+        *U = U0 + s * (*U - U0);
+        *D = D0 + s * dD;
+    }
+}
+
+/* Inflow velocity u_in(z, n) (ramp included) and its derivatives w.r.t.
+ * theta at height index z (cell centre z + 1/2 above the half-way ground).
+ *   uniform: U = theta0, direction phi = theta1;
+ *   log-law: U(z) = (u_star / 0.41) ln((z + 1/2) / z0), theta = (u_star, phi, z0);
+ *   series:  U(z) = zeta1 U_H(n) ln((h + z0) / z0) / ln((H + z0) / z0), h = z + 1/2,
+ *            direction Theta(n) + zeta2 (Sec. 3 perturbation of the measured
+ *            series and normalised log profile), theta = (zeta1, zeta2, z0).
+ * Velocity U (cos phi, sin phi, 0); dudth[3][3]: d u_a / d theta_k. */
+static void inflow_at(const orc_case *k, int z, long n, double u[3], double dudth[3][3])
 {
     double phi = k->theta[1];
     double U, dU[3] = {0.0, 0.0, 0.0};
     if (k->inflow == IN_UNIFORM) {
         U = k->theta[0];
         dU[0] = 1.0;
-    } else {
+    } else if (k->inflow == IN_LOGLAW) {
         double us = k->theta[0], z0 = k->theta[2], h = z + 0.5;
         U = us / 0.41 * log(h / z0);
         dU[0] = log(h / z0) / 0.41;
         dU[2] = -us / (0.41 * z0);
+    } else {
+        double UH, Th;
+        series_at(k, n, &UH, &Th);
+        double z1 = k->theta[0], z0 = k->theta[2], h = z + 0.5, H = k->ref_height;
+        double A = log((h + z0) / z0), B = log((H + z0) / z0);
+        double dA = 1.0 / (h + z0) - 1.0 / z0, dB = 1.0 / (H + z0) - 1.0 / z0;
+        U = z1 * UH * A / B;
+        dU[0] = UH * A / B;
+        dU[2] = z1 * UH * (dA * B - A * dB) / (B * B);
+        phi = Th + k->theta[1];
     }
+    double r = ramp_factor(k, n);
     double dir[3] = {cos(phi), sin(phi), 0.0};
     double ddir[3] = {-sin(phi), cos(phi), 0.0};
     for (int a = 0; a < 3; ++a) {
-        u[a] = U * dir[a];
-        for (int t = 0; t < 3; ++t) dudth[a][t] = dU[t] * dir[a];
-        dudth[a][1] = U * ddir[a];
+        u[a] = r * U * dir[a];
+        for (int t = 0; t < 3; ++t) dudth[a][t] = r * dU[t] * dir[a];
+        dudth[a][1] = r * U * ddir[a];
     }
 }
 
 void orc_inflow_velocity(const orc_case *k, int z, long n, double *u)
 {
     double d[3][3];
-    inflow(k, z, u, d);
-    double r = ramp_factor(k, n);
-    for (int a = 0; a < 3; ++a) u[a] *= r;
+    inflow_at(k, z, n, u, d);
 }
 
 enum { R_STREAM = 0, R_BOUNCE = 1, R_INLET = 2, R_FREESLIP = 3, R_OUTLET = 4, R_REST = 5 };
@@ -397,6 +443,10 @@ int orc_check_case(const orc_case *k)
     for (int a = 0; a < 3; ++a)
         if ((k->face[2 * a] == F_PERIODIC) != (k->face[2 * a + 1] == F_PERIODIC)) return 3;
     if (k->tau0 <= 0.5) return 4;
+    if (k->inflow == IN_SERIES &&
+        (!k->series || k->series_len < 1 || k->hour_steps < 1 || k->blend_steps < 0 ||
+         k->blend_steps > k->hour_steps || !(k->ref_height > 0.0) || !(k->theta[2] > 0.0)))
+        return 7;
     /* the free-slip and outflow rules read top-layer / last-column cells */
     for (int z = 0; z < k->nz; ++z)
         for (int y = 0; y < k->ny; ++y)
@@ -437,7 +487,6 @@ void orc_step(const orc_case *k, long step, const double *fin, double *fout)
 {
     long n = ncells(k);
     double *fs = (double *)malloc(sizeof(double) * NQ * n);
-    double r = ramp_factor(k, step);
 #pragma omp parallel for schedule(static)
     for (long c = 0; c < n; ++c) {
         double fl[NQ], fsl[NQ];
@@ -464,9 +513,9 @@ void orc_step(const orc_case *k, long step, const double *fin, double *fout)
                     double v = fs[p * n + cell_index(k, sx, sy, sz)];
                     if (rule == R_INLET) {
                         double uin[3], d[3][3];
-                        inflow(k, z, uin, d);
+                        inflow_at(k, z, step, uin, d);
                         double cu = C[i][0] * uin[0] + C[i][1] * uin[1] + C[i][2] * uin[2];
-                        v += 6.0 * weight(i) * 1.0 * cu * r;
+                        v += 6.0 * weight(i) * 1.0 * cu;
                     }
                     fout[i * n + c] = v;
                 }
@@ -566,7 +615,6 @@ void orc_adjoint_step(const orc_case *k, long step, const double *f_n,
 {
     long n = ncells(k);
     double *mu = (double *)calloc((size_t)NQ * n, sizeof(double));
-    double r = ramp_factor(k, step);
     double g[3] = {0.0, 0.0, 0.0};
     for (int z = 0; z < k->nz; ++z)
         for (int y = 0; y < k->ny; ++y)
@@ -580,10 +628,10 @@ void orc_adjoint_step(const orc_case *k, long step, const double *f_n,
                     mu[p * n + cell_index(k, sx, sy, sz)] += lam;
                     if (rule == R_INLET) {
                         double uin[3], d[3][3];
-                        inflow(k, z, uin, d);
+                        inflow_at(k, z, step, uin, d);
                         for (int t = 0; t < 3; ++t) {
                             double cd = C[i][0] * d[0][t] + C[i][1] * d[1][t] + C[i][2] * d[2][t];
-                            g[t] += lam * 6.0 * weight(i) * cd * r;
+                            g[t] += lam * 6.0 * weight(i) * cd;
                         }
                     }
                 }

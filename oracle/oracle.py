@@ -40,7 +40,7 @@ _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 NQ = 19
 FACE_CODES = {"wall": 0, "inlet": 1, "outlet": 2, "freeslip": 3, "periodic": 4}
 MODEL_CODES = {"bgk": 0, "smagorinsky": 1, "rr3": 2}
-INFLOW_CODES = {"uniform": 0, "loglaw": 1}
+INFLOW_CODES = {"uniform": 0, "loglaw": 1, "series": 2}
 
 
 def build(force: bool = True) -> str:
@@ -58,7 +58,9 @@ class _Case(ctypes.Structure):
                 ("face", ctypes.c_int * 6), ("solid", ctypes.POINTER(ctypes.c_uint8)),
                 ("model", ctypes.c_int), ("tau0", ctypes.c_double), ("cs", ctypes.c_double),
                 ("inflow", ctypes.c_int), ("theta", ctypes.c_double * 3),
-                ("ramp", ctypes.c_int), ("force", ctypes.c_double * 3)]
+                ("ramp", ctypes.c_int), ("force", ctypes.c_double * 3),
+                ("series", ctypes.POINTER(ctypes.c_double)), ("series_len", ctypes.c_int),
+                ("hour_steps", ctypes.c_int), ("blend_steps", ctypes.c_int), ("ref_height", ctypes.c_double)]
 
 
 _lib = None
@@ -253,7 +255,8 @@ class Case:
     """One deterministic lattice case at one collocation node."""
 
     def __init__(self, nx, ny, nz, faces, solid, model="bgk", tau0=0.6, cs=0.0,
-                 inflow="uniform", theta=(0.0, 0.0, 0.0), ramp=0, force=(0.0, 0.0, 0.0)):
+                 inflow="uniform", theta=(0.0, 0.0, 0.0), ramp=0, force=(0.0, 0.0, 0.0),
+                 series=(), hour_steps=0, blend_steps=0, ref_height=0.0):
         self.solid = np.ascontiguousarray(solid, dtype=np.uint8).reshape(nz, ny, nx)
         self.shape = (nz, ny, nx)
         self.n = nx * ny * nz
@@ -269,6 +272,12 @@ class Case:
             c.theta[k] = float(theta[k])
             c.force[k] = float(force[k])
         c.ramp = ramp
+        # hourly series inflow: [hours][2] (U_H, Theta in rad)
+        self.series = np.ascontiguousarray(np.asarray(series, dtype=np.float64).reshape(-1, 2))
+        if len(self.series):
+            c.series = self.series.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        c.series_len, c.hour_steps, c.blend_steps = len(self.series), int(hour_steps), int(blend_steps)
+        c.ref_height = float(ref_height)
         self.c = c
         err = lib().orc_check_case(ctypes.byref(c))
         if err:
@@ -277,13 +286,14 @@ class Case:
     @classmethod
     def from_workload(cls, w, solid, theta):
         return cls(w.nx, w.ny, w.nz, w.faces, solid, w.model, w.tau0, w.cs, w.inflow,
-                   theta, w.ramp)
+                   theta, w.ramp, series=w.series, hour_steps=w.hour_steps, blend_steps=w.blend_steps,
+                   ref_height=w.ref_height)
 
     def with_theta(self, theta):
         nz, ny, nx = self.shape
         c = self.c
         return Case(nx, ny, nz, list(c.face), self.solid, c.model, c.tau0, c.cs, c.inflow,
-                    theta, c.ramp, list(c.force))
+                    theta, c.ramp, list(c.force), self.series, c.hour_steps, c.blend_steps, c.ref_height)
 
     def init(self) -> np.ndarray:
         f = np.zeros((NQ, self.n))

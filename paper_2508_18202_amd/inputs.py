@@ -68,8 +68,9 @@ class Workload:
     model: str                      # "bgk" or "smagorinsky"
     tau0: float                     # molecular relaxation time
     cs: float                       # Smagorinsky constant (0 for BGK)
-    inflow: str                     # "uniform" or "loglaw"
+    inflow: str                     # "uniform", "loglaw" or "series"
     # inflow parameter recipe: value = base * (1 + rel * xi_1); angle = deg * xi_2
+    # (series: speed multiplier 1 + rel * xi_1 on the hourly speeds)
     speed_base: float               # U (uniform) or u* (log-law)
     speed_rel: float
     angle_deg: float                # direction spread in degrees (0: none)
@@ -85,6 +86,13 @@ class Workload:
     buildings: Optional[Tuple[int, int]] = None   # (n_bx, n_by) array, None: the single block
     probe_kind: Optional[str] = None              # "plane" or "points", see probe_cells
     ckpt_every: int = 0
+    # hourly measured-series inflow ("series"): ((U_H, Theta[rad]), ...) per
+    # hour, steps per hour, blending steps at each hour change, reference
+    # height H of the normalised log profile (cells)
+    series: Tuple[Tuple[float, float], ...] = ()
+    hour_steps: int = 0
+    blend_steps: int = 0
+    ref_height: float = 0.0
 
     @property
     def ncells(self) -> int:
@@ -243,6 +251,37 @@ def assimilation_case(steps: int = 2000, avg_len: int = 500) -> Workload:
                     steps=steps, avg_start=steps - avg_len, ramp=1000,
                     seed_base=5000, buildings=(10, 6), probe_kind="points",
                     ckpt_every=100)
+
+
+def hourly_series(hours: int, seed: int, speed_mean: float = 0.016, speed_amp: float = 0.006,
+                  dir0_deg: float = 0.0, dir_step_deg: float = 12.0) -> Tuple[Tuple[float, float], ...]:
+    """Synthetic hourly reference wind (lattice speed, direction in rad) in
+    place of the station record: speeds from a smoothed seeded sequence around
+    speed_mean, directions a seeded random walk from dir0_deg."""
+    g = SplitMix64(seed)
+    out = []
+    s = 0.0
+    d = math.radians(dir0_deg)
+    for _ in range(hours):
+        s = 0.7 * s + 0.3 * (2.0 * g.uniform01() - 1.0)
+        d += math.radians(dir_step_deg) * (2.0 * g.uniform01() - 1.0)
+        out.append((speed_mean + speed_amp * s, d))   # |s| <= 1
+    return tuple(out)
+
+
+def urban_series(hours: int = 8, hour_steps: int = 500, blend_steps: int = 100) -> Workload:
+    """Urban LES driven by an hourly wind series (the paper's time-dependent
+    inflow): speed multiplier 1 + 0.1 xi_1 and direction offset 6 deg xi_2 on
+    the series, normalised log profile with z0 = 0.1 cells and H = nz."""
+    nz = 64
+    return Workload(name="urban_series_256x128x64", nx=256, ny=128, nz=nz, faces=URBAN_FACES,
+                    model="smagorinsky", tau0=LES_TAU0, cs=0.1, inflow="series",
+                    speed_base=1.0, speed_rel=0.1, angle_deg=6.0, z0=0.1,
+                    quadrature="smolyak_cc", quad_level=2, quad_dim=2,
+                    steps=1000 + hours * hour_steps, avg_start=1000 + hours * hour_steps, ramp=1000,
+                    seed_base=6000, buildings=(6, 4),
+                    series=hourly_series(hours, 6000), hour_steps=hour_steps, blend_steps=blend_steps,
+                    ref_height=float(nz))
 
 
 def scaled(w: Workload, nx: int, ny: int, nz: int, **kw) -> Workload:
