@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--xcd-order", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost leg")
-    ap.add_argument("--no-rr3", action="store_true", help="skip the regularised-collision leg")
+    ap.add_argument("--no-rr3", action="store_true", help="skip the regularised-collision and series-inflow legs")
     ap.add_argument("--no-uneven", action="store_true", help="skip the batched vs one-at-a-time leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-calib", action="store_true",
@@ -120,12 +120,12 @@ def copy_ceiling(nbytes: int = 2 << 30, reps: int = 5) -> float:
     return 2 * nbytes / best / 1e9
 
 
-def rr3_leg(variant, steps: int = 1000):
-    """The regularised third-order collision (with the Smagorinsky tau_eff) on
-    the same 13-node urban batch: launch time of the step pair after the ramp."""
+def _after_ramp_rate(w, variant, steps: int, label: str):
+    """Step-pair launch time of the 13 nodes of workload w, timed with events
+    over `steps` steps after the inflow ramp."""
     import torch
-    from paper_2508_18202_amd import inputs, sc
-    w = inputs.scaled(inputs.urban_les(), 256, 128, 64, model="rr3")
+    from paper_2508_18202_amd import sc
+    from paper_2508_18202_amd import inputs
     solid = inputs.solid_mask(w)
     n_fluid = int((solid == 0).sum())
     x, a, th = sc.collocation(w)
@@ -141,16 +141,36 @@ def rr3_leg(variant, steps: int = 1000):
         e1.record()
         e1.synchronize()
         if ens.health() >= 0:
-            raise RuntimeError("regularised leg went unstable")
+            raise RuntimeError(f"{label} leg went unstable")
         t = e0.elapsed_time(e1) / 1e3 / steps
         launch_bytes = BYTES_PER_CELL_UPDATE * len(ens) * n_fluid
-        return {"workload": "13 Smolyak nodes x 256x128x64 urban LES, regularised third-order collision, "
-                            f"Smagorinsky Cs=0.1, {steps} steps after the ramp",
-                "avg_launch_us": round(t * 1e6, 2), "kernel_mlups": round(len(ens) * n_fluid / t / 1e6, 1),
+        return {"avg_launch_us": round(t * 1e6, 2), "kernel_mlups": round(len(ens) * n_fluid / t / 1e6, 1),
                 "achieved_gbs": round(launch_bytes / t / 1e9, 1),
                 "frac": round(launch_bytes / t / 1e9 / HBM_PEAK_GBS, 4)}
     finally:
         ens.close()
+
+
+def rr3_leg(variant, steps: int = 1000):
+    """The regularised third-order collision (with the Smagorinsky tau_eff) on
+    the same 13-node urban batch."""
+    from paper_2508_18202_amd import inputs
+    w = inputs.scaled(inputs.urban_les(), 256, 128, 64, model="rr3")
+    out = {"workload": "13 Smolyak nodes x 256x128x64 urban LES, regularised third-order collision, "
+                       f"Smagorinsky Cs=0.1, {steps} steps after the ramp"}
+    out.update(_after_ramp_rate(w, variant, steps, "regularised"))
+    return out
+
+
+def series_leg(variant, steps: int = 1000):
+    """The same batch driven by an hourly wind series (four 250-step hours with
+    100-step blends after the ramp): the in-kernel series evaluation."""
+    from paper_2508_18202_amd import inputs
+    w = inputs.urban_series(hours=4, hour_steps=250, blend_steps=100)
+    out = {"workload": "13 Smolyak nodes x 256x128x64 urban LES, Smagorinsky Cs=0.1, hourly-series inflow "
+                       f"(hours of 250 steps, blends of 100), {steps} steps after the ramp"}
+    out.update(_after_ramp_rate(w, variant, steps, "series"))
+    return out
 
 
 def adjoint_leg(variant, steps: int = 2000, avg_len: int = 500, ckpt: int = 100):
@@ -366,6 +386,7 @@ def main():
     }
     if not args.no_rr3:
         out["regularised_collision"] = rr3_leg(variant)
+        out["series_inflow"] = series_leg(variant)
     if not args.no_adjoint:
         out["adjoint_vs_forward"] = adjoint_leg(variant)
     if not args.no_uneven:

@@ -82,8 +82,18 @@ enum { LBM_BGK = 0, LBM_SMAGORINSKY = 1, LBM_RR3 = 2 };
  *   UNIFORM  u_in = speed (cos phi, sin phi, 0);
  *   LOGLAW   u_in(z) = (speed / 0.41) ln((z + 1/2) / z0) (cos phi, sin phi, 0),
  *            speed = friction velocity u*, z0 = roughness length in cells,
- *            z the cell index above the half-way ground. */
-enum { LBM_INFLOW_UNIFORM = 0, LBM_INFLOW_LOGLAW = 1 };
+ *            z the cell index above the half-way ground;
+ *   SERIES   the measured-series inflow of Sec. 3: theta = (zeta1, zeta2, z0),
+ *            u_in(z, n) = zeta1 U_H(n) ln((h + z0)/z0) / ln((H + z0)/z0)
+ *                         (cos(Theta(n) + zeta2), sin(Theta(n) + zeta2), 0),
+ *            h = z + 1/2, H = ref_height; U_H(n), Theta(n) from the hourly
+ *            series (see lbm_instance): hour k starts at step ramp + k hour_steps,
+ *            the values move from hour k-1's to hour k's over its first
+ *            blend_steps steps with weight (1 - cos(pi t / blend_steps)) / 2,
+ *            the direction along the shorter arc, and are then held (hour 0
+ *            before and during the ramp, the last hour after the series).
+ * Every kind is scaled by the ramp factor below. */
+enum { LBM_INFLOW_UNIFORM = 0, LBM_INFLOW_LOGLAW = 1, LBM_INFLOW_SERIES = 2 };
 
 /* Collocation rules (Sec. 2.3, Eq. coef_discrete / quad_moments). */
 enum { LBM_QUAD_GAUSS_LEGENDRE = 0, LBM_QUAD_SMOLYAK_CC = 1 };
@@ -109,12 +119,22 @@ typedef struct lbm_instance {
     float *qoi_part_dev;     /* [ncells][4] FP32 partial sums of (ux, uy, uz, |u|) or NULL */
     double *qoi_sum_dev;     /* [ncells][4] FP64 window sums, or NULL (both or neither) */
     double *probe_sum_dev;   /* [n_probes] FP64 window sums of u_x at the probes, or NULL */
+    /* LBM_INFLOW_SERIES only (ignored otherwise): */
+    const float *series_dev; /* [series_len][2] (U_H, Theta [rad]) per hour, device memory
+                                owned by the caller, outliving the plan */
+    int32_t series_len;      /* >= 1 hours */
+    int32_t hour_steps;      /* >= 1 steps per hour */
+    int32_t blend_steps;     /* 0 .. hour_steps */
+    float ref_height;        /* H > 0 in cells */
 } lbm_instance;
 
 typedef struct lbm_plan_opts {
     int64_t avg_begin;         /* QoI window: states f^n with avg_begin < n <= avg_end */
     int64_t avg_end;           /* avg_end <= avg_begin disables accumulation */
-    int32_t use_graph;         /* replay step pairs from captured HIP graphs where possible */
+    int32_t use_graph;         /* replay step pairs from captured HIP graphs where possible:
+                                  outside the QoI window and once every instance's inflow is
+                                  constant in time (after the ramp and, for a series, after
+                                  the blend into its last hour) */
     int32_t block;             /* threads per workgroup: 64, 128, 256 or 512; 0 = default (256) */
     int32_t cells_per_thread;  /* 1, 2 or 4; 0 = default (1).  A workgroup owns block *
                                   cells_per_thread consecutive cells of one instance */

@@ -86,16 +86,63 @@ __device__ __forceinline__ float ramp_factor(const Geo &G, int64_t n)
     return 0.5f * (1.0f - cosf(3.14159265358979323846f * (float)n / (float)G.ramp));
 }
 
+// Height profile of the inflow speed at cell z (h = z + 1/2 above the
+// half-way ground): uniform U; log-law (u* / 0.41) ln(h / z0); measured series
+// ln((h + z0) / z0), its normalisation and speed being in InflowT.
 __device__ __forceinline__ float inflow_speed(const Geo &G, int z)
 {
     if (G.inflow == 0) return G.speed;
-    return G.speed * KAPPA_INV * logf(((float)z + 0.5f) / G.z0);
+    if (G.inflow == 1) return G.speed * KAPPA_INV * logf(((float)z + 0.5f) / G.z0);
+    return logf(((float)z + 0.5f + G.z0) / G.z0);
+}
+
+// The time-dependent part of u_in at step n: u_in(z, n) = scale * profile(z) *
+// (cphi, sphi, 0).  base is scale without the speed parameter (ramp only for
+// the uniform and log-law kinds; ramp * U_H(n) / ln((H + z0)/z0) for the series).
+struct InflowT {
+    float scale, base, cphi, sphi;
+};
+
+// Reference speed and direction of the hourly series at step n: hour h starts
+// at step ramp + h * hour_steps and moves from hour h-1's values over its first
+// blend_steps steps with weight (1 - cos(pi t / blend_steps)) / 2, the
+// direction along the shorter arc; hour 0 before and during the ramp, the
+// last hour held after the series.
+__device__ __forceinline__ void series_at(const Geo &G, int64_t n, float &U, float &D)
+{
+    int32_t t = (int32_t)(n > (int64_t)G.ramp ? n - G.ramp : 0);
+    int32_t h = t / G.hour_steps;
+    int32_t tp = t - h * G.hour_steps;
+    if (h >= G.series_len) {
+        h = G.series_len - 1;
+        tp = G.hour_steps;
+    }
+    U = G.series[2 * h];
+    D = G.series[2 * h + 1];
+    if (h > 0 && tp < G.blend_steps) {
+        const float s = 0.5f * (1.0f - cosf(3.14159265358979323846f * (float)tp / (float)G.blend_steps));
+        const float U0 = G.series[2 * h - 2], D0 = G.series[2 * h - 1];
+        const float dD = remainderf(D - D0, 6.28318530717958647692f);
+        U = U0 + s * (U - U0);
+        D = D0 + s * dD;
+    }
+}
+
+__device__ __forceinline__ InflowT inflow_at(const Geo &G, int64_t n)
+{
+    const float r = ramp_factor(G, n);
+    if (G.inflow != 2) return InflowT{r, r, G.cphi, G.sphi};
+    float U, D;
+    series_at(G, n, U, D);
+    const float base = r * U * G.inv_log_h;
+    const float phi = D + G.phi;
+    return InflowT{base * G.speed, base, cosf(phi), sinf(phi)};
 }
 
 // 6 w_i c_i . u_in, the moving-wall momentum of link i.
-__device__ __forceinline__ float inlet_term(int i, float U, const Geo &G, float r)
+__device__ __forceinline__ float inlet_term(int i, float U, const InflowT &T)
 {
-    return 6.0f * wgt(i) * U * r * ((float)cx(i) * G.cphi + (float)cy(i) * G.sphi);
+    return 6.0f * wgt(i) * U * T.scale * ((float)cx(i) * T.cphi + (float)cy(i) * T.sphi);
 }
 
 __device__ __forceinline__ int probe_index(const Geo &G, int32_t c)
@@ -147,7 +194,7 @@ __device__ __forceinline__ Shape shape_of(const Geo &G)
 // post-collision values of step n-1, one compile-time direction at a time.
 template <bool NT = false, int... Is>
 __device__ __forceinline__ void gather_all(const Geo &G, const Shape &S, const Preds &p, uint32_t sm, uint32_t c,
-                                           float U, float r, float g[Q], std::integer_sequence<int, Is...>)
+                                           float U, const InflowT &T, float g[Q], std::integer_sequence<int, Is...>)
 {
     const GLOBAL_AS float *__restrict__ f = gp(G.f);
     const uint32_t qs = (uint32_t)G.qs;
@@ -155,7 +202,7 @@ __device__ __forceinline__ void gather_all(const Geo &G, const Shape &S, const P
         [&] {
             const RelLink l = gather_rel<Is>(S, p, sm);
             const float v = ldg<NT>(f, (uint32_t)l.slot * qs + (uint32_t)((int32_t)c + l.delta));
-            g[Is] = l.inlet ? v + inlet_term(Is, U, G, r) : v;
+            g[Is] = l.inlet ? v + inlet_term(Is, U, T) : v;
         }(),
         ...);
 }
@@ -164,7 +211,7 @@ __device__ __forceinline__ void gather_all(const Geo &G, const Shape &S, const P
 // link of the next (naturally stored) state.
 template <bool NT = false, int... Ks>
 __device__ __forceinline__ void scatter_all(const Geo &G, const Shape &S, const Preds &p, uint32_t sm, uint32_t c,
-                                            float U, float r, const float g[Q], std::integer_sequence<int, Ks...>)
+                                            float U, const InflowT &T, const float g[Q], std::integer_sequence<int, Ks...>)
 {
     GLOBAL_AS float *__restrict__ f = gp(G.f);
     const uint32_t qs = (uint32_t)G.qs;
@@ -173,7 +220,7 @@ __device__ __forceinline__ void scatter_all(const Geo &G, const Shape &S, const 
             RelLink a, e;
             scatter_rel<Ks>(S, p, sm, a, e);
             if (a.valid) {
-                const float v = a.inlet ? g[Ks] + inlet_term(opp(Ks), U, G, r) : g[Ks];
+                const float v = a.inlet ? g[Ks] + inlet_term(opp(Ks), U, T) : g[Ks];
                 stg<NT>(f, (uint32_t)a.slot * qs + (uint32_t)((int32_t)c + a.delta), v);
             }
             if (e.valid) stg<NT>(f, (uint32_t)e.slot * qs + (uint32_t)((int32_t)c + e.delta), g[Ks]);
@@ -203,7 +250,7 @@ __device__ __forceinline__ void load_state(const Geo &G, uint32_t c, uint8_t fl,
         const Preds p = preds_of(S, x, y, z);
         const uint32_t sm = gp(G.smask)[c];
         const float U = (fl & FL_INLET) ? inflow_speed(G, z) : 0.0f;
-        gather_all(G, S, p, sm, c, U, ramp_factor(G, n - 1), g, Dirs{});
+        gather_all(G, S, p, sm, c, U, inflow_at(G, n - 1), g, Dirs{});
     }
 }
 
@@ -498,10 +545,10 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
 #pragma unroll
             for (int i = 0; i < Q; ++i) g[j][i] = ldg<NT>(f + (size_t)opp(i) * qs - off_of(G, i), c[j]);
         } else if (general_wave[j]) {
-            gather_all<NT>(G, S, pr[j], sm[j], c[j], U[j], ramp_factor(G, a.step - 1), g[j], Dirs{});
+            gather_all<NT>(G, S, pr[j], sm[j], c[j], U[j], inflow_at(G, a.step - 1), g[j], Dirs{});
         } else {
             const Preds px{pr[j].xlo, pr[j].xhi, false, false, false, false};
-            gather_all<NT>(G, S, px, 0u, c[j], U[j], ramp_factor(G, a.step - 1), g[j], Dirs{});
+            gather_all<NT>(G, S, px, 0u, c[j], U[j], inflow_at(G, a.step - 1), g[j], Dirs{});
         }
     }
 #pragma unroll
@@ -553,10 +600,10 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
 #pragma unroll
             for (int i = 0; i < Q; ++i) stg<NT>(f + (size_t)i * qs + off_of(G, i), c[j], g[j][i]);
         } else if (general_wave[j]) {
-            scatter_all<NT>(G, S, pr[j], sm[j], c[j], U[j], ramp_factor(G, a.step), g[j], Dirs{});
+            scatter_all<NT>(G, S, pr[j], sm[j], c[j], U[j], inflow_at(G, a.step), g[j], Dirs{});
         } else {
             const Preds px{pr[j].xlo, pr[j].xhi, false, false, false, false};
-            scatter_all<NT>(G, S, px, 0u, c[j], U[j], ramp_factor(G, a.step), g[j], Dirs{});
+            scatter_all<NT>(G, S, px, 0u, c[j], U[j], inflow_at(G, a.step), g[j], Dirs{});
         }
     }
 }
@@ -570,22 +617,31 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// d u_in / d theta_t . c for link i at height z: (c . dir) dU/dtheta_t for
-// speed and z0, U (c . d dir / d phi) for the direction.
-__device__ __forceinline__ void inflow_dtheta(const Geo &G, int z, int i, float out[3])
+// c_i . d u_in / d theta_t for link i at height z and step n (T = inflow_at(n),
+// ramp included): (c . dir) dU/dtheta_t for the speed parameter and z0,
+// U (c . d dir / d phi) for the direction.
+__device__ __forceinline__ void inflow_dtheta(const Geo &G, int z, int i, const InflowT &T, float out[3])
 {
-    const float cd = (float)cx(i) * G.cphi + (float)cy(i) * G.sphi;
-    const float cdd = -(float)cx(i) * G.sphi + (float)cy(i) * G.cphi;
+    const float cd = (float)cx(i) * T.cphi + (float)cy(i) * T.sphi;
+    const float cdd = -(float)cx(i) * T.sphi + (float)cy(i) * T.cphi;
     if (G.inflow == 0) {
-        out[0] = cd;
-        out[1] = G.speed * cdd;
+        out[0] = T.base * cd;
+        out[1] = T.base * G.speed * cdd;
         out[2] = 0.0f;
-    } else {
+    } else if (G.inflow == 1) {
         const float L = logf(((float)z + 0.5f) / G.z0);
         const float U = G.speed * KAPPA_INV * L;
-        out[0] = KAPPA_INV * L * cd;
-        out[1] = U * cdd;
-        out[2] = -G.speed * KAPPA_INV / G.z0 * cd;
+        out[0] = T.base * KAPPA_INV * L * cd;
+        out[1] = T.base * U * cdd;
+        out[2] = -T.base * G.speed * KAPPA_INV / G.z0 * cd;
+    } else {
+        // u = base zeta1 A / B-normalised: A = ln((h + z0)/z0), 1/B in base
+        const float h = (float)z + 0.5f;
+        const float A = logf((h + G.z0) / G.z0);
+        const float dA = 1.0f / (h + G.z0) - 1.0f / G.z0;
+        out[0] = T.base * A * cd;
+        out[1] = T.scale * A * cdd;
+        out[2] = T.scale * (dA - A * G.dlog_h * G.inv_log_h) * cd;
     }
 }
 
@@ -593,7 +649,8 @@ __device__ __forceinline__ void inflow_dtheta(const Geo &G, int z, int i, float 
 // inflow-parameter gradient of the moving-wall links among them.
 template <int... Ks>
 __device__ __forceinline__ void adjoint_gather(const Geo &G, const Shape &S, const Preds &p, uint32_t sm, uint32_t c,
-                                               int z, float r, const GLOBAL_AS float *__restrict__ lin, float mu[Q],
+                                               int z, const InflowT &T, const GLOBAL_AS float *__restrict__ lin,
+                                               float mu[Q],
                                                double &gr0,
                                                double &gr1, double &gr2, std::integer_sequence<int, Ks...>)
 {
@@ -610,8 +667,8 @@ __device__ __forceinline__ void adjoint_gather(const Geo &G, const Shape &S, con
                 if (a.inlet) {
                     float dt[3];
                     constexpr int q = opp(Ks);
-                    inflow_dtheta(G, z, q, dt);
-                    const double f6 = 6.0 * (double)wgt(q) * (double)r * (double)l;
+                    inflow_dtheta(G, z, q, T, dt);
+                    const double f6 = 6.0 * (double)wgt(q) * (double)l;
                     gr0 += f6 * dt[0];
                     gr1 += f6 * dt[1];
                     gr2 += f6 * dt[2];
@@ -642,7 +699,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
     const GLOBAL_AS float *__restrict__ lin = gp(a.lam_in[ii]);
     GLOBAL_AS float *__restrict__ lout = gp(a.lam_out[ii]);
     const int32_t base = (tile - G.tile0) * (BS * CPT) + (int32_t)threadIdx.x;
-    const float r = ramp_factor(G, a.step);
+    const InflowT T = inflow_at(G, a.step);
     double gr0 = 0.0, gr1 = 0.0, gr2 = 0.0;
     bool inlet_lane = false;
 
@@ -683,11 +740,11 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
             coords(G, c[j], x, y, z);
             const Preds pr = preds_of(S, x, y, z);
             const uint32_t sm = gp(G.smask)[c[j]];
-            adjoint_gather(G, S, pr, sm, c[j], z, r, lin, mu[j], gr0, gr1, gr2, Dirs{});
+            adjoint_gather(G, S, pr, sm, c[j], z, T, lin, mu[j], gr0, gr1, gr2, Dirs{});
         } else {
             const Preds px{(fl[j] & FL_XLO) != 0, (fl[j] & FL_XHI) != 0, false, false, false, false};
             const int z = (fl[j] & FL_INLET) ? (int)fdiv(c[j], G.dxy) : 0;
-            adjoint_gather(G, S, px, 0u, c[j], z, r, lin, mu[j], gr0, gr1, gr2, Dirs{});
+            adjoint_gather(G, S, px, 0u, c[j], z, T, lin, mu[j], gr0, gr1, gr2, Dirs{});
         }
         if (a.record != 1) {
             const GLOBAL_AS float *rp = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)Q * G.qs;

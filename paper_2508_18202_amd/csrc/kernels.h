@@ -24,12 +24,18 @@ struct Geo {
     int32_t offy, offz;        // linear offsets of +y and +z neighbours
     FastDiv dx, dxy;           // division by nx and nx*ny
     int32_t tile0;             // first tile of this instance in the flattened list
-    int32_t inflow;            // 0 uniform, 1 log-law
+    int32_t inflow;            // 0 uniform, 1 log-law, 2 measured series
     float tau0;
     float kcs;                 // 18 sqrt(2) Cs^2
     float speed, cphi, sphi, phi, z0;
     int32_t ramp;
     int32_t pad_;
+    // measured series: [series_len][2] (U_H, Theta), hour length, blend length,
+    // 1 / ln((H + z0) / z0) of the normalised log profile
+    const float *series;
+    int32_t series_len, hour_steps, blend_steps;
+    float inv_log_h;
+    float dlog_h;              // d ln((H + z0) / z0) / d z0 = 1 / (H + z0) - 1 / z0
 };
 
 // Launch arguments that change from step to step.

@@ -140,7 +140,7 @@ struct lbm_plan {
     int64_t avg_begin = 0, avg_end = 0;
     int pending = 0;             // states accumulated in the FP32 partials since the last flush
     int flush_every = 64;
-    int ramp_max = 0;
+    int64_t steady_from = 0;     // from this step on every instance's inflow is constant in time
     bool use_graph = false;
     hipGraphExec_t gexec = nullptr;
     int graph_pairs = 8;
@@ -182,6 +182,31 @@ void set_theta(Geo &g, const lbm_instance &in)
     g.cphi = std::cos(in.theta[1]);
     g.sphi = std::sin(in.theta[1]);
     g.z0 = in.theta[2];
+    g.series = nullptr;
+    g.series_len = g.hour_steps = g.blend_steps = 0;
+    g.inv_log_h = g.dlog_h = 0.0f;
+    if (in.inflow == LBM_INFLOW_SERIES) {
+        g.series = in.series_dev;
+        g.series_len = in.series_len;
+        g.hour_steps = in.hour_steps;
+        g.blend_steps = in.blend_steps;
+        const double H = in.ref_height, z0 = in.theta[2];
+        g.inv_log_h = (float)(1.0 / std::log((H + z0) / z0));
+        g.dlog_h = (float)(1.0 / (H + z0) - 1.0 / z0);
+    }
+}
+
+// parameters of an instance's inflow that the kernels rely on
+int check_inflow(const lbm_instance &in, const float theta[3])
+{
+    if (in.inflow == LBM_INFLOW_LOGLAW && !(theta[2] > 0.0f)) return fail(LBM_E_INVALID, "z0 must be positive");
+    if (in.inflow != LBM_INFLOW_SERIES) return LBM_OK;
+    if (!(theta[2] > 0.0f)) return fail(LBM_E_INVALID, "z0 must be positive");
+    if (!in.series_dev || in.series_len < 1 || in.hour_steps < 1 || in.blend_steps < 0 ||
+        in.blend_steps > in.hour_steps || !(in.ref_height > 0.0f))
+        return fail(LBM_E_INVALID, "series inflow: need a series, series_len >= 1, hour_steps >= 1, "
+                                   "0 <= blend_steps <= hour_steps and ref_height > 0");
+    return LBM_OK;
 }
 
 // device copy of a host array of pointers, cached by content
@@ -223,7 +248,7 @@ int ensure_graph(lbm_plan *p)
     hipStream_t cap;
     HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     StepArgs a{};
-    a.step = (p->ramp_max + 1) / 2 * 2 + 2;
+    a.step = (p->steady_from + 1) / 2 * 2 + 2;
     HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < p->graph_pairs; ++k) {
         launch_step(p->v, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, cap);
@@ -240,7 +265,7 @@ int ensure_graph(lbm_plan *p)
 bool pair_plain(const lbm_plan *p, int64_t n)
 {
     for (int64_t m = n; m < n + 2; ++m) {
-        if (m < p->ramp_max) return false;
+        if (m < p->steady_from) return false;
         if (p->avg_end > p->avg_begin && m >= p->avg_begin && m < p->avg_end + 1) return false;
     }
     return true;
@@ -499,8 +524,10 @@ int lbm_plan_create(const lbm_instance *inst, int32_t n_inst, const lbm_plan_opt
             r = fail(LBM_E_INVALID, "instance %d: unknown model", i);
         if (!r && !(in.tau0 > 0.5f)) r = fail(LBM_E_INVALID, "instance %d: tau0 must exceed 1/2 (got %g)", i, in.tau0);
         if (!r && !(in.cs >= 0.0f)) r = fail(LBM_E_INVALID, "instance %d: negative Smagorinsky constant", i);
-        if (!r && in.inflow != LBM_INFLOW_UNIFORM && in.inflow != LBM_INFLOW_LOGLAW)
+        if (!r && in.inflow != LBM_INFLOW_UNIFORM && in.inflow != LBM_INFLOW_LOGLAW &&
+            in.inflow != LBM_INFLOW_SERIES)
             r = fail(LBM_E_INVALID, "instance %d: unknown inflow kind", i);
+        if (!r) r = check_inflow(in, in.theta);
         if (!r && in.inflow == LBM_INFLOW_LOGLAW && !(in.theta[2] > 0.0f))
             r = fail(LBM_E_INVALID, "instance %d: log-law roughness z0 must be positive", i);
         if (!r && ((in.qoi_part_dev == nullptr) != (in.qoi_sum_dev == nullptr)))
@@ -533,7 +560,12 @@ int lbm_plan_create(const lbm_instance *inst, int32_t n_inst, const lbm_plan_opt
         g.kcs = in.model != LBM_BGK ? (float)(18.0 * std::sqrt(2.0) * in.cs * in.cs) : 0.0f;
         g.ramp = in.ramp;
         set_theta(g, in);
-        p->ramp_max = std::max(p->ramp_max, in.ramp);
+        // the inflow is time-dependent during the ramp and, for a measured
+        // series, until the blend into its last hour has ended
+        int64_t steady = in.ramp;
+        if (in.inflow == LBM_INFLOW_SERIES)
+            steady += (int64_t)(in.series_len - 1) * in.hour_steps + in.blend_steps;
+        p->steady_from = std::max(p->steady_from, steady);
     }
     if (hipMalloc(&p->geo_d, sizeof(Geo) * n_inst) != hipSuccess ||
         hipMalloc(&p->health_d, sizeof(int32_t) * n_inst) != hipSuccess ||
@@ -580,7 +612,8 @@ int lbm_plan_set_theta(lbm_plan *p, int32_t i, const float theta[3])
     int r = check_plan(p);
     if (r) return r;
     if (i < 0 || i >= p->n_inst || !theta) return fail(LBM_E_INVALID, "bad instance index or theta");
-    if (p->inst[i].inflow == LBM_INFLOW_LOGLAW && !(theta[2] > 0.0f)) return fail(LBM_E_INVALID, "z0 must be positive");
+    r = check_inflow(p->inst[i], theta);
+    if (r) return r;
     for (int k = 0; k < 3; ++k) p->inst[i].theta[k] = theta[k];
     set_theta(p->geo_h[i], p->inst[i]);
     HIPCHK(hipDeviceSynchronize());
@@ -816,7 +849,7 @@ int lbm_plan_autotune(lbm_plan *p, hipStream_t s, int32_t variant_out[4])
             int rc = build_tiles(p);
             if (rc) return rc;
             StepArgs a{};
-            a.step = p->ramp_max + 2;
+            a.step = p->steady_from + 2;
             for (int w = 0; w < 2 + pairs; ++w) {
                 if (w == 2) HIPCHK(hipEventRecord(e0, s));
                 launch_step(v, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);

@@ -22,8 +22,8 @@ WALL, INLET, OUTLET, FREESLIP, PERIODIC = 0, 1, 2, 3, 4
 FACES = {"wall": WALL, "inlet": INLET, "outlet": OUTLET, "freeslip": FREESLIP, "periodic": PERIODIC}
 BGK, SMAGORINSKY, RR3 = 0, 1, 2
 MODELS = {"bgk": BGK, "smagorinsky": SMAGORINSKY, "rr3": RR3}
-INFLOW_UNIFORM, INFLOW_LOGLAW = 0, 1
-INFLOWS = {"uniform": INFLOW_UNIFORM, "loglaw": INFLOW_LOGLAW}
+INFLOW_UNIFORM, INFLOW_LOGLAW, INFLOW_SERIES = 0, 1, 2
+INFLOWS = {"uniform": INFLOW_UNIFORM, "loglaw": INFLOW_LOGLAW, "series": INFLOW_SERIES}
 QUAD_GAUSS_LEGENDRE, QUAD_SMOLYAK_CC = 0, 1
 QUADS = {"gauss_legendre": QUAD_GAUSS_LEGENDRE, "smolyak_cc": QUAD_SMOLYAK_CC}
 RECORD_MACROS, RECORD_POPULATIONS = 1, 2
@@ -45,7 +45,10 @@ class lbm_instance(ctypes.Structure):
                 ("f_dev", ctypes.c_void_p), ("model", ctypes.c_int32), ("tau0", ctypes.c_float),
                 ("cs", ctypes.c_float), ("inflow", ctypes.c_int32), ("theta", ctypes.c_float * 3),
                 ("ramp", ctypes.c_int32), ("qoi_part_dev", ctypes.c_void_p),
-                ("qoi_sum_dev", ctypes.c_void_p), ("probe_sum_dev", ctypes.c_void_p)]
+                ("qoi_sum_dev", ctypes.c_void_p), ("probe_sum_dev", ctypes.c_void_p),
+                ("series_dev", ctypes.c_void_p), ("series_len", ctypes.c_int32),
+                ("hour_steps", ctypes.c_int32), ("blend_steps", ctypes.c_int32),
+                ("ref_height", ctypes.c_float)]
 
 
 class lbm_plan_opts(ctypes.Structure):

@@ -80,8 +80,13 @@ class Ensemble:
         self.avg_begin, self.avg_end = avg_begin, avg_end
         window = avg_end > avg_begin
         insts = []
+        self.series: List[Optional[torch.Tensor]] = []   # per case: hourly series on the device
         for ci, (cg, ths) in enumerate(zip(self.cases, thetas)):
             w = cg.w
+            ser = None
+            if w.inflow == "series":
+                ser = torch.tensor(w.series, dtype=torch.float32, device="cuda").reshape(-1).contiguous()
+            self.series.append(ser)
             for j, th in enumerate(ths):
                 f = torch.empty(19 * cg.qs, dtype=torch.float32, device="cuda")
                 init_populations(cg, f)
@@ -106,6 +111,12 @@ class Ensemble:
                 inst.qoi_part_dev = qp.data_ptr() if qp is not None else None
                 inst.qoi_sum_dev = qsm.data_ptr() if qsm is not None else None
                 inst.probe_sum_dev = ps.data_ptr() if ps is not None else None
+                if ser is not None:
+                    inst.series_dev = ser.data_ptr()
+                    inst.series_len = len(w.series)
+                    inst.hour_steps = w.hour_steps
+                    inst.blend_steps = w.blend_steps
+                    inst.ref_height = w.ref_height
                 insts.append(inst)
                 self.index.append((ci, j))
                 self.f.append(f)

@@ -21,7 +21,8 @@ def per_channel_rel(gpu_c4, ora_4c, fluid):
 
 
 def oracle_case(w, solid, theta, **over):
-    kw = dict(model=w.model, tau0=w.tau0, cs=w.cs, inflow=w.inflow, theta=theta, ramp=w.ramp)
+    kw = dict(model=w.model, tau0=w.tau0, cs=w.cs, inflow=w.inflow, theta=theta, ramp=w.ramp,
+              series=w.series, hour_steps=w.hour_steps, blend_steps=w.blend_steps, ref_height=w.ref_height)
     kw.update(over)
     return orc.Case(w.nx, w.ny, w.nz, list(w.faces), solid, **kw)
 

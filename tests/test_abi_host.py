@@ -12,6 +12,7 @@
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -234,3 +235,25 @@ def test_tile_orders_are_permutations(mode):
         out = np.empty(grid, np.int32)
         hostcheck().lbmhc_tile_order(grid, mode, out.ctypes.data_as(ctypes.c_void_p))
         assert np.array_equal(np.sort(out), np.arange(grid)), (mode, n_tiles)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the ABI structs have the header's size and field
+    offsets (a C probe compiled against include/lbm_sc.h prints them)."""
+    structs = {"lbm_domain": L.lbm_domain, "lbm_instance": L.lbm_instance, "lbm_plan_opts": L.lbm_plan_opts}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm_sc.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for field, *_ in cls._fields_:
+            lines.append(f'printf("{name}.{field} %zu\\n", offsetof({name}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-D__HIP_PLATFORM_AMD__", f"-I{os.path.join(ROOT, 'include')}",
+                           "-I/opt/rocm/include", str(src), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for field, *_ in cls._fields_:
+            assert int(got[f"{name}.{field}"]) == getattr(cls, field).offset, (name, field)

@@ -114,6 +114,18 @@ def test_autograd_wrapper_matches_direct_adjoint():
         ens.close()
 
 
+def test_adjoint_series_inflow():
+    """Gradient w.r.t. (speed multiplier, direction offset, z0) of the
+    hourly-series inflow (hours of 20 steps, blends of 8, ramp 10) against the
+    oracle adjoint."""
+    w = inputs.scaled(inputs.urban_series(hours=4, hour_steps=20, blend_steps=8), 20, 10, 10,
+                      model="smagorinsky", cs=0.1, tau0=0.56, ramp=10, ref_height=10.0)
+    solid = np.zeros((w.nz, w.ny, w.nx), np.uint8)
+    solid[0:5, 3:7, 6:10] = 1
+    thetas = [(1.05, 0.03, 0.1), (0.93, -0.06, 0.12), (1.0, 0.0, 0.1)]
+    _compare(w, solid, thetas, 90, 60, 30, "series adjoint")
+
+
 def test_adjoint_rejects_the_regularised_model():
     """The adjoint kernels cover BGK and Smagorinsky; a plan of the
     regularised model is refused with LBM_E_UNSUPPORTED before any launch."""

@@ -314,6 +314,91 @@ def test_unstable_instance_is_isolated():
         ref.close()
 
 
+def test_series_inflow_step_by_step():
+    """Time-dependent inflow from an hourly series (short hours: ramp 2, three
+    steps per hour, two blending steps): populations after every hour change
+    and into the held tail, against the oracle."""
+    _say("series inflow step-by-step")
+    w = inputs.scaled(inputs.urban_series(hours=4, hour_steps=3, blend_steps=2), 24, 12, 10, ramp=2,
+                      tau0=0.56, ref_height=10.0)
+    solid = np.zeros((w.nz, w.ny, w.nx), np.uint8)
+    solid[0:5, 3:7, 7:11] = 1
+    theta = (1.06, math.radians(3.0), 0.1)
+    ens, cg = _ensemble(w, solid, [theta])
+    case = oracle_case(w, solid, theta)
+    f = case.init()
+    _, wl, _ = orc.lattice()
+    fluid = cg.fluid
+    done = 0
+    try:
+        for target in (1, 3, 5, 6, 7, 9, 12, 17):
+            ens.advance(target - done)
+            while done < target:
+                f = case.step(done, f)
+                done += 1
+            g = ens.populations(0).cpu().numpy().astype(np.float64)
+            ref = f - wl[:, None]
+            err = np.abs(g[:, fluid] - ref[:, fluid]).max()
+            assert err <= 1e-5 * np.abs(ref[:, fluid]).max() + 1e-9, (target, err)
+    finally:
+        ens.close()
+
+
+def test_series_graph_replay_matches_launches():
+    """Graph replay starts only once the series inflow is constant: through
+    the hours and into the held tail, graphs and plain launches agree bit for
+    bit."""
+    w = inputs.scaled(inputs.urban_series(hours=3, hour_steps=24, blend_steps=10), 64, 32, 24, ramp=12,
+                      ref_height=24.0)
+    solid = inputs.solid_mask(w)
+    _, _, th = sc.collocation(w)
+    outs = []
+    for graph in (False, True):
+        ens, _ = _ensemble(w, solid, th[:2], variant=(128, 2, 1, 0), use_graph=graph)
+        try:
+            got = []
+            for n in (40, 96, 140):
+                ens.advance(n - L.lbm_plan_step(ens.plan))
+                got.append([ens.populations(i).cpu().numpy() for i in range(2)])
+            outs.append(got)
+        finally:
+            ens.close()
+    for a, b in zip(*outs):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_series_urban_short_horizon():
+    """The urban recipe driven by an hourly series (13 Smolyak nodes on the
+    speed multiplier and direction offset), 200 steps with an hour every 40
+    steps, averages over the last 50: fields and moments against the oracle."""
+    w = inputs.scaled(inputs.urban_series(hours=6, hour_steps=40, blend_steps=15), 64, 32, 24, ramp=20,
+                      steps=200, avg_start=150, ref_height=24.0)
+    solid = inputs.solid_mask(w)
+    _say("series urban short: GPU")
+    r = sc.run_sc(w, solid)
+    ens = r["ensemble"]
+    try:
+        q = r["q"].cpu().numpy()
+        fluid = r["geometry"].fluid
+        x, a = orc.collocation(w)
+        qo = []
+        for j, xi in enumerate(x):
+            th = orc.node_params(w, xi)
+            res = orc.run(oracle_case(w, solid, th), w.steps, avg_start=w.avg_start)
+            qo.append(res["avg"])
+            errs = per_channel_rel(q[j], res["avg"], fluid)
+            assert max(errs) < FIELD_TOL, (j, errs)
+        eo, vo = orc.moments(np.stack(qo), a)
+        mean = r["mean"].cpu().numpy().T
+        var = r["var"].cpu().numpy().T
+        for k in range(4):
+            assert rel_l2(mean[k], eo[k], fluid) < MOMENT_TOL
+            assert rel_l2(np.sqrt(np.maximum(var[k], 0)), np.sqrt(np.maximum(vo[k], 0)), fluid) < MOMENT_TOL
+    finally:
+        ens.close()
+
+
 def test_rr3_urban_short_horizon():
     """The regularised third-order collision with the Smagorinsky tau_eff on
     the urban recipe (64x32x24, 13 Smolyak nodes, log-law inflow), 200 steps,
