@@ -215,6 +215,23 @@ def smolyak_cc(level: int, dim: int):
     return np.array([pts[k] for k in keys]), np.array([acc[k] for k in keys])
 
 
+def gauss_hermite(n: int):
+    """n-point Gauss-Hermite rule for z ~ N(0, 1) (probabilists' polynomials):
+    numpy's hermegauss nodes, weights divided by their sum sqrt(2 pi)."""
+    x, w = np.polynomial.hermite_e.hermegauss(n)
+    return x, w / w.sum()
+
+
+def tensor_gauss_hermite(n: int, dim: int):
+    """Dense tensor product of the n-point rule (Sec. 3): node (i_1 .. i_d)
+    in lexicographic order (last coordinate fastest), weight the product."""
+    x, w = gauss_hermite(n)
+    idx = list(itertools.product(range(n), repeat=dim))
+    nodes = np.array([[x[i] for i in t] for t in idx])
+    weights = np.array([np.prod([w[i] for i in t]) for t in idx])
+    return nodes, weights
+
+
 def collocation(w) -> tuple:
     """(nodes [N_q, d], weights [N_q]) of a workload's collocation rule."""
     if w.quadrature == "gauss_legendre":
@@ -222,7 +239,65 @@ def collocation(w) -> tuple:
         return x.reshape(-1, 1), a
     if w.quadrature == "smolyak_cc":
         return smolyak_cc(w.quad_level, w.quad_dim)
+    if w.quadrature == "gauss_hermite":
+        return tensor_gauss_hermite(w.quad_level, w.quad_dim)
     raise ValueError(w.quadrature)
+
+
+# --------------------------------------------------------------------------- gPC
+
+def gpc_multi_indices(dim: int, order: int) -> np.ndarray:
+    """Multi-indices of total degree <= order, graded (degree 0, 1, ...),
+    within a degree the first variable's power descending."""
+    out = []
+    for deg in range(order + 1):
+        def rec(prefix, left, k):
+            if k == dim - 1:
+                out.append(prefix + [left])
+                return
+            for a in range(left, -1, -1):
+                rec(prefix + [a], left - a, k + 1)
+        rec([], deg, 0)
+    return np.array(out, dtype=np.int64).reshape(-1, dim)
+
+
+def hermite_he(n: int, z: np.ndarray) -> np.ndarray:
+    """Probabilists' Hermite polynomial He_n(z) by He_{k+1} = z He_k - k He_{k-1}."""
+    z = np.asarray(z, dtype=np.float64)
+    h0, h1 = np.ones_like(z), z.copy()
+    if n == 0:
+        return h0
+    for k in range(1, n):
+        h0, h1 = h1, z * h1 - k * h0
+    return h1
+
+
+def gpc_basis(nodes: np.ndarray, order: int):
+    """Phi [N_q, P] of the orthonormal Hermite chaos prod_k He_{a_k}(z_k)/sqrt(a_k!)
+    at the nodes, and the multi-indices [P, d]."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    alpha = gpc_multi_indices(nodes.shape[1], order)
+    phi = np.ones((nodes.shape[0], alpha.shape[0]))
+    for p, a in enumerate(alpha):
+        for k, ak in enumerate(a):
+            phi[:, p] *= hermite_he(int(ak), nodes[:, k]) / math.sqrt(math.factorial(int(ak)))
+    return phi, alpha
+
+
+def gpc(q: np.ndarray, nodes: np.ndarray, weights: np.ndarray, order: int) -> dict:
+    """gPC coefficients by projection with the collocation rule (Sec. 2.3):
+    c_alpha = sum_j a_j Q_j Phi_alpha(Z^(j)); mean c_0, variance
+    sum_{alpha != 0} c_alpha^2, 95 % band mean -+ 1.96 std (float64)."""
+    q = np.asarray(q, dtype=np.float64)
+    phi, alpha = gpc_basis(nodes, order)
+    coef = np.zeros((phi.shape[1],) + q.shape[1:])
+    for j in range(q.shape[0]):
+        for p in range(phi.shape[1]):
+            coef[p] += weights[j] * phi[j, p] * q[j]
+    var = (coef[1:] ** 2).sum(0)
+    sd = np.sqrt(var)
+    return {"coef": coef, "alpha": alpha, "mean": coef[0], "var": var,
+            "band": np.stack([coef[0] - 1.96 * sd, coef[0] + 1.96 * sd])}
 
 
 def node_params(w, xi: Sequence[float]) -> np.ndarray:

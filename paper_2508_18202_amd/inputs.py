@@ -149,6 +149,8 @@ def probe_cells(w: Workload, mask: np.ndarray) -> np.ndarray:
     * "points": an 8 x 8 grid at z = 10 over the building region; a probe that
       lands in a solid cell moves to the nearest fluid cell of that plane
       (smallest squared distance, ties broken by smaller y, then smaller x).
+    * "lines": vertical profiles, the fluid cells of the four columns
+      x in {3nx/8, 5nx/8}, y in {ny/4, 3ny/4}.
     """
     nx, ny, nz = w.nx, w.ny, w.nz
     if w.probe_kind is None:
@@ -179,6 +181,16 @@ def probe_cells(w: Workload, mask: np.ndarray) -> np.ndarray:
                 order = np.lexsort((fx, fy, d2))
                 k = order[0]
                 out.append((zp * ny + int(fy[k])) * nx + int(fx[k]))
+        return np.sort(np.asarray(out, dtype=np.int64))
+    if w.probe_kind == "lines":
+        # vertical profiles (the paper's probe lines): four columns at
+        # x in {3nx/8, 5nx/8}, y in {ny/4, 3ny/4}, every fluid cell of z
+        out = []
+        for px in ((3 * nx) // 8, (5 * nx) // 8):
+            for py in (ny // 4, (3 * ny) // 4):
+                for z in range(nz):
+                    if not mask[z, py, px]:
+                        out.append((z * ny + py) * nx + px)
         return np.sort(np.asarray(out, dtype=np.int64))
     raise ValueError(f"unknown probe kind {w.probe_kind!r}")
 
@@ -282,6 +294,19 @@ def urban_series(hours: int = 8, hour_steps: int = 500, blend_steps: int = 100) 
                     seed_base=6000, buildings=(6, 4),
                     series=hourly_series(hours, 6000), hour_steps=hour_steps, blend_steps=blend_steps,
                     ref_height=float(nz))
+
+
+def urban_gpc(hours: int = 8, hour_steps: int = 500, blend_steps: int = 100) -> Workload:
+    """The paper's stochastic set-up on the urban box: zeta_1 ~ N(1, 0.1^2) on
+    the hourly speeds and zeta_2 ~ N(0, (6 deg)^2) on the directions, dense
+    11 x 11 Gauss-Hermite rule (121 nodes), normalised log profile with
+    z0 = 0.1 cells and H = nz, time-averaged u_x on vertical probe lines for
+    the gPC expansion (order 5)."""
+    w = urban_series(hours, hour_steps, blend_steps)
+    steps = w.steps
+    return dataclasses.replace(w, name="urban_gpc_256x128x64", quadrature="gauss_hermite", quad_level=11,
+                               quad_dim=2, avg_start=steps - hours * hour_steps // 2, probe_kind="lines",
+                               seed_base=7000, series=hourly_series(hours, 7000))
 
 
 def scaled(w: Workload, nx: int, ny: int, nz: int, **kw) -> Workload:
