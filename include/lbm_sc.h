@@ -96,7 +96,7 @@ enum { LBM_BGK = 0, LBM_SMAGORINSKY = 1, LBM_RR3 = 2 };
 enum { LBM_INFLOW_UNIFORM = 0, LBM_INFLOW_LOGLAW = 1, LBM_INFLOW_SERIES = 2 };
 
 /* Collocation rules (Sec. 2.3, Eq. coef_discrete / quad_moments). */
-enum { LBM_QUAD_GAUSS_LEGENDRE = 0, LBM_QUAD_SMOLYAK_CC = 1 };
+enum { LBM_QUAD_GAUSS_LEGENDRE = 0, LBM_QUAD_SMOLYAK_CC = 1, LBM_QUAD_GAUSS_HERMITE = 2 };
 
 typedef struct lbm_domain {
     int32_t nx, ny, nz;
@@ -154,14 +154,19 @@ const char *lbm_version(void);
 
 /* ------------------------------------------------------- collocation (a1/a2)
  * lbm_quadrature: nodes [n][dim] (row-major) and probability weights [n] of
- *   LBM_QUAD_GAUSS_LEGENDRE (level = number of points, dim must be 1; xi ~ U(-1,1))
- *   or LBM_QUAD_SMOLYAK_CC (level L >= 0, dim >= 1; nested Clenshaw-Curtis
- *   rules with 1, 3, 5, 9, ... points, combination technique).
+ *   LBM_QUAD_GAUSS_LEGENDRE (level = number of points, dim must be 1; xi ~ U(-1,1)),
+ *   LBM_QUAD_SMOLYAK_CC (level L >= 0, dim >= 1; nested Clenshaw-Curtis
+ *   rules with 1, 3, 5, 9, ... points, combination technique) or
+ *   LBM_QUAD_GAUSS_HERMITE (level = points per dimension, dim >= 1; the dense
+ *   tensor-product rule for z ~ N(0, 1)^d of Sec. 3, node j = (i_1 .. i_d)
+ *   with the last coordinate fastest; at most 65536 nodes).
  *   Returns the node count through *n_out.  With nodes_host == NULL only the
  *   count is returned.  cap = capacity of the output arrays in nodes.
  * lbm_node_params: theta = (base*(1 + rel*xi_1), radians(angle_deg*xi_2), z0)
  *   -- the multiplicative speed perturbation and additive direction
- *   perturbation of Sec. 3 with uniform xi (dim 1: no direction term). */
+ *   perturbation of Sec. 3 (dim 1: no direction term); with Gaussian nodes,
+ *   base 1, rel sigma_1 and angle_deg sigma_2 give zeta_1 ~ N(1, sigma_1^2)
+ *   and zeta_2 ~ N(0, sigma_2^2). */
 int lbm_quadrature(int32_t kind, int32_t level, int32_t dim, double *nodes_host,
                    double *weights_host, int32_t cap, int32_t *n_out);
 int lbm_node_params(const double *xi_host, int32_t dim, double base, double rel,
@@ -251,6 +256,32 @@ int lbm_qoi_average(lbm_plan *plan, int32_t inst, float *out_dev, float *probe_o
 int lbm_sc_moments(const float *q_dev, const double *w_host, int32_t n_nodes, int64_t n_elems,
                    double *mean_dev, double *var_dev, unsigned long long *n_negative_dev,
                    hipStream_t stream);
+
+/* ------------------------------------------- gPC coefficients (NEXT f2)
+ * Sec. 2.3: the expansion of a QoI in polynomials orthonormal under the
+ * input distribution, coefficients by projection with the collocation rule,
+ * c_alpha = sum_j a_j Q_j Phi_alpha(Z^(j)); for Gaussian inputs the
+ * probabilists' Hermite polynomials, Phi_alpha(z) = prod_k He_{alpha_k}(z_k)
+ * / sqrt(alpha_k!).  Mean c_0, variance sum_{alpha != 0} c_alpha^2.
+ * lbm_gpc_basis (host): the P multi-indices of total degree <= order in dim
+ *   variables (graded: degree 0, 1, ...; within a degree the first
+ *   variable's power descending) into alpha_out[P][dim], and
+ *   phi_out[j][p] = Phi_alpha_p(nodes[j]) for the n_nodes nodes [n][dim].
+ *   P is returned through *n_basis; with phi_out == NULL only the count.
+ *   cap = capacity of phi_out in rows of P values.
+ * lbm_gpc_coefficients (device, FP64): coef[p][e] = sum_j wphi[j][p] q[j][e]
+ *   for the node-major FP32 input q_dev[n_nodes][n_elems] and the weighted
+ *   basis wphi_dev[n_nodes][n_basis] = a_j Phi_p(Z^(j)) (device, caller
+ *   owned); coef_dev [n_basis][n_elems].  Optional (may be NULL), with basis
+ *   row 0 the constant polynomial as lbm_gpc_basis orders it:
+ *   var_dev[e] = sum_{p >= 1} coef[p][e]^2 and the 95 % band
+ *   band_dev[0][e] = coef[0][e] - 1.96 sqrt(var), band_dev[1][e] = coef[0][e] + 1.96 sqrt(var).
+ *   Rejected: n_nodes < 1, n_basis < 1 or > 64, n_elems < 0. */
+int lbm_gpc_basis(const double *nodes_host, int32_t n_nodes, int32_t dim, int32_t order,
+                  double *phi_out, int32_t *alpha_out, int32_t cap, int32_t *n_basis);
+int lbm_gpc_coefficients(const float *q_dev, const double *wphi_dev, int32_t n_nodes, int32_t n_basis,
+                         int64_t n_elems, double *coef_dev, double *var_dev, double *band_dev,
+                         hipStream_t stream);
 
 /* ---------------------------------------------------------- adjoint (a8)
  * Discrete adjoint of one step n -> n+1 for every instance of the plan

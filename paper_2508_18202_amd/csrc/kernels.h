@@ -85,6 +85,10 @@ int launch_fields(int parity, const Geo *geo, int32_t inst, const Geo &g, int64_
                   float *out, int32_t mode, hipStream_t s);
 int launch_average(const Geo &g, double inv_count, float *out, float *pout, hipStream_t s);
 int launch_zero_qoi(const Geo &g, hipStream_t s);
+// coef[p][e] = sum_j wphi[j][p] q[j][e] (FP64), n_basis <= 64; optional
+// var = sum_{p >= 1} coef^2 and band = coef[0] -+ 1.96 sqrt(var)
+int launch_gpc(const float *q, const double *wphi, int32_t nq, int32_t nb, int64_t n, double *coef, double *var,
+               double *band, hipStream_t s);
 int launch_moments(const float *q, const double *w, int32_t nq, int64_t n, double *mean,
                    double *var, unsigned long long *nneg, hipStream_t s);
 

@@ -415,6 +415,10 @@ int lbm_quadrature(int32_t kind, int32_t level, int32_t dim, double *nodes_host,
         if (!gauss_legendre(level, x, w)) return fail(LBM_E_INVALID, "Gauss-Legendre eigen-solve failed");
     } else if (kind == LBM_QUAD_SMOLYAK_CC) {
         if (!smolyak_cc(level, dim, x, w)) return fail(LBM_E_INVALID, "Smolyak level %d dim %d not supported", level, dim);
+    } else if (kind == LBM_QUAD_GAUSS_HERMITE) {
+        if (level < 1 || level > 256) return fail(LBM_E_INVALID, "Gauss-Hermite point count %d out of range", level);
+        if (!tensor_gauss_hermite(level, dim, x, w))
+            return fail(LBM_E_INVALID, "Gauss-Hermite rule with %d points in %d dimensions not supported", level, dim);
     } else {
         return fail(LBM_E_INVALID, "unknown quadrature kind %d", kind);
     }
@@ -425,6 +429,39 @@ int lbm_quadrature(int32_t kind, int32_t level, int32_t dim, double *nodes_host,
     if (cap < n) return fail(LBM_E_INVALID, "capacity %d < %d nodes", cap, n);
     std::memcpy(nodes_host, x.data(), sizeof(double) * x.size());
     std::memcpy(weights_host, w.data(), sizeof(double) * w.size());
+    return LBM_OK;
+}
+
+int lbm_gpc_basis(const double *nodes_host, int32_t n_nodes, int32_t dim, int32_t order, double *phi_out,
+                  int32_t *alpha_out, int32_t cap, int32_t *n_basis)
+{
+    if (dim < 1 || dim > 8 || order < 0 || order > 16 || n_nodes < 0)
+        return fail(LBM_E_INVALID, "gPC basis: need 1 <= dim <= 8, 0 <= order <= 16, n_nodes >= 0");
+    std::vector<int> alpha;
+    gpc_multi_indices(dim, order, alpha);
+    const int32_t P = (int32_t)(alpha.size() / dim);
+    if (n_basis) *n_basis = P;
+    if (!phi_out) return LBM_OK;
+    if (!nodes_host || !alpha_out) return fail(LBM_E_INVALID, "gPC basis: nodes and alpha output needed");
+    if (cap < n_nodes) return fail(LBM_E_INVALID, "gPC basis: capacity %d < %d nodes", cap, n_nodes);
+    std::vector<double> phi;
+    gpc_basis(nodes_host, n_nodes, dim, alpha, phi);
+    std::memcpy(phi_out, phi.data(), sizeof(double) * phi.size());
+    for (size_t k = 0; k < alpha.size(); ++k) alpha_out[k] = alpha[k];
+    return LBM_OK;
+}
+
+int lbm_gpc_coefficients(const float *q_dev, const double *wphi_dev, int32_t n_nodes, int32_t n_basis,
+                         int64_t n_elems, double *coef_dev, double *var_dev, double *band_dev, hipStream_t s)
+{
+    if (n_nodes < 1 || n_basis < 1 || n_basis > 64 || n_elems < 0)
+        return fail(LBM_E_INVALID, "gPC coefficients: need n_nodes >= 1, 1 <= n_basis <= 64, n_elems >= 0");
+    if (n_elems == 0) return LBM_OK;
+    if (!q_dev || !wphi_dev || !coef_dev) return fail(LBM_E_INVALID, "gPC coefficients: NULL buffer");
+    int r = check_device();
+    if (r) return r;
+    if (launch_gpc(q_dev, wphi_dev, n_nodes, n_basis, n_elems, coef_dev, var_dev, band_dev, s))
+        return fail(LBM_E_HIP, "gPC launch failed: %s", hipGetErrorString(hipGetLastError()));
     return LBM_OK;
 }
 

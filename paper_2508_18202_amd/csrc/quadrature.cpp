@@ -1,6 +1,11 @@
 // quadrature.cpp -- collocation rules of the stochastic collocation step
 // (arXiv 2508.18202, Sec. 2.3, Eq. coef_discrete and Eq. quad_moments: nodes
-// Z^(j) and weights a_j) for inputs xi ~ U(-1, 1)^d, probability weights.
+// Z^(j) and weights a_j) for inputs xi ~ U(-1, 1)^d or z ~ N(0, 1)^d,
+// probability weights, and the Hermite chaos basis of the gPC expansion.
+//
+//   Gauss-Hermite   Golub-Welsch on the orthonormal probabilists' Hermite
+//                   recurrence (off-diagonal sqrt(k)), tensor product over
+//                   the dimensions (the paper's dense tensor-product rule).
 //
 //   Gauss-Legendre  Golub-Welsch: the nodes are the eigenvalues of the Jacobi
 //                   matrix of the Legendre recurrence (off-diagonal
@@ -100,6 +105,104 @@ bool gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
 }
 
 // Solve A y = b (dense, partial pivoting).
+// Golub-Welsch for the standard normal: the orthonormal probabilists'
+// Hermite recurrence has zero diagonal and off-diagonal sqrt(k).
+bool gauss_hermite(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    if (n < 1) return false;
+    std::vector<double> d(n, 0.0), e(n > 1 ? n - 1 : 0), z(n, 0.0);
+    for (int k = 1; k < n; ++k) e[k - 1] = std::sqrt((double)k);
+    z[0] = 1.0;
+    if (!tql_first_row(d, e, z)) return false;
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
+    x.resize(n);
+    w.resize(n);
+    for (int i = 0; i < n; ++i) {
+        x[i] = d[idx[i]];
+        w[i] = z[idx[i]] * z[idx[i]];
+    }
+    for (int i = 0; i < n / 2; ++i) {
+        const double a = 0.5 * (x[n - 1 - i] - x[i]);
+        x[i] = -a;
+        x[n - 1 - i] = a;
+        const double b = 0.5 * (w[i] + w[n - 1 - i]);
+        w[i] = w[n - 1 - i] = b;
+    }
+    if (n & 1) x[n / 2] = 0.0;
+    double s = 0.0;
+    for (double v : w) s += v;
+    for (double &v : w) v /= s;
+    return true;
+}
+
+bool tensor_gauss_hermite(int n, int dim, std::vector<double> &nodes, std::vector<double> &weights)
+{
+    if (dim < 1 || dim > 8) return false;
+    std::vector<double> x, w;
+    if (!gauss_hermite(n, x, w)) return false;
+    long total = 1;
+    for (int k = 0; k < dim; ++k) {
+        total *= n;
+        if (total > 65536) return false;
+    }
+    nodes.assign((size_t)total * dim, 0.0);
+    weights.assign((size_t)total, 1.0);
+    for (long j = 0; j < total; ++j) {
+        long r = j;
+        for (int k = dim - 1; k >= 0; --k) {
+            const int i = (int)(r % n);
+            r /= n;
+            nodes[(size_t)j * dim + k] = x[i];
+            weights[(size_t)j] *= w[i];
+        }
+    }
+    return true;
+}
+
+static void multi_rec(int dim, int k, int left, std::vector<int> &cur, std::vector<int> &out)
+{
+    if (k == dim - 1) {
+        cur[k] = left;
+        out.insert(out.end(), cur.begin(), cur.end());
+        return;
+    }
+    for (int a = left; a >= 0; --a) {
+        cur[k] = a;
+        multi_rec(dim, k + 1, left - a, cur, out);
+    }
+}
+
+void gpc_multi_indices(int dim, int order, std::vector<int> &alpha)
+{
+    alpha.clear();
+    std::vector<int> cur(dim, 0);
+    for (int deg = 0; deg <= order; ++deg) multi_rec(dim, 0, deg, cur, alpha);
+}
+
+void gpc_basis(const double *nodes, int n_nodes, int dim, const std::vector<int> &alpha, std::vector<double> &phi)
+{
+    const int P = (int)alpha.size() / dim;
+    int maxdeg = 0;
+    for (int a : alpha) maxdeg = std::max(maxdeg, a);
+    phi.assign((size_t)n_nodes * P, 1.0);
+    std::vector<double> he(maxdeg + 1);
+    std::vector<double> fact(maxdeg + 1, 1.0);
+    for (int k = 1; k <= maxdeg; ++k) fact[k] = fact[k - 1] * k;
+    for (int j = 0; j < n_nodes; ++j)
+        for (int k = 0; k < dim; ++k) {
+            const double z = nodes[(size_t)j * dim + k];
+            he[0] = 1.0;
+            if (maxdeg >= 1) he[1] = z;
+            for (int m = 1; m < maxdeg; ++m) he[m + 1] = z * he[m] - m * he[m - 1];
+            for (int p = 0; p < P; ++p) {
+                const int a = alpha[(size_t)p * dim + k];
+                phi[(size_t)j * P + p] *= he[a] / std::sqrt(fact[a]);
+            }
+        }
+}
+
 static bool solve(std::vector<double> A, std::vector<double> b, int n, std::vector<double> &y)
 {
     for (int c = 0; c < n; ++c) {

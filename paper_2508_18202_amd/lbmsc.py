@@ -24,8 +24,8 @@ BGK, SMAGORINSKY, RR3 = 0, 1, 2
 MODELS = {"bgk": BGK, "smagorinsky": SMAGORINSKY, "rr3": RR3}
 INFLOW_UNIFORM, INFLOW_LOGLAW, INFLOW_SERIES = 0, 1, 2
 INFLOWS = {"uniform": INFLOW_UNIFORM, "loglaw": INFLOW_LOGLAW, "series": INFLOW_SERIES}
-QUAD_GAUSS_LEGENDRE, QUAD_SMOLYAK_CC = 0, 1
-QUADS = {"gauss_legendre": QUAD_GAUSS_LEGENDRE, "smolyak_cc": QUAD_SMOLYAK_CC}
+QUAD_GAUSS_LEGENDRE, QUAD_SMOLYAK_CC, QUAD_GAUSS_HERMITE = 0, 1, 2
+QUADS = {"gauss_legendre": QUAD_GAUSS_LEGENDRE, "smolyak_cc": QUAD_SMOLYAK_CC, "gauss_hermite": QUAD_GAUSS_HERMITE}
 RECORD_MACROS, RECORD_POPULATIONS = 1, 2
 
 
@@ -90,6 +90,10 @@ _SIGS = [
     ("lbm_read_populations", ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
     ("lbm_qoi_average", ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     ("lbm_sc_moments", ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P]),
+    ("lbm_gpc_basis", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int32,
+                                     _P]),
+    ("lbm_gpc_coefficients", ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P, _P, _P,
+                                            _P]),
     ("lbm_adjoint_step", ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P, ctypes.c_int32,
                                         ctypes.c_int32, _P, _P, _P]),
     ("lbm_adjoint_init", ctypes.c_int, [_P, _P, _P, _P]),
@@ -150,6 +154,25 @@ def lbm_quadrature(kind, level: int, dim: int):
     w = np.zeros(n.value)
     _check(lib().lbm_quadrature(k, level, dim, x.ctypes.data, w.ctypes.data, n.value, ctypes.byref(n)))
     return x, w
+
+
+def lbm_gpc_basis(nodes: np.ndarray, order: int):
+    """(phi [n, P], alpha [P, dim]) of the orthonormal Hermite chaos basis."""
+    x = np.ascontiguousarray(nodes, dtype=np.float64)
+    n, dim = x.shape
+    P = ctypes.c_int32(0)
+    _check(lib().lbm_gpc_basis(None, n, dim, order, None, None, 0, ctypes.byref(P)))
+    phi = np.zeros((n, P.value))
+    alpha = np.zeros((P.value, dim), dtype=np.int32)
+    _check(lib().lbm_gpc_basis(x.ctypes.data, n, dim, order, phi.ctypes.data, alpha.ctypes.data, n,
+                               ctypes.byref(P)))
+    return phi, alpha
+
+
+def lbm_gpc_coefficients(q_dev: int, wphi_dev: int, n_nodes: int, n_basis: int, n_elems: int, coef_dev: int,
+                         var_dev, band_dev, stream: int) -> None:
+    _check(lib().lbm_gpc_coefficients(q_dev, wphi_dev, n_nodes, n_basis, n_elems, coef_dev, var_dev, band_dev,
+                                      stream))
 
 
 def lbm_node_params(xi: Sequence[float], base: float, rel: float, angle_deg: float, z0: float):

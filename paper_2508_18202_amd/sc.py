@@ -199,6 +199,25 @@ def moments(q: torch.Tensor, weights: np.ndarray, count_negative: bool = False):
     return mean, var
 
 
+def gpc(q: torch.Tensor, nodes: np.ndarray, weights: np.ndarray, order: int):
+    """gPC expansion (Sec. 2.3) of q [N_q, ...] (float32, node-major) in the
+    orthonormal Hermite chaos of total degree <= order at the collocation
+    nodes: coefficients [P, ...], multi-indices [P, d], mean (coef 0),
+    variance (sum of the squared higher coefficients) and the 95 % band
+    mean -+ 1.96 std, all FP64 from one kernel."""
+    phi, alpha = L.lbm_gpc_basis(nodes, order)
+    wphi = torch.from_numpy(phi * np.asarray(weights, dtype=np.float64)[:, None]).to(q.device).contiguous()
+    q = q.contiguous()
+    n = q[0].numel()
+    P = phi.shape[1]
+    coef = torch.empty((P,) + tuple(q.shape[1:]), dtype=torch.float64, device=q.device)
+    var = torch.empty(tuple(q.shape[1:]), dtype=torch.float64, device=q.device)
+    band = torch.empty((2,) + tuple(q.shape[1:]), dtype=torch.float64, device=q.device)
+    L.lbm_gpc_coefficients(q.data_ptr(), wphi.data_ptr(), q.shape[0], P, n, coef.data_ptr(), var.data_ptr(),
+                           band.data_ptr(), stream_handle())
+    return {"coef": coef, "alpha": alpha, "mean": coef[0], "var": var, "band": band}
+
+
 def run_sc(w: Workload, solid: np.ndarray, steps: Optional[int] = None, avg_start: Optional[int] = None,
            probes: Optional[np.ndarray] = None, use_graph: bool = True, block: int = 0,
            check_every: int = 0, variant: Optional[Sequence[int]] = None):

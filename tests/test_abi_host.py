@@ -68,8 +68,35 @@ def test_smolyak_matches_oracle(level, dim):
         assert abs(a[k] - b[k]) < 1e-14
 
 
+@pytest.mark.parametrize("n,dim", [(1, 1), (3, 1), (5, 2), (11, 2), (20, 1), (4, 3)])
+def test_gauss_hermite_matches_oracle(n, dim):
+    x, w = L.lbm_quadrature("gauss_hermite", n, dim)
+    xo, wo = orc.tensor_gauss_hermite(n, dim)
+    assert x.shape == xo.shape
+    assert np.abs(x - xo).max() < 1e-12 * max(1.0, np.abs(xo).max())
+    assert np.abs(w - wo).max() < 1e-14
+
+
+@pytest.mark.parametrize("dim,order", [(1, 0), (1, 7), (2, 5), (3, 3)])
+def test_gpc_basis_matches_oracle(dim, order):
+    nodes, _ = orc.tensor_gauss_hermite(5, dim)
+    phi, alpha = L.lbm_gpc_basis(nodes, order)
+    phio, alphao = orc.gpc_basis(nodes, order)
+    assert np.array_equal(alpha, alphao)
+    assert np.abs(phi - phio).max() < 1e-12 * max(1.0, np.abs(phio).max())
+
+
+def test_gpc_rejections():
+    with pytest.raises(L.LbmError):
+        L.lbm_gpc_basis(np.zeros((3, 9)), 2)           # more than 8 variables
+    with pytest.raises(L.LbmError):
+        L.lbm_gpc_coefficients(1, 1, 4, 65, 10, 1, None, None, 0)      # more than 64 terms
+    with pytest.raises(L.LbmError):
+        L.lbm_gpc_coefficients(1, 1, 0, 3, 10, 1, None, None, 0)       # no nodes
+
+
 def test_node_params_match_oracle():
-    for w in (inputs.small_block(), inputs.urban_les(), inputs.adjoint_case()):
+    for w in (inputs.small_block(), inputs.urban_les(), inputs.adjoint_case(), inputs.urban_gpc()):
         x, _ = L.lbm_quadrature(w.quadrature, w.quad_level, w.quad_dim)
         for xi in x:
             th = L.lbm_node_params(xi, w.speed_base, w.speed_rel, w.angle_deg, w.z0)
