@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--xcd-order", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost leg")
-    ap.add_argument("--no-rr3", action="store_true", help="skip the regularised-collision and series-inflow legs")
+    ap.add_argument("--no-rr3", action="store_true",
+                    help="skip the regularised-collision, series-inflow and Gauss-Hermite/gPC legs")
     ap.add_argument("--no-uneven", action="store_true", help="skip the batched vs one-at-a-time leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-calib", action="store_true",
@@ -171,6 +172,62 @@ def series_leg(variant, steps: int = 1000):
                        f"(hours of 250 steps, blends of 100), {steps} steps after the ramp"}
     out.update(_after_ramp_rate(w, variant, steps, "series"))
     return out
+
+
+def gauss_hermite_leg(variant, steps: int = 300, avg_len: int = 100):
+    """The paper's stochastic set-up at its node count: 121 Gauss-Hermite
+    nodes (11 x 11) of a 128x64x48 urban box with the hourly-series inflow,
+    stepped in one plan; then the order-5 gPC expansion of the time-averaged
+    fields (21 coefficients, variance and 95 % band per value)."""
+    import torch
+    from paper_2508_18202_amd import inputs, sc
+    w = inputs.scaled(inputs.urban_gpc(hours=4, hour_steps=100, blend_steps=30), 128, 64, 48, ramp=100,
+                      ref_height=48.0)
+    solid = inputs.solid_mask(w)
+    n_fluid = int((solid == 0).sum())
+    x, a, th = sc.collocation(w)
+    cg = sc.make_geometry(w, solid)
+    total = w.ramp + steps
+    ens = sc.Ensemble([cg], [th], avg_begin=total - avg_len, avg_end=total, use_graph=True, variant=variant)
+    try:
+        ens.advance(w.ramp)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ens.advance(steps - avg_len)
+        e1.record()
+        ens.advance(avg_len)
+        if ens.health() >= 0:
+            raise RuntimeError("Gauss-Hermite leg went unstable")
+        t_step = e0.elapsed_time(e1) / 1e3 / (steps - avg_len)
+        q = torch.empty(len(ens), cg.ncells, 4, dtype=torch.float32, device="cuda")
+        for j in range(len(ens)):
+            ens.averages_into(j, q[j])
+        sc.gpc(q, x, a, 5)                             # warm-up
+        torch.cuda.synchronize()
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record()
+        r = sc.gpc(q, x, a, 5)
+        g1.record()
+        g1.synchronize()
+        t_gpc = g0.elapsed_time(g1) / 1e3
+        n_el = q[0].numel()
+        P = r["coef"].shape[0]
+        gpc_bytes = n_el * (len(ens) * 4 + P * 8 + 8 + 16)
+        launch_bytes = BYTES_PER_CELL_UPDATE * len(ens) * n_fluid
+        return {"workload": "121 Gauss-Hermite nodes (11 x 11) x 128x64x48 urban LES, hourly-series inflow, "
+                            f"{steps - avg_len} timed steps; order-5 gPC of the time-averaged fields",
+                "instances": len(ens),
+                "step_us": round(t_step * 1e6, 2),
+                "kernel_mlups": round(len(ens) * n_fluid / t_step / 1e6, 1),
+                "frac": round(launch_bytes / t_step / 1e9 / HBM_PEAK_GBS, 4),
+                "gpc_terms": P, "gpc_elements": n_el, "gpc_ms": round(t_gpc * 1e3, 3),
+                "gpc_gbs": round(gpc_bytes / t_gpc / 1e9, 1),
+                "gpc_fp64_gflops": round(2.0 * n_el * len(ens) * P / t_gpc / 1e9, 1)}
+    finally:
+        ens.close()
 
 
 def adjoint_leg(variant, steps: int = 2000, avg_len: int = 500, ckpt: int = 100):
@@ -387,6 +444,7 @@ def main():
     if not args.no_rr3:
         out["regularised_collision"] = rr3_leg(variant)
         out["series_inflow"] = series_leg(variant)
+        out["gauss_hermite_gpc"] = gauss_hermite_leg(variant)
     if not args.no_adjoint:
         out["adjoint_vs_forward"] = adjoint_leg(variant)
     if not args.no_uneven:
