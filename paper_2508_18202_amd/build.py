@@ -53,6 +53,7 @@ UNITS = [("steps.hip", ["-DLBM_STEP_MODEL=0"], "steps_m0.o"),
          ("steps.hip", ["-DLBM_STEP_MODEL=2"], "steps_m2.o"),
          ("adjoint.hip", [], "adjoint.o"),
          ("kernels.hip", [], "kernels.o"),
+         ("gpc.hip", [], "gpc.o"),
          ("lbm_sc.hip", [], "lbm_sc.o"),
          ("quadrature.cpp", [], "quadrature.o")]
 BUILD_DIR = os.path.join(PKG, "_build")

@@ -176,42 +176,6 @@ __global__ __launch_bounds__(256) void k_moments_arg_shift(const float *__restri
     if (nneg && s < 0.0) atomicAdd(nneg, 1ull);
 }
 
-// gPC coefficients of one element per thread: coef[p][e] = sum_j wphi[j][p] q[j][e]
-// in FP64.  The weighted basis index does not depend on the lane, so its
-// values come through the scalar cache; q is read node-major (coalesced).
-template <int PMAX>
-__global__ __launch_bounds__(256) void k_gpc(const float *__restrict__ q, const double *__restrict__ wphi,
-                                             int32_t nq, int32_t nb, int64_t n, double *__restrict__ coef,
-                                             double *__restrict__ var, double *__restrict__ band)
-{
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= n) return;
-    double acc[PMAX];
-#pragma unroll
-    for (int p = 0; p < PMAX; ++p) acc[p] = 0.0;
-    for (int32_t j = 0; j < nq; ++j) {
-        const double v = (double)q[(int64_t)j * n + e];
-        const double *b = wphi + (int64_t)j * nb;
-#pragma unroll
-        for (int p = 0; p < PMAX; ++p)
-            if (p < nb) acc[p] += b[p] * v;
-    }
-#pragma unroll
-    for (int p = 0; p < PMAX; ++p)
-        if (p < nb) coef[(int64_t)p * n + e] = acc[p];
-    if (var || band) {
-        double v = 0.0;
-#pragma unroll
-        for (int p = 1; p < PMAX; ++p)
-            if (p < nb) v += acc[p] * acc[p];
-        if (var) var[e] = v;
-        if (band) {
-            const double h = 1.96 * sqrt(v);
-            band[e] = acc[0] - h;
-            band[n + e] = acc[0] + h;
-        }
-    }
-}
 
 // grad[i][k] += sum of part[tile][k] over instance i's tiles: one workgroup
 // per instance, strided partial sums then a tree in shared memory.
@@ -339,17 +303,6 @@ int launch_zero_qoi(const Geo &g, hipStream_t s)
     const int32_t n4 = 4 * g.ncells;
     const int32_t n = n4 > g.n_probes ? n4 : g.n_probes;
     hipLaunchKernelGGL(k_zero, dim3((n + 255) / 256), dim3(256), 0, s, g.qpart, g.qsum, g.psum, n4, g.n_probes);
-    return (int)hipGetLastError();
-}
-
-int launch_gpc(const float *q, const double *wphi, int32_t nq, int32_t nb, int64_t n, double *coef, double *var,
-               double *band, hipStream_t s)
-{
-    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-    if (nb <= 8) hipLaunchKernelGGL(k_gpc<8>, grid, block, 0, s, q, wphi, nq, nb, n, coef, var, band);
-    else if (nb <= 16) hipLaunchKernelGGL(k_gpc<16>, grid, block, 0, s, q, wphi, nq, nb, n, coef, var, band);
-    else if (nb <= 32) hipLaunchKernelGGL(k_gpc<32>, grid, block, 0, s, q, wphi, nq, nb, n, coef, var, band);
-    else hipLaunchKernelGGL(k_gpc<64>, grid, block, 0, s, q, wphi, nq, nb, n, coef, var, band);
     return (int)hipGetLastError();
 }
 
