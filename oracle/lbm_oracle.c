@@ -23,6 +23,9 @@
  *   - bounce-back walls/ground, a local velocity (moving-wall bounce-back)
  *     inflow, a zero-gradient outflow and a free-slip sky (Sec. 2.2 boundary
  *     list), plus periodic faces;
+ *   - the cylindrical domain of Secs. 2.2 and 3: cells of the solid mask
+ *     coded 2 are the exterior of the cylinder, and every link crossing into
+ *     them carries the local velocity condition of the wind (the mantle);
  *   - the discrete adjoint of one step (not in the paper; used for the
  *     inflow-parameter gradients).
  *
@@ -378,19 +381,28 @@ void orc_inflow_velocity(const orc_case *k, int z, long n, double *u)
     inflow_at(k, z, n, u, d);
 }
 
-enum { R_STREAM = 0, R_BOUNCE = 1, R_INLET = 2, R_FREESLIP = 3, R_OUTLET = 4, R_REST = 5 };
+enum { R_STREAM = 0, R_BOUNCE = 1, R_INLET = 2, R_FREESLIP = 3, R_OUTLET = 4, R_REST = 5, R_MANTLE = 6 };
+
+/* Cell kinds of the solid mask: fluid, building (no-slip bounce-back) and
+ * mantle (the exterior of a cylindrical domain, whose surface carries the
+ * local velocity condition of the wind). */
+enum { S_FLUID = 0, S_BUILDING = 1, S_MANTLE = 2 };
 
 /* Pull rule of destination link (x, i): returns the rule kind and writes the
  * source cell and the post-collision population index that f_out(x, i) is
  * taken from.  Rules, first match wins, with s = x - c_i (periodic axes
  * wrapped):
- *   R1 s is solid, or s leaves the box through a WALL face: bounce-back,
- *      source (x, opp(i));
+ *   R1 s is a building cell, or s leaves the box through a WALL face:
+ *      bounce-back, source (x, opp(i));
+ *   R6 s is a mantle cell: the velocity condition of the mantle, the
+ *      moving-wall bounce-back of R2 with the wind u_in(z, n) of the cell's
+ *      height;
  *   R2 s.x < 0 through the INLET face: moving-wall bounce-back, source
  *      (x, opp(i)) plus 6 w_i rho_w c_i.u_in with rho_w = 1;
  *   R3 s.z >= nz through the FREESLIP sky: specular reflection, source
- *      (x - c_ix, y - c_iy, nz-1) with c_z flipped, a source at x = nx clamped
- *      to nx-1;
+ *      m = (x - c_ix, y - c_iy, nz-1) with c_z flipped, a source at x = nx
+ *      clamped to nx-1; when m is a mantle cell the reflected path crosses the
+ *      mantle and R6 applies instead;
  *   R4 s.x >= nx through the OUTLET face: zero gradient, source (nx-1, s.y, s.z),
  *      same population;
  *   R5 otherwise plain streaming from (s, i).
@@ -407,9 +419,14 @@ static int pull_rule(const orc_case *k, int x, int y, int z, int i,
     int wall_exit = (sx < 0 && k->face[0] == F_WALL) || (sx >= k->nx && k->face[1] == F_WALL) ||
                     (sy < 0 && k->face[2] == F_WALL) || (sy >= k->ny && k->face[3] == F_WALL) ||
                     (sz < 0 && k->face[4] == F_WALL) || (sz >= k->nz && k->face[5] == F_WALL);
-    if ((inside && k->solid[cell_index(k, sx, sy, sz)]) || wall_exit) {
+    int kind = inside ? k->solid[cell_index(k, sx, sy, sz)] : S_FLUID;
+    if (kind == S_BUILDING || wall_exit) {
         *sx_o = x; *sy_o = y; *sz_o = z; *pop_o = opposite(i);
         return R_BOUNCE;
+    }
+    if (kind == S_MANTLE) {
+        *sx_o = x; *sy_o = y; *sz_o = z; *pop_o = opposite(i);
+        return R_MANTLE;
     }
     if (sx < 0 && k->face[0] == F_INLET) {
         *sx_o = x; *sy_o = y; *sz_o = z; *pop_o = opposite(i);
@@ -418,6 +435,10 @@ static int pull_rule(const orc_case *k, int x, int y, int z, int i,
     if (sz >= k->nz && k->face[5] == F_FREESLIP) {
         int px = sx;  /* x - c_ix, already wrapped when x is periodic */
         if (px >= k->nx && k->face[1] == F_OUTLET) px = k->nx - 1;
+        if (k->solid[cell_index(k, px, sy, k->nz - 1)] == S_MANTLE) {
+            *sx_o = x; *sy_o = y; *sz_o = z; *pop_o = opposite(i);
+            return R_MANTLE;
+        }
         *sx_o = px; *sy_o = sy; *sz_o = k->nz - 1; *pop_o = zflip(i);
         return R_FREESLIP;
     }
@@ -447,12 +468,28 @@ int orc_check_case(const orc_case *k)
         (!k->series || k->series_len < 1 || k->hour_steps < 1 || k->blend_steps < 0 ||
          k->blend_steps > k->hour_steps || !(k->ref_height > 0.0) || !(k->theta[2] > 0.0)))
         return 7;
-    /* the free-slip and outflow rules read top-layer / last-column cells */
+    /* the free-slip and outflow rules read top-layer / last-column cells; a
+     * mantle column may reach the sky (R3 turns into R6 there) */
     for (int z = 0; z < k->nz; ++z)
         for (int y = 0; y < k->ny; ++y)
             for (int x = 0; x < k->nx; ++x) {
-                if (!k->solid[cell_index(k, x, y, z)]) continue;
-                if (k->face[5] == F_FREESLIP && z == k->nz - 1) return 5;
+                int kind = k->solid[cell_index(k, x, y, z)];
+                if (kind > S_MANTLE) return 9;
+                if (kind == S_FLUID) {
+                    /* one fluid cell borders buildings or the mantle, not both */
+                    int seen = 0;
+                    for (int i = 1; i < NQ; ++i) {
+                        int sx = x - C[i][0], sy = y - C[i][1], sz = z - C[i][2];
+                        if (k->face[0] == F_PERIODIC) sx = wrap(sx, k->nx);
+                        if (k->face[2] == F_PERIODIC) sy = wrap(sy, k->ny);
+                        if (k->face[4] == F_PERIODIC) sz = wrap(sz, k->nz);
+                        if (sx < 0 || sx >= k->nx || sy < 0 || sy >= k->ny || sz < 0 || sz >= k->nz) continue;
+                        seen |= 1 << k->solid[cell_index(k, sx, sy, sz)];
+                    }
+                    if ((seen & (1 << S_BUILDING)) && (seen & (1 << S_MANTLE))) return 8;
+                    continue;
+                }
+                if (k->face[5] == F_FREESLIP && z == k->nz - 1 && kind == S_BUILDING) return 5;
                 if (k->face[1] == F_OUTLET && x == k->nx - 1) return 6;
             }
     return 0;
@@ -511,7 +548,7 @@ void orc_step(const orc_case *k, long step, const double *fin, double *fout)
                     int sx, sy, sz, p;
                     int rule = pull_rule(k, x, y, z, i, &sx, &sy, &sz, &p);
                     double v = fs[p * n + cell_index(k, sx, sy, sz)];
-                    if (rule == R_INLET) {
+                    if (rule == R_INLET || rule == R_MANTLE) {
                         double uin[3], d[3][3];
                         inflow_at(k, z, step, uin, d);
                         double cu = C[i][0] * uin[0] + C[i][1] * uin[1] + C[i][2] * uin[2];
@@ -607,7 +644,7 @@ void orc_collision_jacobian(const orc_case *k, const double *f, double *J)
 /* Discrete adjoint of step n -> n+1.
  *   mu      = P^T lam_next           (scatter-add of every pull link to its source)
  *   lam_n   = J(f_n)^T mu            (fluid cells; zero on solid cells)
- *   grad_k += sum over inlet links (x,i) of lam_next(x,i) * d b_i / d theta_k,
+ *   grad_k += sum over inlet and mantle links (x,i) of lam_next(x,i) * d b_i / d theta_k,
  * with b_i = 6 w_i rho_w c_i.u_in(z; theta) r(n).  lam_n receives no
  * objective source here; callers add dj_n/df_n. */
 void orc_adjoint_step(const orc_case *k, long step, const double *f_n,
@@ -626,7 +663,7 @@ void orc_adjoint_step(const orc_case *k, long step, const double *f_n,
                     int rule = pull_rule(k, x, y, z, i, &sx, &sy, &sz, &p);
                     double lam = lam_next[i * n + c];
                     mu[p * n + cell_index(k, sx, sy, sz)] += lam;
-                    if (rule == R_INLET) {
+                    if (rule == R_INLET || rule == R_MANTLE) {
                         double uin[3], d[3][3];
                         inflow_at(k, z, step, uin, d);
                         for (int t = 0; t < 3; ++t) {

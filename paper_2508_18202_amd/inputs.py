@@ -93,6 +93,9 @@ class Workload:
     hour_steps: int = 0
     blend_steps: int = 0
     ref_height: float = 0.0
+    # cylindrical domain: radius of the vertical cylinder about the box centre
+    # (cells); 0 for the plain box
+    cylinder_radius: float = 0.0
 
     @property
     def ncells(self) -> int:
@@ -134,7 +137,41 @@ def small_block_mask(nx: int = 32, ny: int = 16, nz: int = 16) -> np.ndarray:
     return mask
 
 
+def cylinder_mask(nx: int, ny: int, nz: int, radius: float, nbx: int, nby: int,
+                  seed: int) -> np.ndarray:
+    """Mask [nz, ny, nx] of a cylindrical domain: 2 (mantle region) for every
+    column whose centre (x + 1/2, y + 1/2) lies farther than `radius` from the
+    box centre (nx/2, ny/2), 1 for a seeded n_bx x n_by block array in the
+    central square of side `radius` (the building-array rule of this module
+    on that square, footprint max(2, min(radius / 6, 2 pitch / 3)), heights
+    up to nz / 2 below 16 layers), 0 fluid."""
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    r2 = (xx + 0.5 - nx / 2.0) ** 2 + (yy + 0.5 - ny / 2.0) ** 2
+    mask = np.zeros((nz, ny, nx), dtype=np.uint8)
+    mask[:, r2 > radius * radius] = 2
+    if nbx * nby == 0:
+        return mask
+    half = int(radius) // 2
+    x0, x1 = nx // 2 - half, nx // 2 + half
+    y0, y1 = ny // 2 - half, ny // 2 + half
+    pitch = min((x1 - x0) // nbx, (y1 - y0) // nby)
+    F = max(2, min(int(radius) // 6, (2 * pitch) // 3))
+    hmax = min(40, nz - 8) if nz >= 16 else nz // 2
+    rng = SplitMix64(seed)
+    for by in range(nby):
+        for bx in range(nbx):
+            h = rng.uniform_int(min(8, hmax), hmax)
+            cx = _int_div_centre(x0, x1, nbx, bx)
+            cy = _int_div_centre(y0, y1, nby, by)
+            xs, ys = cx - F // 2, cy - F // 2
+            mask[0:h, ys:ys + F, xs:xs + F] = 1
+    return mask
+
+
 def solid_mask(w: Workload, case: int = 0) -> np.ndarray:
+    if w.cylinder_radius > 0:
+        nbx, nby = w.buildings if w.buildings is not None else (0, 0)
+        return cylinder_mask(w.nx, w.ny, w.nz, w.cylinder_radius, nbx, nby, w.seed(case))
     if w.buildings is None:
         return small_block_mask(w.nx, w.ny, w.nz)
     return building_array_mask(w.nx, w.ny, w.nz, w.buildings[0], w.buildings[1],
@@ -307,6 +344,34 @@ def urban_gpc(hours: int = 8, hour_steps: int = 500, blend_steps: int = 100) -> 
     return dataclasses.replace(w, name="urban_gpc_256x128x64", quadrature="gauss_hermite", quad_level=11,
                                quad_dim=2, avg_start=steps - hours * hour_steps // 2, probe_kind="lines",
                                seed_base=7000, series=hourly_series(hours, 7000))
+
+
+CYLINDER_FACES = ("wall", "wall", "wall", "wall", "wall", "freeslip")
+
+
+def cylinder_gpc(radius: int = 270, height: int = 40, hours: int = 8, hour_steps: int = 500,
+                 blend_steps: int = 100) -> Workload:
+    """The paper's domain class: a vertical cylinder of radius 270 and height
+    40 cells (1 m cells) whose mantle carries the wind, bounce-back ground, a
+    free-slip sky, two seeded blocks in the centre in place of the real
+    buildings; Smagorinsky LES driven by an hourly series with the reference
+    speed at Ma = 0.0346 (0.02 in lattice units), zeta_1 ~ N(1, 0.1^2) on the
+    speeds and zeta_2 ~ N(0, (6 deg)^2) on the directions, 11 x 11
+    Gauss-Hermite nodes, normalised log profile with z0 = 0.1 cells and
+    H = height.  The box is 2 radius + 4 cells wide so that a ring of mantle
+    cells surrounds the disk everywhere."""
+    n = 2 * radius + 4
+    steps = 1000 + hours * hour_steps
+    return Workload(name=f"cylinder_gpc_r{radius}_h{height}", nx=n, ny=n, nz=height,
+                    faces=CYLINDER_FACES, model="smagorinsky", tau0=LES_TAU0, cs=0.1,
+                    inflow="series", speed_base=1.0, speed_rel=0.1, angle_deg=6.0, z0=0.1,
+                    quadrature="gauss_hermite", quad_level=11, quad_dim=2,
+                    steps=steps, avg_start=steps - hours * hour_steps // 2, ramp=1000,
+                    seed_base=8000, buildings=(2, 1), probe_kind="lines",
+                    series=hourly_series(hours, 8000, speed_mean=0.02, speed_amp=0.006,
+                                         dir0_deg=225.0, dir_step_deg=20.0),
+                    hour_steps=hour_steps, blend_steps=blend_steps, ref_height=float(height),
+                    cylinder_radius=float(radius))
 
 
 def scaled(w: Workload, nx: int, ny: int, nz: int, **kw) -> Workload:

@@ -14,7 +14,7 @@ from paper_2508_18202_amd import inputs  # noqa: E402
 
 
 def table():
-    ws = [inputs.small_block(), inputs.urban_les(), inputs.adjoint_case(), inputs.assimilation_case()] + inputs.uneven_cases()
+    ws = [inputs.small_block(), inputs.urban_les(), inputs.adjoint_case(), inputs.assimilation_case(), inputs.cylinder_gpc()] + inputs.uneven_cases()
     return {w.name: inputs.mask_hash(inputs.solid_mask(w)) for w in ws}
 
 

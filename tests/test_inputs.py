@@ -23,7 +23,7 @@ def test_splitmix64_reference_vector():
 def test_geometry_hashes_are_stable():
     with open(os.path.join(GOLDEN, "geometry_hashes.json")) as fh:
         want = json.load(fh)
-    ws = [inputs.small_block(), inputs.urban_les(), inputs.adjoint_case(), inputs.assimilation_case()] + inputs.uneven_cases()
+    ws = [inputs.small_block(), inputs.urban_les(), inputs.adjoint_case(), inputs.assimilation_case(), inputs.cylinder_gpc()] + inputs.uneven_cases()
     for w in ws:
         assert inputs.mask_hash(inputs.solid_mask(w)) == want[w.name], w.name
 
@@ -87,3 +87,27 @@ def test_table1_lattice_velocity():
     cs = math.sqrt((w * c[:, 0] ** 2).sum())
     assert abs(t["Ma"] * cs - 0.02) < 1e-6
     assert t["collocation_points_per_dim"] ** 2 == t["collocation_points_total"]
+
+
+def test_cylinder_mask_rules():
+    w = inputs.cylinder_gpc()
+    m = inputs.solid_mask(w)
+    R = w.cylinder_radius
+    assert m.shape == (40, 544, 544) and w.nx == w.ny == 2 * int(R) + 4
+    mant = m[0] == 2
+    # a ring of mantle cells surrounds the disk: the box border is mantle
+    assert mant[0].all() and mant[-1].all() and mant[:, 0].all() and mant[:, -1].all()
+    # the disk holds about pi R^2 columns (Gauss circle problem: error O(R))
+    assert abs((~mant).sum() - math.pi * R * R) < 4 * R
+    # the mantle region is the same in every layer and symmetric under a half
+    # turn and a quarter turn about the axis
+    assert ((m == 2) == mant[None]).all()
+    assert (mant == mant[::-1, ::-1]).all() and (mant == mant.T[:, ::-1]).all()
+    # two blocks on the ground, inside the central square of side R
+    from scipy.ndimage import label
+    lab, n = label(m[0] == 1)
+    assert n == 2
+    ys, xs = np.nonzero(m[0] == 1)
+    c = w.nx // 2
+    assert xs.min() >= c - R // 2 and xs.max() < c + R // 2
+    assert (m[-1] != 1).all()
