@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--no-rr3", action="store_true",
                     help="skip the regularised-collision, series-inflow and Gauss-Hermite/gPC legs")
     ap.add_argument("--no-uneven", action="store_true", help="skip the batched vs one-at-a-time leg")
+    ap.add_argument("--no-cylinder", action="store_true", help="skip the paper-size cylinder leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-calib", action="store_true",
                     help="also run a plain copy of known size (HBM counter calibration)")
@@ -226,6 +227,52 @@ def gauss_hermite_leg(variant, steps: int = 300, avg_len: int = 100):
                 "gpc_terms": P, "gpc_elements": n_el, "gpc_ms": round(t_gpc * 1e3, 3),
                 "gpc_gbs": round(gpc_bytes / t_gpc / 1e9, 1),
                 "gpc_fp64_gflops": round(2.0 * n_el * len(ens) * P / t_gpc / 1e9, 1)}
+    finally:
+        ens.close()
+
+
+def cylinder_leg(variant, steps: int = 40, warm: int = 6, max_nodes: int = 121):
+    """The paper's domain class at its size: a cylinder of radius 270 and
+    height 40 cells (1 m cells; box 544 x 544 x 40, 9.04 M fluid cells) whose
+    mantle carries an hourly-series wind, two central blocks, Smagorinsky LES;
+    the 121 Gauss-Hermite nodes (11 x 11) in one plan when HBM holds them
+    (about 0.9 GB each), else as many as fit; probe-line sums accumulated over
+    the timed steps."""
+    import torch
+    from paper_2508_18202_amd import inputs, sc
+    w = inputs.cylinder_gpc()
+    solid = inputs.solid_mask(w)
+    n_fluid = int((solid == 0).sum())
+    x, a, th = sc.collocation(w)
+    probes = inputs.probe_cells(w, solid)
+    cg = sc.make_geometry(w, solid, probes)
+    per_inst = 19 * cg.qs * 4 + 16 * len(probes)
+    free, _ = torch.cuda.mem_get_info()
+    k = int(max(1, min(max_nodes, len(th), (free - (16 << 30)) // per_inst)))
+    ens = sc.Ensemble([cg], [th[:k]], avg_begin=warm, avg_end=warm + steps, fields=False,
+                      use_graph=True, variant=variant)
+    try:
+        ens.advance(warm)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ens.advance(steps)
+        e1.record()
+        e1.synchronize()
+        if ens.health() >= 0:
+            raise RuntimeError("cylinder leg went unstable")
+        t = e0.elapsed_time(e1) / 1e3 / steps
+        launch_bytes = BYTES_PER_CELL_UPDATE * k * n_fluid
+        return {"workload": f"{k} of the 121 Gauss-Hermite nodes x cylinder r=270 h=40 (544x544x40 box), "
+                            "mantle velocity condition with an hourly-series wind, Smagorinsky Cs=0.1, "
+                            f"probe lines, {steps} timed steps",
+                "instances": k, "fluid_cells_per_instance": n_fluid,
+                "fluid_fraction_of_box": round(n_fluid / cg.ncells, 4),
+                "step_ms": round(t * 1e3, 3),
+                "kernel_mlups": round(k * n_fluid / t / 1e6, 1),
+                "frac": round(launch_bytes / t / 1e9 / HBM_PEAK_GBS, 4),
+                "hbm_gib_populations": round(k * 19 * cg.qs * 4 / 2 ** 30, 1)}
     finally:
         ens.close()
 
@@ -445,6 +492,8 @@ def main():
         out["regularised_collision"] = rr3_leg(variant)
         out["series_inflow"] = series_leg(variant)
         out["gauss_hermite_gpc"] = gauss_hermite_leg(variant)
+    if not args.no_cylinder:
+        out["cylinder"] = cylinder_leg(variant)
     if not args.no_adjoint:
         out["adjoint_vs_forward"] = adjoint_leg(variant)
     if not args.no_uneven:

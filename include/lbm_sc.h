@@ -176,13 +176,23 @@ int lbm_node_params(const double *xi_host, int32_t dim, double base, double rel,
  * Sizes the caller must allocate: the geometry buffer in bytes and the
  * population plane stride in floats (f_dev holds 19 planes).
  * lbm_init_geometry validates the case, builds per-cell flags and solid-link
- * masks on the device from solid_host ([nz][ny][nx] bytes, 1 = solid) and
- * the sorted probe list (probe_host, n_probes distinct fluid cell indices, may
- * be NULL when n_probes == 0), and sets f_dev to the rest equilibrium
- * (f_i - w_i = 0).  Rejected (LBM_E_INVALID): face kinds outside the list
- * above, unpaired periodic faces, solid cells in the top layer under a
+ * masks on the device from solid_host ([nz][ny][nx] bytes: 0 fluid,
+ * 1 building, 2 mantle region) and the sorted probe list (probe_host,
+ * n_probes distinct fluid cell indices, may be NULL when n_probes == 0), and
+ * sets f_dev to the rest equilibrium (f_i - w_i = 0).
+ * Building cells are no-slip bounce-back walls.  Mantle cells are the
+ * exterior of a cylindrical domain (Secs. 2.2 and 3): every link that
+ * crosses into them takes the local velocity condition of the wind, the
+ * moving-wall bounce-back with the instance's inflow u_in(z, n), also where
+ * the free-slip reflection of a top-layer link would come from a mantle cell.
+ * A cylinder of radius R about the box centre is the mantle code on every
+ * column whose centre lies farther than R from the axis, with WALL side
+ * faces (never reached) and typically a free-slip sky.
+ * Rejected (LBM_E_INVALID): face kinds outside the list above, unpaired
+ * periodic faces, mask codes above 2, building cells in the top layer under a
  * free-slip sky, solid cells in the last two x columns or an odd nx with an
- * outlet, more than 2^31 - 1 cells. */
+ * outlet, a fluid cell bordering a building and a mantle cell at once, more
+ * than 2^31 - 1 cells. */
 int64_t lbm_geometry_bytes(const lbm_domain *dom, int32_t n_probes);
 int64_t lbm_population_stride(const lbm_domain *dom);
 int lbm_init_geometry(const lbm_domain *dom, const uint8_t *solid_host,

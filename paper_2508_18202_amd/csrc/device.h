@@ -247,9 +247,9 @@ __device__ __forceinline__ void load_state(const Geo &G, uint32_t c, uint8_t fl,
         for (int i = 0; i < Q; ++i) g[i] = ldg(f + (size_t)opp(i) * qs - off_of(G, i), c);
     } else {
         const Shape S = shape_of(G);
-        const Preds p = preds_of(S, x, y, z);
+        const Preds p = preds_of(S, x, y, z, fl);
         const uint32_t sm = gp(G.smask)[c];
-        const float U = (fl & FL_INLET) ? inflow_speed(G, z) : 0.0f;
+        const float U = (fl & (FL_INLET | FL_MANTLE)) ? inflow_speed(G, z) : 0.0f;
         gather_all(G, S, p, sm, c, U, inflow_at(G, n - 1), g, Dirs{});
     }
 }
@@ -487,6 +487,9 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
     GLOBAL_AS float *__restrict__ f = gp(G.f);
     const uint32_t qs = (uint32_t)G.qs;
     const int32_t base = (tile - G.tile0) * (BS * CPT) + (int32_t)threadIdx.x;
+    // all-solid lines of the tile carry no state and no neighbour's rule
+    // touches them: their cells are skipped like cells past the end
+    const uint64_t dead = a.dead ? a.dead[tile] : 0ull;
 
     uint32_t c[CPT];
     uint8_t fl[CPT];
@@ -500,7 +503,7 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         const int32_t lc = base + j * BS;
-        const bool active = lc < G.ncells;
+        const bool active = lc < G.ncells && !((dead >> ((j * BS + (int)threadIdx.x) >> 5)) & 1ull);
         act[j] = active;
         c[j] = active ? (uint32_t)lc : 0u;
         // Even steps touch only the cell's own 19 slots.  The slots of a solid
@@ -521,15 +524,15 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
         // full rules for all lanes
         near_wave[j] = PARITY == 1 && __any(fluid[j] && (fl[j] & FL_NEAR));
         general_wave[j] = PARITY == 1 && __any(fluid[j] && (fl[j] & FL_GENERAL));
-        pr[j] = Preds{false, false, false, false, false, false};
+        pr[j] = Preds{false, false, false, false, false, false, false};
         sm[j] = 0;
         U[j] = 0.0f;
         if (general_wave[j] && fluid[j]) {
             int x, y, z;
             coords(G, c[j], x, y, z);
-            pr[j] = preds_of(S, x, y, z);
+            pr[j] = preds_of(S, x, y, z, fl[j]);
             sm[j] = gp(G.smask)[c[j]];
-            U[j] = (fl[j] & FL_INLET) ? inflow_speed(G, z) : 0.0f;
+            U[j] = (fl[j] & (FL_INLET | FL_MANTLE)) ? inflow_speed(G, z) : 0.0f;
         } else if (general_wave[j] && act[j]) {
             sm[j] = gp(G.smask)[c[j]];   // solid cell: its fill links
         } else if (near_wave[j] && fluid[j]) {
@@ -547,7 +550,7 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
         } else if (general_wave[j]) {
             gather_all<NT>(G, S, pr[j], sm[j], c[j], U[j], inflow_at(G, a.step - 1), g[j], Dirs{});
         } else {
-            const Preds px{pr[j].xlo, pr[j].xhi, false, false, false, false};
+            const Preds px{pr[j].xlo, pr[j].xhi, false, false, false, false, false};
             gather_all<NT>(G, S, px, 0u, c[j], U[j], inflow_at(G, a.step - 1), g[j], Dirs{});
         }
     }
@@ -602,7 +605,7 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
         } else if (general_wave[j]) {
             scatter_all<NT>(G, S, pr[j], sm[j], c[j], U[j], inflow_at(G, a.step), g[j], Dirs{});
         } else {
-            const Preds px{pr[j].xlo, pr[j].xhi, false, false, false, false};
+            const Preds px{pr[j].xlo, pr[j].xhi, false, false, false, false, false};
             scatter_all<NT>(G, S, px, 0u, c[j], U[j], inflow_at(G, a.step), g[j], Dirs{});
         }
     }
@@ -724,7 +727,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         fluid[j] = !(fl[j] & FL_SOLID);
-        if (fluid[j] && (fl[j] & FL_INLET)) inlet_lane = true;
+        if (fluid[j] && (fl[j] & (FL_INLET | FL_MANTLE))) inlet_lane = true;
         near_wave[j] = __any(fluid[j] && (fl[j] & FL_NEAR));
         general_wave[j] = __any(fluid[j] && (fl[j] & FL_GENERAL));
     }
@@ -738,11 +741,11 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
         } else if (general_wave[j]) {
             int x, y, z;
             coords(G, c[j], x, y, z);
-            const Preds pr = preds_of(S, x, y, z);
+            const Preds pr = preds_of(S, x, y, z, fl[j]);
             const uint32_t sm = gp(G.smask)[c[j]];
             adjoint_gather(G, S, pr, sm, c[j], z, T, lin, mu[j], gr0, gr1, gr2, Dirs{});
         } else {
-            const Preds px{(fl[j] & FL_XLO) != 0, (fl[j] & FL_XHI) != 0, false, false, false, false};
+            const Preds px{(fl[j] & FL_XLO) != 0, (fl[j] & FL_XHI) != 0, false, false, false, false, false};
             const int z = (fl[j] & FL_INLET) ? (int)fdiv(c[j], G.dxy) : 0;
             adjoint_gather(G, S, px, 0u, c[j], z, T, lin, mu[j], gr0, gr1, gr2, Dirs{});
         }

@@ -32,6 +32,8 @@ struct Geo3 {
     int64_t cell(int x, int y, int z) const { return ((int64_t)z * b.ny + y) * b.nx + x; }
 };
 
+bool mantle_of(const Geo3 &g, int64_t c) { return (g.fl[c] & FL_MANTLE) != 0; }
+
 void build(Geo3 &g, int nx, int ny, int nz, const int *face, const uint8_t *solid)
 {
     g.b.nx = nx;
@@ -64,7 +66,7 @@ void lbmhc_rules(int nx, int ny, int nz, const int *face, const uint8_t *solid, 
             for (int x = 0; x < nx; ++x) {
                 const int64_t c = g.cell(x, y, z);
                 for (int i = 0; i < Q; ++i)
-                    rules[i * g.n + c] = (g.fl[c] & FL_SOLID) ? -1 : pull_src(g.b, x, y, z, i, g.m[c]).kind;
+                    rules[i * g.n + c] = (g.fl[c] & FL_SOLID) ? -1 : pull_src(g.b, x, y, z, i, g.m[c], mantle_of(g, c)).kind;
             }
 }
 
@@ -86,14 +88,14 @@ int lbmhc_check(int nx, int ny, int nz, const int *face, const uint8_t *solid, i
                 if (g.fl[c] & FL_SOLID) continue;
                 for (int k = 1; k < Q; ++k) {
                     Link d[2];
-                    const int nd = push_dsts(g.b, x, y, z, k, g.m[c], d[0], d[1]);
+                    const int nd = push_dsts(g.b, x, y, z, k, g.m[c], mantle_of(g, c), d[0], d[1]);
                     if (nd == 2) ++stats[2];
                     for (int j = 0; j < nd; ++j) {
                         if (d[j].x < 0 || d[j].x >= nx || d[j].y < 0 || d[j].y >= ny || d[j].z < 0 || d[j].z >= nz)
                             return 1;
                         const int64_t dc = g.cell(d[j].x, d[j].y, d[j].z);
                         if (g.fl[dc] & FL_SOLID) return 2;
-                        const Link s = pull_src(g.b, d[j].x, d[j].y, d[j].z, d[j].pop, g.m[dc]);
+                        const Link s = pull_src(g.b, d[j].x, d[j].y, d[j].z, d[j].pop, g.m[dc], mantle_of(g, dc));
                         if (s.x != x || s.y != y || s.z != z || s.pop != k || s.kind != d[j].kind) return 3;
                         if (hit[(size_t)d[j].pop * g.n + dc]++) return 4;
                     }
@@ -106,7 +108,7 @@ int lbmhc_check(int nx, int ny, int nz, const int *face, const uint8_t *solid, i
                 if (g.fl[c] & FL_SOLID) continue;
                 for (int i = 1; i < Q; ++i) {
                     ++stats[0];
-                    const Link s = pull_src(g.b, x, y, z, i, g.m[c]);
+                    const Link s = pull_src(g.b, x, y, z, i, g.m[c], mantle_of(g, c));
                     if (s.kind != R_STREAM) ++stats[1];
                     if (!hit[(size_t)i * g.n + c]) return 5;  // a link without a source
                     const int64_t sc = g.cell(s.x, s.y, s.z);
@@ -115,7 +117,7 @@ int lbmhc_check(int nx, int ny, int nz, const int *face, const uint8_t *solid, i
                     if (!(g.fl[c] & FL_NEAR)) {
                         if (s.kind != R_STREAM || s.x != x - cx(i) || s.y != y - cy(i) || s.z != z - cz(i)) return 7;
                         Link d[2];
-                        if (push_dsts(g.b, x, y, z, i, g.m[c], d[0], d[1]) != 1 || d[0].kind != R_STREAM) return 8;
+                        if (push_dsts(g.b, x, y, z, i, g.m[c], mantle_of(g, c), d[0], d[1]) != 1 || d[0].kind != R_STREAM) return 8;
                     }
                 }
             }
@@ -130,14 +132,14 @@ int lbmhc_check(int nx, int ny, int nz, const int *face, const uint8_t *solid, i
                 const int64_t c = g.cell(x, y, z);
                 if (g.fl[c] & FL_SOLID) continue;
                 for (int i = 0; i < Q; ++i) {
-                    const Link s = pull_src(g.b, x, y, z, i, g.m[c]);
+                    const Link s = pull_src(g.b, x, y, z, i, g.m[c], mantle_of(g, c));
                     touch[slot(opp(s.pop), g.cell(s.x, s.y, s.z))].push_back(c);
                 }
                 touch[slot(0, c)].push_back(c);
                 ++writes[slot(0, c)];
                 for (int k = 1; k < Q; ++k) {
                     Link d[2];
-                    const int nd = push_dsts(g.b, x, y, z, k, g.m[c], d[0], d[1]);
+                    const int nd = push_dsts(g.b, x, y, z, k, g.m[c], mantle_of(g, c), d[0], d[1]);
                     for (int j = 0; j < nd; ++j) {
                         const int64_t s = slot(d[j].pop, g.cell(d[j].x, d[j].y, d[j].z));
                         touch[s].push_back(c);
@@ -229,18 +231,18 @@ template <int I>
 int check_rel_one(const Geo3 &g, const Shape &s, int x, int y, int z)
 {
     const int64_t c = g.cell(x, y, z);
-    const Preds p = preds_of(s, x, y, z);
+    const Preds p = preds_of(s, x, y, z, g.fl[c]);
     const uint32_t m = g.m[c];
     const RelLink r = gather_rel<I>(s, p, m);
-    const Link src = pull_src(g.b, x, y, z, I, m);
+    const Link src = pull_src(g.b, x, y, z, I, m, p.mantle);
     if (I == 0) {
         if (r.slot != 0 || r.delta != 0 || r.inlet) return 20;
     } else {
         const int64_t want = g.cell(src.x, src.y, src.z);
         if (c + r.delta != want || r.slot != opp(src.pop)) return 21;
-        if (r.inlet != (src.kind == R_INLET)) return 22;
+        if (r.inlet != (src.kind == R_INLET || src.kind == R_MANTLE)) return 22;
         Link d[2];
-        const int nd = push_dsts(g.b, x, y, z, I, m, d[0], d[1]);
+        const int nd = push_dsts(g.b, x, y, z, I, m, p.mantle, d[0], d[1]);
         RelLink a, e;
         scatter_rel<I>(s, p, m, a, e);
         const int nr = (int)a.valid + (int)e.valid;
@@ -252,7 +254,7 @@ int check_rel_one(const Geo3 &g, const Shape &s, int x, int y, int z)
         for (int j = 0; j < nd; ++j) {
             const int64_t dc = g.cell(d[j].x, d[j].y, d[j].z);
             if (c + got[j].delta != dc || got[j].slot != d[j].pop) return 24;
-            if (got[j].inlet != (d[j].kind == R_INLET)) return 25;
+            if (got[j].inlet != (d[j].kind == R_INLET || d[j].kind == R_MANTLE)) return 25;
         }
     }
     return 0;
@@ -266,9 +268,9 @@ int check_xpath_one(const Geo3 &g, const Shape &s, int x, int y, int z)
     const int64_t c = g.cell(x, y, z);
     const uint8_t fl = g.fl[c];
     if (!(fl & FL_NEAR) || (fl & FL_GENERAL)) return 0;
-    const Preds p = preds_of(s, x, y, z);
-    const Preds px{(fl & FL_XLO) != 0, (fl & FL_XHI) != 0, false, false, false, false};
-    if (p.ylo || p.yhi || p.zlo || p.zhi || g.m[c]) return 30;
+    const Preds p = preds_of(s, x, y, z, fl);
+    const Preds px{(fl & FL_XLO) != 0, (fl & FL_XHI) != 0, false, false, false, false, false};
+    if (p.ylo || p.yhi || p.zlo || p.zhi || p.mantle || g.m[c]) return 30;
     const RelLink a = gather_rel<I>(s, p, g.m[c]), b = gather_rel<I>(s, px, 0u);
     if (a.slot != b.slot || a.delta != b.delta || a.inlet != b.inlet) return 31;
     RelLink pa, pe, qa, qe;

@@ -50,6 +50,31 @@ __global__ __launch_bounds__(1024) void k_flush(const Geo *__restrict__ geo, con
     *p = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// Lines (32 consecutive cells: one 128-byte line of each population plane)
+// whose cells are all solid or past the end of the instance.  One wavefront
+// per tile, one lane per line; lines of a plane start at multiples of 32
+// cells because tiles and plane strides are multiples of 64 cells.
+__global__ __launch_bounds__(64) void k_dead_lines(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
+                                                  int32_t n_tiles, int32_t tcells, uint64_t *__restrict__ out)
+{
+    const int tile = blockIdx.x;
+    if (tile >= n_tiles) return;
+    const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
+    const Geo &G = geo[ii];
+    const int lines = tcells >> 5;
+    const int l = threadIdx.x;
+    bool dead = true;
+    if (l < lines) {
+        const int32_t c0 = (tile - G.tile0) * tcells + 32 * l;
+        for (int k = 0; k < 32 && dead; ++k) {
+            const int32_t c = c0 + k;
+            if (c < G.ncells && !(gp(G.flags)[c] & FL_SOLID)) dead = false;
+        }
+    }
+    const uint64_t m = __ballot(l < lines && dead);
+    if (l == 0) out[tile] = m;
+}
+
 // mode 0: fields (ux, uy, uz, |u|) [ncells][4]; mode 1: populations [19][qs]
 template <int PARITY>
 __global__ __launch_bounds__(256) void k_fields(const Geo *__restrict__ geo, int32_t ii, int64_t step, float *out,
@@ -277,6 +302,15 @@ int launch_capture(int tcells, int parity, const Geo *geo, const int32_t *tile_i
 int launch_flush(int tcells, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, hipStream_t s)
 {
     hipLaunchKernelGGL(k_flush, dim3(grid_of(n_tiles)), dim3(tcells), 0, s, geo, tile_inst, n_tiles);
+    return (int)hipGetLastError();
+}
+
+int launch_dead_lines(int tcells, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, uint64_t *out,
+                      hipStream_t s)
+{
+    if (tcells < 32 || tcells > 2048 || (tcells & 31)) return (int)hipErrorInvalidValue;
+    if (n_tiles <= 0) return 0;
+    hipLaunchKernelGGL(k_dead_lines, dim3(n_tiles), dim3(64), 0, s, geo, tile_inst, n_tiles, tcells, out);
     return (int)hipGetLastError();
 }
 

@@ -134,6 +134,7 @@ struct lbm_plan {
     std::vector<Geo> geo_h;
     Geo *geo_d = nullptr;
     int32_t *tiles_d = nullptr;
+    uint64_t *dead_d = nullptr;   // per tile: all-solid 32-cell lines (StepArgs::dead)
     int32_t n_tiles = 0;
     int32_t *health_d = nullptr;
     int64_t step = 0;
@@ -167,6 +168,14 @@ int build_tiles(lbm_plan *p)
     HIPCHK(hipMalloc(&p->tiles_d, sizeof(int32_t) * std::max<size_t>(1, tiles.size())));
     HIPCHK(hipMemcpy(p->tiles_d, tiles.data(), sizeof(int32_t) * tiles.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(p->geo_d, p->geo_h.data(), sizeof(Geo) * p->n_inst, hipMemcpyHostToDevice));
+    // the flags may still be in flight on the caller's geometry stream
+    if (p->dead_d) HIPCHK(hipFree(p->dead_d));
+    p->dead_d = nullptr;
+    HIPCHK(hipMalloc(&p->dead_d, sizeof(uint64_t) * std::max<size_t>(1, tiles.size())));
+    HIPCHK(hipDeviceSynchronize());
+    if (launch_dead_lines(p->v.tile(), p->geo_d, p->tiles_d, p->n_tiles, p->dead_d, nullptr))
+        return fail(LBM_E_HIP, "dead-line launch failed");
+    HIPCHK(hipDeviceSynchronize());
     if (p->gexec) {
         HIPCHK(hipGraphExecDestroy(p->gexec));
         p->gexec = nullptr;
@@ -249,6 +258,7 @@ int ensure_graph(lbm_plan *p)
     HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     StepArgs a{};
     a.step = (p->steady_from + 1) / 2 * 2 + 2;
+    a.dead = p->dead_d;
     HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < p->graph_pairs; ++k) {
         launch_step(p->v, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, cap);
@@ -291,6 +301,7 @@ int run_steps(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_d, i
         }
         StepArgs a{};
         a.step = n;
+        a.dead = p->dead_d;
         // recording runs re-play steps for the adjoint and leave the QoI sums alone
         a.accumulate = (kind == 0 && step_accumulates(p, n)) ? 1 : 0;
         a.record = kind;
@@ -488,6 +499,44 @@ int64_t lbm_population_stride(const lbm_domain *dom)
     return stride_of(ncells_of(dom));
 }
 
+// A fluid cell takes all of its solid links by one rule (the per-cell
+// FL_MANTLE bit), so none may border a building and the mantle region at
+// once.  Walks the fluid neighbours of every building cell.
+static int check_mantle_contact(const lbm_domain *dom, const uint8_t *solid)
+{
+    const int nx = dom->nx, ny = dom->ny, nz = dom->nz;
+    const bool px = dom->face[0] == LBM_PERIODIC, py = dom->face[2] == LBM_PERIODIC, pz = dom->face[4] == LBM_PERIODIC;
+    auto at = [&](int x, int y, int z, bool &in) -> uint8_t {
+        if (px) x = wrap1(x, nx);
+        if (py) y = wrap1(y, ny);
+        if (pz) z = wrap1(z, nz);
+        in = x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz;
+        return in ? solid[((int64_t)z * ny + y) * nx + x] : (uint8_t)CELL_FLUID;
+    };
+    bool any_mantle = false;
+    for (int64_t c = 0, n = (int64_t)nx * ny * nz; c < n && !any_mantle; ++c) any_mantle = solid[c] == CELL_MANTLE;
+    if (!any_mantle) return LBM_OK;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                if (solid[((int64_t)z * ny + y) * nx + x] != CELL_BUILDING) continue;
+                for (int i = 1; i < Q; ++i) {
+                    // fluid cell f = b + c_i sees b as its neighbour f - c_i
+                    int fx = x + cx(i), fy = y + cy(i), fz = z + cz(i);
+                    bool in;
+                    if (at(fx, fy, fz, in) != CELL_FLUID || !in) continue;
+                    if (px) fx = wrap1(fx, nx);
+                    if (py) fy = wrap1(fy, ny);
+                    if (pz) fz = wrap1(fz, nz);
+                    for (int j = 1; j < Q; ++j)
+                        if (at(fx - cx(j), fy - cy(j), fz - cz(j), in) == CELL_MANTLE)
+                            return fail(LBM_E_INVALID, "fluid cell (%d,%d,%d) borders a building and the mantle", fx,
+                                        fy, fz);
+                }
+            }
+    return LBM_OK;
+}
+
 int lbm_init_geometry(const lbm_domain *dom, const uint8_t *solid_host, const int32_t *probe_host, int32_t n_probes,
                       void *geom_dev, float *f_dev, hipStream_t stream)
 {
@@ -502,12 +551,18 @@ int lbm_init_geometry(const lbm_domain *dom, const uint8_t *solid_host, const in
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
-                if (!solid_host[((int64_t)z * ny + y) * nx + x]) continue;
-                if (dom->face[5] == LBM_FREESLIP && z == nz - 1)
-                    return fail(LBM_E_INVALID, "solid cell (%d,%d,%d) in the layer under a free-slip sky", x, y, z);
+                const uint8_t kind = solid_host[((int64_t)z * ny + y) * nx + x];
+                if (kind == CELL_FLUID) continue;
+                if (kind > CELL_MANTLE)
+                    return fail(LBM_E_INVALID, "cell (%d,%d,%d): mask code %d (0 fluid, 1 building, 2 mantle)", x, y,
+                                z, (int)kind);
+                if (dom->face[5] == LBM_FREESLIP && z == nz - 1 && kind == CELL_BUILDING)
+                    return fail(LBM_E_INVALID, "building cell (%d,%d,%d) in the layer under a free-slip sky", x, y, z);
                 if (dom->face[1] == LBM_OUTLET && x >= nx - 2)
                     return fail(LBM_E_INVALID, "solid cell (%d,%d,%d) in the last two columns before an outlet", x, y, z);
             }
+    r = check_mantle_contact(dom, solid_host);
+    if (r) return r;
     for (int32_t k = 0; k < n_probes; ++k) {
         const int32_t c = probe_host[k];
         if (c < 0 || c >= n) return fail(LBM_E_INVALID, "probe %d outside the box", k);
@@ -627,6 +682,7 @@ void lbm_plan_destroy(lbm_plan *p)
     for (auto &kv : p->tables) (void)hipFree(kv.second);
     if (p->geo_d) (void)hipFree(p->geo_d);
     if (p->tiles_d) (void)hipFree(p->tiles_d);
+    if (p->dead_d) (void)hipFree(p->dead_d);
     if (p->health_d) (void)hipFree(p->health_d);
     if (p->gpart_d) (void)hipFree(p->gpart_d);
     delete p;
@@ -887,6 +943,7 @@ int lbm_plan_autotune(lbm_plan *p, hipStream_t s, int32_t variant_out[4])
             if (rc) return rc;
             StepArgs a{};
             a.step = p->steady_from + 2;
+            a.dead = p->dead_d;
             for (int w = 0; w < 2 + pairs; ++w) {
                 if (w == 2) HIPCHK(hipEventRecord(e0, s));
                 launch_step(v, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);

@@ -6,12 +6,16 @@
 // faces.  For a destination link (x, i) the population after streaming is
 // taken from a post-collision value (cell, pop), first matching rule wins,
 // with s = x - c_i (periodic axes wrapped):
-//   BOUNCE   s solid, or s outside through a WALL face      -> (x, opp(i))
-//   INLET    s.x < 0 through the INLET face                  -> (x, opp(i)) + 6 w_i c_i.u_in
-//   FREESLIP s.z >= nz through the FREESLIP sky              -> (x - c_ix [x = nx clamped to
-//                                                               nx-1], y - c_iy, nz-1), zflip(i)
-//   OUTLET   s.x >= nx through the OUTLET face               -> (nx-1, s.y, s.z), i
-//   STREAM   otherwise                                       -> (s, i)
+//   BOUNCE   s a building cell, or s outside through a WALL face -> (x, opp(i))
+//   MANTLE   s in the mantle region of a cylindrical domain      -> (x, opp(i)) + 6 w_i c_i.u_in
+//   INLET    s.x < 0 through the INLET face                      -> (x, opp(i)) + 6 w_i c_i.u_in
+//   FREESLIP s.z >= nz through the FREESLIP sky                  -> (x - c_ix [x = nx clamped to
+//                                                                   nx-1], y - c_iy, nz-1), zflip(i);
+//            MANTLE instead when that reflected source is a mantle cell
+//   OUTLET   s.x >= nx through the OUTLET face                   -> (nx-1, s.y, s.z), i
+//   STREAM   otherwise                                           -> (s, i)
+// The mantle carries the wind by the local velocity condition on the whole
+// surface of the cylinder (Sec. 2.2), in the moving-wall form of the inlet.
 // pull_src() evaluates this map; push_dsts() is its exact inverse (every
 // destination link whose source is a given post-collision value).  Both are
 // compiled for the device (kernels) and the host (exhaustive checks).
@@ -21,7 +25,7 @@
 
 namespace lbmsc {
 
-enum : int { R_STREAM = 0, R_BOUNCE = 1, R_INLET = 2, R_FREESLIP = 3, R_OUTLET = 4, R_REST = 5 };
+enum : int { R_STREAM = 0, R_BOUNCE = 1, R_INLET = 2, R_FREESLIP = 3, R_OUTLET = 4, R_REST = 5, R_MANTLE = 6 };
 
 struct Box {
     int nx, ny, nz;
@@ -37,8 +41,9 @@ struct Link {
 LBM_HD int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 // Source of destination link (x, i).  smask bit i: the (wrapped) neighbour
-// x - c_i lies in the box and is solid.
-LBM_HD Link pull_src(const Box &b, int x, int y, int z, int i, uint32_t smask)
+// x - c_i lies in the box and is solid; mantle: those neighbours are mantle
+// cells (FL_MANTLE).
+LBM_HD Link pull_src(const Box &b, int x, int y, int z, int i, uint32_t smask, bool mantle)
 {
     if (i == 0) return Link{x, y, z, 0, R_REST};
     int sx = x - cx(i), sy = y - cy(i), sz = z - cz(i);
@@ -49,9 +54,12 @@ LBM_HD Link pull_src(const Box &b, int x, int y, int z, int i, uint32_t smask)
     const bool wall = (sx < 0 && b.face[0] == FACE_WALL) || (sx >= b.nx && b.face[1] == FACE_WALL) ||
                       (sy < 0 && b.face[2] == FACE_WALL) || (sy >= b.ny && b.face[3] == FACE_WALL) ||
                       (sz < 0 && b.face[4] == FACE_WALL) || (sz >= b.nz && b.face[5] == FACE_WALL);
-    if ((inside && ((smask >> i) & 1u)) || wall) return Link{x, y, z, opp(i), R_BOUNCE};
+    if (inside && ((smask >> i) & 1u)) return Link{x, y, z, opp(i), mantle ? R_MANTLE : R_BOUNCE};
+    if (wall) return Link{x, y, z, opp(i), R_BOUNCE};
     if (sx < 0 && b.face[0] == FACE_INLET) return Link{x, y, z, opp(i), R_INLET};
     if (sz >= b.nz && b.face[5] == FACE_FREESLIP) {
+        // the reflected source is the in-plane neighbour x - (c_x, c_y, 0)
+        if (mantle && ((smask >> dir_xy(cx(i), cy(i))) & 1u)) return Link{x, y, z, opp(i), R_MANTLE};
         int px = (sx >= b.nx) ? b.nx - 1 : sx;
         return Link{px, sy, b.nz - 1, zflip(i), R_FREESLIP};
     }
@@ -63,7 +71,7 @@ LBM_HD Link pull_src(const Box &b, int x, int y, int z, int i, uint32_t smask)
 // source is the post-collision value (x, k), k != 0, of a fluid cell x.
 // Returns how many (0, 1 or 2), in d0 and d1.  smask is x's own solid-link
 // mask: the neighbour x + c_k is x - c_opp(k), i.e. bit opp(k).
-LBM_HD int push_dsts(const Box &b, int x, int y, int z, int k, uint32_t smask, Link &d0, Link &d1)
+LBM_HD int push_dsts(const Box &b, int x, int y, int z, int k, uint32_t smask, bool mantle, Link &d0, Link &d1)
 {
     int dx = x + cx(k), dy = y + cy(k), dz = z + cz(k);
     if (b.face[0] == FACE_PERIODIC) dx = wrap1(dx, b.nx);
@@ -79,12 +87,16 @@ LBM_HD int push_dsts(const Box &b, int x, int y, int z, int k, uint32_t smask, L
     if (inside && !solid) {
         prim = Link{dx, dy, dz, k, R_STREAM};
     } else if (solid || wall) {
-        prim = Link{x, y, z, opp(k), R_BOUNCE};
+        prim = Link{x, y, z, opp(k), (solid && mantle) ? R_MANTLE : R_BOUNCE};
     } else if (dx < 0 && b.face[0] == FACE_INLET) {
         prim = Link{x, y, z, opp(k), R_INLET};
     } else if (dz >= b.nz && b.face[5] == FACE_FREESLIP && dx >= 0 && dx < b.nx) {
-        // x is in the top layer and c_kz = +1: reflected into (x + c_kx, y + c_ky, nz-1)
-        prim = Link{dx, dy, b.nz - 1, zflip(k), R_FREESLIP};
+        // x is in the top layer and c_kz = +1: reflected into (x + c_kx, y + c_ky, nz-1),
+        // unless that cell, x - (-c_kx, -c_ky, 0), is a mantle cell
+        if (mantle && ((smask >> dir_xy(-cx(k), -cy(k))) & 1u))
+            prim = Link{x, y, z, opp(k), R_MANTLE};
+        else
+            prim = Link{dx, dy, b.nz - 1, zflip(k), R_FREESLIP};
     } else {
         has_prim = false;  // leaves through the outflow or past the sky corner
     }
@@ -114,12 +126,11 @@ LBM_HD int push_dsts(const Box &b, int x, int y, int z, int k, uint32_t smask, L
     return (int)has_prim + (int)has_ext;
 }
 
-// Per-cell flags and solid-link mask.  Bit i of the mask: the neighbour
-// x - c_i (periodic axes wrapped) is in the box and solid.  FL_NEAR marks
-// cells whose links are not all plain in-box streaming from fluid cells
-// (solid or wrapped neighbours, box faces, the outflow column and the sky
-// layer, which also write extra links); the kernels take the general rule
-// path only for those.
+// FL_NEAR marks cells whose links are not all plain in-box streaming from
+// fluid cells (solid or wrapped neighbours, box faces, the outflow column and
+// the sky layer, which also write extra links); the kernels take the general
+// rule path only for those.  FL_MANTLE marks fluid cells next to the mantle
+// region (mask code 2).
 // Per-cell flags and mask.  Fluid cell: bit i of m = the (wrapped) neighbour
 // x - c_i lies in the box and is solid.  Solid cell: bit k of m = the
 // neighbour x + c_k lies in the box without wrapping and is solid; the slot
@@ -152,10 +163,12 @@ LBM_HD void cell_flags(const Box &b, const uint8_t *solid, int x, int y, int z, 
         const bool inside = sx >= 0 && sx < b.nx && !yz_out;
         if (!inside || wrapped) near = true;
         if (wrapped || yz_out) general = true;
-        if (inside && solid[((int64_t)sz * b.ny + sy) * b.nx + sx]) {
+        const uint8_t kind = inside ? solid[((int64_t)sz * b.ny + sy) * b.nx + sx] : CELL_FLUID;
+        if (kind != CELL_FLUID) {
             m |= 1u << i;
             near = true;
             general = true;
+            if (kind == CELL_MANTLE) fl |= FL_MANTLE;
         }
     }
     if (near) fl |= FL_NEAR;
@@ -174,6 +187,7 @@ LBM_HD void cell_flags(const Box &b, const uint8_t *solid, int x, int y, int z, 
 
 struct Preds {
     bool xlo, xhi, ylo, yhi, zlo, zhi;   // cell on the -x, +x, ... face of the box
+    bool mantle;                         // solid neighbours are mantle cells (FL_MANTLE)
 };
 
 struct Shape {
@@ -189,9 +203,9 @@ struct RelLink {
     bool valid;    // the link exists (scatter: a destination)
 };
 
-LBM_HD Preds preds_of(const Shape &s, int x, int y, int z)
+LBM_HD Preds preds_of(const Shape &s, int x, int y, int z, uint8_t fl)
 {
-    return Preds{x == 0, x == s.nx - 1, y == 0, y == s.ny - 1, z == 0, z == s.nz - 1};
+    return Preds{x == 0, x == s.nx - 1, y == 0, y == s.ny - 1, z == 0, z == s.nz - 1, (fl & FL_MANTLE) != 0};
 }
 
 // wrap correction of a periodic axis: moving by -1 from 0, or +1 from n-1
@@ -214,9 +228,15 @@ LBM_HD RelLink gather_rel(const Shape &s, const Preds &p, uint32_t smask)
                       (yb && s.face[2] == FACE_WALL) || (ya && s.face[3] == FACE_WALL) ||
                       (zb && s.face[4] == FACE_WALL) || (za && s.face[5] == FACE_WALL);
     const bool solid = !outside && ((smask >> I) & 1u);
-    const bool bounce = solid || wall;
-    const bool inlet = !bounce && xb && s.face[0] == FACE_INLET;
-    const bool fslip = !bounce && !inlet && za && s.face[5] == FACE_FREESLIP;
+    const bool bounce = (solid && !p.mantle) || wall;
+    const bool mwall = solid && p.mantle;
+    const bool face_in = !bounce && !mwall && xb && s.face[0] == FACE_INLET;
+    const bool sky = !bounce && !mwall && !face_in && za && s.face[5] == FACE_FREESLIP;
+    // the sky's reflected source x - (c_x, c_y, 0) may lie in the mantle
+    constexpr int J = CZ == 0 ? 0 : dir_xy(CX, CY);
+    const bool sky_mantle = sky && p.mantle && ((smask >> J) & 1u);
+    const bool fslip = sky && !sky_mantle;
+    const bool inlet = face_in || mwall || sky_mantle;
     const bool outlet = !bounce && !inlet && !fslip && xa && s.face[1] == FACE_OUTLET;
     const int wx = wrap_corr(px, xb, xa, s.nx);
     const int wy = wrap_corr(py, yb, ya, s.ny) * s.offy;
@@ -273,13 +293,22 @@ LBM_HD void scatter_rel(const Shape &s, const Preds &p, uint32_t smask, RelLink 
     } else if (solid || wall) {
         prim.slot = opp(K);
         prim.delta = 0;
+        prim.inlet = solid && p.mantle;
     } else if (xb && s.face[0] == FACE_INLET) {
         prim.slot = opp(K);
         prim.delta = 0;
         prim.inlet = true;
     } else if (za && s.face[5] == FACE_FREESLIP && (px || !(xb || xa))) {
-        prim.slot = zflip(K);
-        prim.delta = CX + wx + CY * s.offy + wy;
+        // reflected into x + (c_x, c_y, 0) = x - c_J, or the mantle there
+        constexpr int J = CZ == 0 ? 0 : dir_xy(-CX, -CY);
+        if (p.mantle && ((smask >> J) & 1u)) {
+            prim.slot = opp(K);
+            prim.delta = 0;
+            prim.inlet = true;
+        } else {
+            prim.slot = zflip(K);
+            prim.delta = CX + wx + CY * s.offy + wy;
+        }
     } else {
         prim.valid = false;
         prim.slot = K;

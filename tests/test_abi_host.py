@@ -157,6 +157,25 @@ def _random_solid(nx, ny, nz, faces, seed):
     return s
 
 
+def _mantle_solid(nx, ny, nz, faces, seed):
+    """Random mask with mantle cells (code 2) in the low-x part, also in the
+    top layer, and building cells (code 1) in the high-x part, three columns
+    apart (also across a periodic x face), so no fluid cell borders both."""
+    rng = np.random.default_rng(seed)
+    s = np.zeros((nz, ny, nx), np.uint8)
+    xm = max(1, nx // 2 - 2)
+    s[:, :, :xm][rng.random((nz, ny, xm)) < 0.3] = 2
+    xb0, xb1 = nx // 2 + 1, nx - 2
+    if xb1 > xb0:
+        blk = s[:, :, xb0:xb1]
+        blk[rng.random(blk.shape) < 0.15] = 1
+    if faces[5] == "freeslip":
+        s[nz - 1][s[nz - 1] == 1] = 0
+    if faces[1] == "outlet":
+        s[:, :, nx - 2:] = 0
+    return s
+
+
 def _check(nx, ny, nz, faces, solid, block):
     face = (ctypes.c_int * 6)(*[L.FACES[f] for f in faces])
     stats = (ctypes.c_int64 * 7)()
@@ -190,8 +209,46 @@ def test_relative_rules_equal_link_rules(faces):
         assert rc == 0, (faces, nx, ny, nz, rc)
 
 
+@pytest.mark.parametrize("faces", FACE_SETS + [inputs.CYLINDER_FACES])
+@pytest.mark.parametrize("block", [64, 256, 2048])
+def test_mantle_scatter_is_inverse_and_race_free(faces, block):
+    for seed, (nx, ny, nz) in enumerate([(8, 6, 5), (12, 4, 7), (10, 9, 3), (16, 16, 4)]):
+        solid = _mantle_solid(nx, ny, nz, faces, 300 + seed)
+        rc, stats = _check(nx, ny, nz, faces, solid, block)
+        assert rc == 0, (faces, nx, ny, nz, rc, stats)
+
+
+@pytest.mark.parametrize("faces", FACE_SETS + [inputs.CYLINDER_FACES])
+def test_mantle_relative_rules_equal_link_rules(faces):
+    hostcheck().lbmhc_check_relative.restype = ctypes.c_int
+    for seed, (nx, ny, nz) in enumerate([(8, 6, 5), (12, 4, 7), (10, 9, 3), (2, 3, 2), (6, 1, 4)]):
+        if faces[1] == "outlet" and nx % 2:
+            continue
+        solid = _mantle_solid(nx, ny, nz, faces, 400 + seed)
+        face = (ctypes.c_int * 6)(*[L.FACES[f] for f in faces])
+        s = np.ascontiguousarray(solid, np.uint8)
+        rc = hostcheck().lbmhc_check_relative(nx, ny, nz, face, s.ctypes.data_as(ctypes.c_void_p))
+        assert rc == 0, (faces, nx, ny, nz, rc)
+
+
+@pytest.mark.parametrize("faces", FACE_SETS + [inputs.CYLINDER_FACES])
+def test_mantle_rule_kinds_match_oracle(faces):
+    nx, ny, nz = 12, 7, 6
+    solid = _mantle_solid(nx, ny, nz, faces, 17)
+    assert (solid == 2).any()
+    face = (ctypes.c_int * 6)(*[L.FACES[f] for f in faces])
+    mine = np.zeros((19, nx * ny * nz), np.int32)
+    s = np.ascontiguousarray(solid, np.uint8)
+    hostcheck().lbmhc_rules(nx, ny, nz, face, s.ctypes.data_as(ctypes.c_void_p),
+                            mine.ctypes.data_as(ctypes.c_void_p))
+    theirs = orc.Case(nx, ny, nz, list(faces), solid, tau0=0.6).link_rules()
+    assert np.array_equal(mine, theirs)
+    assert (mine == 6).any()                     # mantle links exist
+
+
 @pytest.mark.parametrize("w", [inputs.small_block(), inputs.scaled(inputs.urban_les(), 64, 32, 24),
-                               inputs.scaled(inputs.adjoint_case(), 64, 32, 24)])
+                               inputs.scaled(inputs.adjoint_case(), 64, 32, 24),
+                               inputs.scaled(inputs.cylinder_gpc(), 36, 36, 12, cylinder_radius=16.0)])
 def test_workload_geometries_race_free(w):
     solid = inputs.solid_mask(w)
     for block in (64, 128, 256, 512, 1024, 2048):

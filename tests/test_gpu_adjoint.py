@@ -143,3 +143,16 @@ def test_adjoint_rejects_the_regularised_model():
         assert e.value.code == L.LBM_E_UNSUPPORTED
     finally:
         ens.close()
+
+
+def test_adjoint_cylinder():
+    """Gradient w.r.t. (speed, direction, z0) of a log-law wind entering a
+    cylinder through its mantle (radius 9, one central block, Smagorinsky)
+    against the oracle adjoint: every mantle link carries the inflow
+    sensitivity."""
+    w = inputs.scaled(inputs.cylinder_gpc(), 22, 22, 10, inflow="loglaw", model="smagorinsky", cs=0.1,
+                      tau0=0.56, ramp=10, cylinder_radius=9.0, buildings=(1, 1))
+    solid = inputs.solid_mask(w)
+    assert (solid == 1).any() and (solid == 2).any()
+    thetas = [(0.012, 0.4, 0.5), (0.010, 2.2, 0.5), (0.014, -1.3, 0.4)]
+    _compare(w, solid, thetas, 90, 60, 30, "cylinder adjoint")

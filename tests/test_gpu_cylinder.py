@@ -1,0 +1,195 @@
+"""GPU parity of the cylindrical domain (mask code 2: the mantle region whose
+surface carries the wind by the local velocity condition) against the FP64
+oracle, through the C ABI.
+
+Tolerances as for the box: populations max |g - f| <= 1e-5 max |f| per
+checked step; relative L2 <= 1e-5 per velocity channel of the time-averaged
+fields; <= 1e-4 on quadrature moments and gPC coefficients.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as orc
+from paper_2508_18202_amd import inputs
+from paper_2508_18202_amd import lbmsc as L
+from paper_2508_18202_amd import sc
+from gpu_util import oracle_case, per_channel_rel, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+FIELD_TOL = 1e-5
+MOMENT_TOL = 1e-4
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _small_cylinder(model="smagorinsky", n=28, nz=10, radius=12.0, **kw):
+    base = inputs.cylinder_gpc(hours=4, hour_steps=3, blend_steps=2)
+    args = dict(cylinder_radius=radius, ref_height=float(nz), ramp=2, tau0=0.56, model=model,
+                cs=0.12 if model != "bgk" else 0.0)
+    args.update(kw)
+    return inputs.scaled(base, n, n, nz, **args)
+
+
+@pytest.mark.parametrize("model", ["bgk", "smagorinsky", "rr3"])
+def test_cylinder_step_by_step_populations(model):
+    """Every step of a small cylinder (radius 12, two blocks, series wind
+    that turns every three steps): populations after 1, 2, 3, 4, 9 and 17
+    steps against the oracle; the raw slots of solid cells stay zero."""
+    _say(f"cylinder step-by-step {model}")
+    w = _small_cylinder(model)
+    solid = inputs.solid_mask(w)
+    assert (solid == 1).any() and (solid == 2).any()
+    theta = (1.04, math.radians(5.0), 0.1)
+    cg = sc.make_geometry(w, solid)
+    ens = sc.Ensemble([cg], [[theta]])
+    case = oracle_case(w, solid, theta)
+    f = case.init()
+    _, wl, _ = orc.lattice()
+    fluid = cg.fluid
+    done = 0
+    try:
+        for target in (1, 2, 3, 4, 9, 17):
+            ens.advance(target - done)
+            while done < target:
+                f = case.step(done, f)
+                done += 1
+            g = ens.populations(0).cpu().numpy().astype(np.float64)
+            ref = f - wl[:, None]
+            raw = ens.f[0].view(19, cg.qs)[:, : cg.ncells].cpu().numpy()
+            assert not np.any(raw[:, ~fluid]), target
+            err = np.abs(g[:, fluid] - ref[:, fluid]).max()
+            scale = np.abs(ref[:, fluid]).max()
+            assert err <= 1e-5 * scale + 1e-9, (target, err, scale)
+    finally:
+        ens.close()
+
+
+def test_cylinder_uniform_stream_fixed_point():
+    """A uniform stream at rho = 1 through the empty cylinder (z periodic) is
+    a fixed point of the mantle condition: the GPU keeps it to FP32 rounding."""
+    n, nz, U, ang = 32, 4, 0.05, 0.9
+    w = inputs.scaled(inputs.cylinder_gpc(), n, n, nz, faces=("wall", "wall", "wall", "wall", "periodic", "periodic"),
+                      inflow="uniform", model="bgk", tau0=0.6, cs=0.0, ramp=0, cylinder_radius=14.0,
+                      buildings=None)
+    solid = inputs.cylinder_mask(n, n, nz, 14.0, 0, 0, 0)
+    cg = sc.make_geometry(w, solid)
+    ens = sc.Ensemble([cg], [[(U, ang, 0.0)]])
+    try:
+        feq = orc.equilibrium(1.0, [U * math.cos(ang), U * math.sin(ang), 0.0])
+        _, wl, _ = orc.lattice()
+        f0 = np.repeat((feq - wl)[:, None], cg.ncells, axis=1)
+        f0[:, ~cg.fluid] = 0.0
+        # step 0 keeps the natural layout: the stored f - w, solid slots zero
+        ens.f[0].view(19, cg.qs)[:, : cg.ncells] = torch.from_numpy(f0.astype(np.float32)).cuda()
+        ens.advance(40)
+        g = ens.populations(0).cpu().numpy().astype(np.float64)
+        assert np.abs(g[:, cg.fluid] - f0[:, cg.fluid]).max() < 2e-7
+    finally:
+        ens.close()
+
+
+def test_cylinder_short_horizon_fields_moments_gpc():
+    """The cylinder recipe (Smagorinsky, series wind, 3 x 3 Gauss-Hermite
+    nodes) on a 36 x 36 x 12 box of radius 16, 160 steps with an hour every
+    30, averages over the last 40: fields per node, moments, and the gPC of
+    the probe-line averages against the oracle."""
+    w = inputs.scaled(inputs.cylinder_gpc(hours=5, hour_steps=30, blend_steps=10), 36, 36, 12,
+                      cylinder_radius=16.0, ref_height=12.0, ramp=20, steps=160, avg_start=120, quad_level=3)
+    solid = inputs.solid_mask(w)
+    probes = inputs.probe_cells(w, solid)
+    assert len(probes) > 20
+    _say("cylinder short horizon: GPU")
+    r = sc.run_sc(w, solid, probes=probes)
+    ens = r["ensemble"]
+    try:
+        q = r["q"].cpu().numpy()
+        pq = r["probe_q"].cpu().numpy()
+        fluid = r["geometry"].fluid
+        x, a = orc.collocation(w)
+        assert np.abs(r["nodes"] - x).max() < 1e-12 and np.abs(r["weights"] - a).max() < 1e-14
+        qo, po = [], []
+        for j, xi in enumerate(x):
+            _say(f"cylinder short horizon: oracle node {j}")
+            th = orc.node_params(w, xi)
+            res = orc.run(oracle_case(w, solid, th), w.steps, avg_start=w.avg_start, probes=probes)
+            qo.append(res["avg"])
+            po.append(res["probe"])
+            errs = per_channel_rel(q[j], res["avg"], fluid)
+            assert max(errs) < FIELD_TOL, (j, errs)
+            assert np.abs(pq[j] - res["probe"]).max() < 1e-5 * np.abs(res["probe"]).max()
+        eo, vo = orc.moments(np.stack(qo), a)
+        mean = r["mean"].cpu().numpy().T
+        var = r["var"].cpu().numpy().T
+        for k in range(4):
+            assert rel_l2(mean[k], eo[k], fluid) < MOMENT_TOL
+            assert rel_l2(np.sqrt(np.maximum(var[k], 0)), np.sqrt(np.maximum(vo[k], 0)), fluid) < MOMENT_TOL
+        g = sc.gpc(r["probe_q"], r["nodes"], r["weights"], 2)
+        go = orc.gpc(np.stack(po), x, a, 2)
+        c, co = g["coef"].cpu().numpy(), go["coef"]
+        assert np.abs(c - co).max() <= MOMENT_TOL * np.abs(co).max()
+    finally:
+        ens.close()
+
+
+@pytest.mark.parametrize("variant", [(128, 2, 1, 0), (64, 4, 3, 1), (512, 1, 2, 0), (256, 4, 0, 1)])
+def test_cylinder_launch_shapes_bitwise(variant):
+    """Every launch shape and graph replay (which starts once the series wind
+    is held) give the same populations bit for bit on the cylinder."""
+    w = inputs.scaled(inputs.cylinder_gpc(hours=2, hour_steps=10, blend_steps=4), 36, 36, 12,
+                      cylinder_radius=16.0, ref_height=12.0, ramp=6, quad_level=3)
+    solid = inputs.solid_mask(w)
+    _, _, th = sc.collocation(w)
+    outs = []
+    for kw in (dict(variant=(256, 1, 0, 0), use_graph=False), dict(variant=variant, use_graph=True)):
+        cg = sc.make_geometry(w, solid)
+        ens = sc.Ensemble([cg], [th[:2]], **kw)
+        try:
+            ens.advance(41)
+            outs.append([ens.populations(i).cpu().numpy() for i in range(2)])
+        finally:
+            ens.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_cylinder_rejections():
+    w = _small_cylinder()
+    base = inputs.solid_mask(w)
+
+    def init(solid):
+        cg = sc.make_geometry(w, solid)
+        buf = torch.empty(19 * cg.qs, device="cuda")
+        sc.init_populations(cg, buf)
+
+    init(base)                                     # mantle columns reach the sky: accepted
+    bad = base.copy()
+    ring = np.argwhere(base[0] == 2)
+    y, x = next((int(y), int(x)) for y, x in ring if base[0, y, x + 1] == 0 and x + 3 < w.nx)
+    bad[0, y, x + 2] = 1                           # the fluid cell between touches both kinds
+    with pytest.raises(L.LbmError):
+        init(bad)
+    bad = base.copy()
+    bad[0, w.ny // 2, w.nx // 2] = 3
+    with pytest.raises(L.LbmError):
+        init(bad)
+    bad = base.copy()
+    bad[w.nz - 1, w.ny // 2, w.nx // 2 - 3] = 1    # a building under the free-slip sky
+    with pytest.raises(L.LbmError):
+        init(bad)
