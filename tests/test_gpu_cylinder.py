@@ -181,7 +181,7 @@ def test_cylinder_rejections():
     init(base)                                     # mantle columns reach the sky: accepted
     bad = base.copy()
     ring = np.argwhere(base[0] == 2)
-    y, x = next((int(y), int(x)) for y, x in ring if base[0, y, x + 1] == 0 and x + 3 < w.nx)
+    y, x = next((int(y), int(x)) for y, x in ring if x + 3 < w.nx and base[0, y, x + 1] == 0)
     bad[0, y, x + 2] = 1                           # the fluid cell between touches both kinds
     with pytest.raises(L.LbmError):
         init(bad)
