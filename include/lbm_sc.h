@@ -233,8 +233,10 @@ int lbm_plan_autotune(lbm_plan *plan, hipStream_t stream, int32_t variant_out[4]
  * (gather from neighbours, scatter to neighbours).  QoIs of every state f^n
  * in the plan's window are accumulated: qoi sums of (ux, uy, uz, |u|) and
  * probe sums of u_x (solid cells contribute nothing).  The 19 slots of a
- * solid cell carry no state: no rule reads them, and the even step swaps
- * them pairwise without collision (zero stays zero after lbm_init_geometry). */
+ * solid cell carry no state: no rule reads them, the even step swaps them
+ * pairwise without collision and the odd step writes zero into them (zero
+ * stays zero after lbm_init_geometry); runs of 32 consecutive solid cells
+ * are not touched at all. */
 int lbm_collide_stream(lbm_plan *plan, int32_t n_steps, hipStream_t stream);
 
 /* Same, and also record the state of every step n for the adjoint sweep

@@ -51,16 +51,16 @@ enum : int { FACE_WALL = 0, FACE_INLET = 1, FACE_OUTLET = 2, FACE_FREESLIP = 3, 
 //   SOLID    solid cell
 //   NEAR     some link of the cell is not plain in-box streaming
 //   PROBE    probe cell
-//   INLET    on the inflow face (x = 0 with an INLET face)
+//   FACE     some link of the cell crosses a y or z face of the box (wrapped
+//            or not) or the sky
 //   GENERAL  NEAR for a reason other than being in the x = 0 or x = nx-1
-//            column of non-periodic x faces (solid neighbour, y or z face,
-//            periodic wrap, sky layer)
+//            column of non-periodic x faces (solid neighbour, FACE, x wrap)
 //   XLO/XHI  x = 0 / x = nx-1
 //   MANTLE   fluid cell whose solid neighbours belong to the mantle region
 //            of a cylindrical domain (all of them: a cell may not border a
 //            building and the mantle at once)
 enum : uint8_t {
-    FL_SOLID = 1, FL_NEAR = 2, FL_PROBE = 4, FL_INLET = 8, FL_GENERAL = 16, FL_XLO = 32, FL_XHI = 64,
+    FL_SOLID = 1, FL_NEAR = 2, FL_PROBE = 4, FL_FACE = 8, FL_GENERAL = 16, FL_XLO = 32, FL_XHI = 64,
     FL_MANTLE = 128
 };
 

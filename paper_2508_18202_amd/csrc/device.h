@@ -145,6 +145,13 @@ __device__ __forceinline__ float inlet_term(int i, float U, const InflowT &T)
     return 6.0f * wgt(i) * U * T.scale * ((float)cx(i) * T.cphi + (float)cy(i) * T.sphi);
 }
 
+// The cell has links with the moving-wall momentum: on the inflow face, or
+// next to the mantle region.
+__device__ __forceinline__ bool inflow_lane(const Geo &G, uint8_t fl)
+{
+    return (fl & FL_MANTLE) || ((fl & FL_XLO) && G.box.face[0] == FACE_INLET);
+}
+
 __device__ __forceinline__ int probe_index(const Geo &G, int32_t c)
 {
     int lo = 0, hi = G.n_probes - 1;
@@ -249,7 +256,7 @@ __device__ __forceinline__ void load_state(const Geo &G, uint32_t c, uint8_t fl,
         const Shape S = shape_of(G);
         const Preds p = preds_of(S, x, y, z, fl);
         const uint32_t sm = gp(G.smask)[c];
-        const float U = (fl & (FL_INLET | FL_MANTLE)) ? inflow_speed(G, z) : 0.0f;
+        const float U = inflow_lane(G, fl) ? inflow_speed(G, z) : 0.0f;
         gather_all(G, S, p, sm, c, U, inflow_at(G, n - 1), g, Dirs{});
     }
 }
@@ -493,7 +500,7 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
 
     uint32_t c[CPT];
     uint8_t fl[CPT];
-    bool act[CPT], fluid[CPT], near_wave[CPT], general_wave[CPT];
+    bool act[CPT], fluid[CPT], near_wave[CPT], general_wave[CPT], face_wave[CPT], flow_wave[CPT];
     Preds pr[CPT];
     uint32_t sm[CPT];
     float U[CPT];
@@ -518,27 +525,33 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
         }
         fl[j] = active ? gp(G.flags)[c[j]] : (uint8_t)FL_SOLID;
         fluid[j] = !(fl[j] & FL_SOLID);
-        // odd steps: wavefronts without boundary cells take the plain stencil;
-        // wavefronts whose boundary cells only sit in the inflow/outflow
-        // columns evaluate the x rules for all lanes; the others evaluate the
-        // full rules for all lanes
+        // odd steps, per wavefront: without boundary cells the plain stencil;
+        // with boundary cells only in the x = 0 / nx-1 columns the x rules;
+        // with solid neighbours but no y/z face, wrap or sky link the x and
+        // solid-link rules (y/z terms dropped at compile time); otherwise the
+        // full rules.  The inflow is evaluated only where a lane needs it.
+        const bool flow = fluid[j] && inflow_lane(G, fl[j]);
         near_wave[j] = PARITY == 1 && __any(fluid[j] && (fl[j] & FL_NEAR));
         general_wave[j] = PARITY == 1 && __any(fluid[j] && (fl[j] & FL_GENERAL));
+        face_wave[j] = PARITY == 1 && __any(fluid[j] && (fl[j] & FL_FACE));
+        flow_wave[j] = PARITY == 1 && __any(flow);
         pr[j] = Preds{false, false, false, false, false, false, false};
         sm[j] = 0;
         U[j] = 0.0f;
-        if (general_wave[j] && fluid[j]) {
+        if (face_wave[j] && fluid[j]) {
             int x, y, z;
             coords(G, c[j], x, y, z);
             pr[j] = preds_of(S, x, y, z, fl[j]);
             sm[j] = gp(G.smask)[c[j]];
-            U[j] = (fl[j] & (FL_INLET | FL_MANTLE)) ? inflow_speed(G, z) : 0.0f;
-        } else if (general_wave[j] && act[j]) {
-            sm[j] = gp(G.smask)[c[j]];   // solid cell: its fill links
+            U[j] = flow ? inflow_speed(G, z) : 0.0f;
+        } else if (general_wave[j] && fluid[j]) {
+            sm[j] = gp(G.smask)[c[j]];
+            pr[j] = preds_xs(fl[j]);
+            if (flow) U[j] = inflow_speed(G, (int)fdiv(c[j], G.dxy));
         } else if (near_wave[j] && fluid[j]) {
             pr[j].xlo = fl[j] & FL_XLO;
             pr[j].xhi = fl[j] & FL_XHI;
-            if (fl[j] & FL_INLET) U[j] = inflow_speed(G, (int)fdiv(c[j], G.dxy));
+            if (flow) U[j] = inflow_speed(G, (int)fdiv(c[j], G.dxy));
         }
     }
 #pragma unroll
@@ -547,11 +560,17 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
         if (!near_wave[j]) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) g[j][i] = ldg<NT>(f + (size_t)opp(i) * qs - off_of(G, i), c[j]);
+            continue;
+        }
+        const InflowT T = flow_wave[j] ? inflow_at(G, a.step - 1) : InflowT{0.f, 0.f, 0.f, 0.f};
+        if (face_wave[j]) {
+            gather_all<NT>(G, S, pr[j], sm[j], c[j], U[j], T, g[j], Dirs{});
         } else if (general_wave[j]) {
-            gather_all<NT>(G, S, pr[j], sm[j], c[j], U[j], inflow_at(G, a.step - 1), g[j], Dirs{});
+            const Preds ps{pr[j].xlo, pr[j].xhi, false, false, false, false, pr[j].mantle};
+            gather_all<NT>(G, S, ps, sm[j], c[j], U[j], T, g[j], Dirs{});
         } else {
             const Preds px{pr[j].xlo, pr[j].xhi, false, false, false, false, false};
-            gather_all<NT>(G, S, px, 0u, c[j], U[j], inflow_at(G, a.step - 1), g[j], Dirs{});
+            gather_all<NT>(G, S, px, 0u, c[j], U[j], T, g[j], Dirs{});
         }
     }
 #pragma unroll
@@ -589,24 +608,30 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
             continue;
         }
         if (!fluid[j]) {
-            // solid cells of boundary wavefronts write zero into the slots of
-            // their solid-to-solid links, which only they own, so that the
-            // wavefront's stores cover whole lines around the solid body
-            if (general_wave[j] && act[j]) {
+            // no fluid cell reads or writes a slot of a solid cell (links into
+            // solids resolve to the fluid side's own slots), so each solid cell
+            // of a live line writes zero into its own 19 slots: with the fluid
+            // cells' scatter, every line of every plane is written whole
+            if (act[j]) {
 #pragma unroll
-                for (int k = 1; k < Q; ++k)
-                    if ((sm[j] >> k) & 1u) stg<NT>(f + (size_t)k * qs + off_of(G, k), c[j], 0.0f);
+                for (int k = 0; k < Q; ++k) stg<NT>(f + (size_t)k * qs, c[j], 0.0f);
             }
             continue;
         }
         if (!near_wave[j]) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) stg<NT>(f + (size_t)i * qs + off_of(G, i), c[j], g[j][i]);
+            continue;
+        }
+        const InflowT T = flow_wave[j] ? inflow_at(G, a.step) : InflowT{0.f, 0.f, 0.f, 0.f};
+        if (face_wave[j]) {
+            scatter_all<NT>(G, S, pr[j], sm[j], c[j], U[j], T, g[j], Dirs{});
         } else if (general_wave[j]) {
-            scatter_all<NT>(G, S, pr[j], sm[j], c[j], U[j], inflow_at(G, a.step), g[j], Dirs{});
+            const Preds ps{pr[j].xlo, pr[j].xhi, false, false, false, false, pr[j].mantle};
+            scatter_all<NT>(G, S, ps, sm[j], c[j], U[j], T, g[j], Dirs{});
         } else {
             const Preds px{pr[j].xlo, pr[j].xhi, false, false, false, false, false};
-            scatter_all<NT>(G, S, px, 0u, c[j], U[j], inflow_at(G, a.step), g[j], Dirs{});
+            scatter_all<NT>(G, S, px, 0u, c[j], U[j], T, g[j], Dirs{});
         }
     }
 }
@@ -702,13 +727,12 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
     const GLOBAL_AS float *__restrict__ lin = gp(a.lam_in[ii]);
     GLOBAL_AS float *__restrict__ lout = gp(a.lam_out[ii]);
     const int32_t base = (tile - G.tile0) * (BS * CPT) + (int32_t)threadIdx.x;
-    const InflowT T = inflow_at(G, a.step);
     double gr0 = 0.0, gr1 = 0.0, gr2 = 0.0;
     bool inlet_lane = false;
 
     uint32_t c[CPT];
     uint8_t fl[CPT];
-    bool act[CPT], fluid[CPT], near_wave[CPT], general_wave[CPT];
+    bool act[CPT], fluid[CPT], near_wave[CPT], general_wave[CPT], face_wave[CPT];
     float mu[CPT][Q];
     f32x4 st[CPT];                 // (rho, ux, uy, uz) of a kind-1 record
     float gs[CPT][Q];              // populations of a kind-2 record
@@ -727,10 +751,13 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         fluid[j] = !(fl[j] & FL_SOLID);
-        if (fluid[j] && (fl[j] & (FL_INLET | FL_MANTLE))) inlet_lane = true;
+        if (fluid[j] && inflow_lane(G, fl[j])) inlet_lane = true;
         near_wave[j] = __any(fluid[j] && (fl[j] & FL_NEAR));
         general_wave[j] = __any(fluid[j] && (fl[j] & FL_GENERAL));
+        face_wave[j] = __any(fluid[j] && (fl[j] & FL_FACE));
     }
+    // the inflow only where a lane of the wavefront has moving-wall links
+    const InflowT T = __any(inlet_lane) ? inflow_at(G, a.step) : InflowT{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         if (!fluid[j]) continue;
@@ -738,15 +765,20 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
         if (!near_wave[j]) {
 #pragma unroll
             for (int k = 0; k < Q; ++k) mu[j][k] = ldg(lin + (size_t)k * qs + off_of(G, k), c[j]);
-        } else if (general_wave[j]) {
+        } else if (face_wave[j]) {
             int x, y, z;
             coords(G, c[j], x, y, z);
             const Preds pr = preds_of(S, x, y, z, fl[j]);
             const uint32_t sm = gp(G.smask)[c[j]];
             adjoint_gather(G, S, pr, sm, c[j], z, T, lin, mu[j], gr0, gr1, gr2, Dirs{});
+        } else if (general_wave[j]) {
+            const Preds ps = preds_xs(fl[j]);
+            const uint32_t sm = gp(G.smask)[c[j]];
+            const int z = inflow_lane(G, fl[j]) ? (int)fdiv(c[j], G.dxy) : 0;
+            adjoint_gather(G, S, ps, sm, c[j], z, T, lin, mu[j], gr0, gr1, gr2, Dirs{});
         } else {
             const Preds px{(fl[j] & FL_XLO) != 0, (fl[j] & FL_XHI) != 0, false, false, false, false, false};
-            const int z = (fl[j] & FL_INLET) ? (int)fdiv(c[j], G.dxy) : 0;
+            const int z = inflow_lane(G, fl[j]) ? (int)fdiv(c[j], G.dxy) : 0;
             adjoint_gather(G, S, px, 0u, c[j], z, T, lin, mu[j], gr0, gr1, gr2, Dirs{});
         }
         if (a.record != 1) {

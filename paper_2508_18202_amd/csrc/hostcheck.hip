@@ -73,7 +73,7 @@ void lbmhc_rules(int nx, int ny, int nz, const int *face, const uint8_t *solid, 
 // Returns 0 when all properties hold, otherwise a code; stats[0..6] =
 // fluid links, links through a non-plain rule, values with two destinations,
 // shared slots, shared slots spanning two workgroups, slots written twice,
-// fill writes of solid cells.
+// zero writes of solid cells into their own slots.
 int lbmhc_check(int nx, int ny, int nz, const int *face, const uint8_t *solid, int block, int64_t *stats)
 {
     Geo3 g;
@@ -148,23 +148,15 @@ int lbmhc_check(int nx, int ny, int nz, const int *face, const uint8_t *solid, i
                 }
             }
     if (stats[5]) return 9;
-    // fill writes of solid cells: into solid cells' slots only, one writer
-    // each, never touched by a fluid cell
-    std::unordered_map<int64_t, int> fills;
+    // the odd step writes zero into every slot of every solid cell: no fluid
+    // cell may read or write any of them
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 const int64_t c = g.cell(x, y, z);
                 if (!(g.fl[c] & FL_SOLID)) continue;
-                for (int k = 1; k < Q; ++k) {
-                    if (!((g.m[c] >> k) & 1u)) continue;
-                    const int dx = x + cx(k), dy = y + cy(k), dz = z + cz(k);
-                    if (dx < 0 || dx >= nx || dy < 0 || dy >= ny || dz < 0 || dz >= nz) return 11;
-                    const int64_t dc = g.cell(dx, dy, dz);
-                    if (!(g.fl[dc] & FL_SOLID)) return 11;
-                    const int64_t s = slot(k, dc);
-                    if (touch.count(s)) return 12;
-                    if (fills[s]++) return 13;
+                for (int k = 0; k < Q; ++k) {
+                    if (touch.count(slot(k, c))) return 12;
                     ++stats[6];
                 }
             }
@@ -180,6 +172,14 @@ int lbmhc_check(int nx, int ny, int nz, const int *face, const uint8_t *solid, i
     }
     if (stats[4]) return 10;
     return 0;
+}
+
+// Per-cell flag bytes as the kernels see them.
+void lbmhc_flags(int nx, int ny, int nz, const int *face, const uint8_t *solid, uint8_t *fl)
+{
+    Geo3 g;
+    build(g, nx, ny, nz, face, solid);
+    for (int64_t c = 0; c < g.n; ++c) fl[c] = g.fl[c];
 }
 
 // Tile order of a launch: out[p] = tile_order(p, grid, mode) for p < grid.
@@ -282,6 +282,37 @@ int check_xpath_one(const Geo3 &g, const Shape &s, int x, int y, int z)
     return 0;
 }
 
+// cells flagged GENERAL but not FACE: the x and solid-link form (y/z
+// predicates dropped, solid mask and mantle bit kept) must give the full
+// form's links
+template <int I>
+int check_xs_one(const Geo3 &g, const Shape &s, int x, int y, int z)
+{
+    const int64_t c = g.cell(x, y, z);
+    const uint8_t fl = g.fl[c];
+    if (!(fl & FL_GENERAL) || (fl & FL_FACE)) return 0;
+    const Preds p = preds_of(s, x, y, z, fl);
+    const Preds q = preds_xs(fl);
+    if (p.ylo || p.yhi || p.zlo || p.zhi) return 40;
+    const RelLink a = gather_rel<I>(s, p, g.m[c]), b = gather_rel<I>(s, q, g.m[c]);
+    if (a.slot != b.slot || a.delta != b.delta || a.inlet != b.inlet) return 41;
+    RelLink pa, pe, qa, qe;
+    scatter_rel<I>(s, p, g.m[c], pa, pe);
+    scatter_rel<I>(s, q, g.m[c], qa, qe);
+    if (pa.valid != qa.valid || pe.valid != qe.valid) return 42;
+    if (pa.valid && (pa.slot != qa.slot || pa.delta != qa.delta || pa.inlet != qa.inlet)) return 43;
+    if (pe.valid && (pe.slot != qe.slot || pe.delta != qe.delta)) return 44;
+    return 0;
+}
+
+template <int... Is>
+int check_xs_all(const Geo3 &g, const Shape &s, int x, int y, int z, std::integer_sequence<int, Is...>)
+{
+    int r = 0;
+    ((r = r ? r : check_xs_one<Is>(g, s, x, y, z)), ...);
+    return r;
+}
+
 template <int... Is>
 int check_xpath_all(const Geo3 &g, const Shape &s, int x, int y, int z, std::integer_sequence<int, Is...>)
 {
@@ -311,6 +342,7 @@ extern "C" int lbmhc_check_relative(int nx, int ny, int nz, const int *face, con
                 if (g.fl[g.cell(x, y, z)] & FL_SOLID) continue;
                 int r = check_rel_all(g, s, x, y, z, std::make_integer_sequence<int, Q>{});
                 if (!r) r = check_xpath_all(g, s, x, y, z, std::make_integer_sequence<int, Q>{});
+                if (!r) r = check_xs_all(g, s, x, y, z, std::make_integer_sequence<int, Q>{});
                 if (r) return r;
             }
     return 0;

@@ -132,37 +132,29 @@ LBM_HD int push_dsts(const Box &b, int x, int y, int z, int k, uint32_t smask, b
 // rule path only for those.  FL_MANTLE marks fluid cells next to the mantle
 // region (mask code 2).
 // Per-cell flags and mask.  Fluid cell: bit i of m = the (wrapped) neighbour
-// x - c_i lies in the box and is solid.  Solid cell: bit k of m = the
-// neighbour x + c_k lies in the box without wrapping and is solid; the slot
-// (k, x + c_k) of such a link is touched by no fluid cell's rules (links into
-// solid cells resolve to the fluid side's own slots), so the odd step may
-// fill it to keep whole cache lines written.
+// x - c_i lies in the box and is solid.  Solid cell: FL_SOLID, no mask.
 LBM_HD void cell_flags(const Box &b, const uint8_t *solid, int x, int y, int z, uint8_t &fl, uint32_t &m)
 {
     fl = 0;
     m = 0;
     if (solid[((int64_t)z * b.ny + y) * b.nx + x]) {
         fl = FL_SOLID;
-        for (int k = 1; k < Q; ++k) {
-            const int dx = x + cx(k), dy = y + cy(k), dz = z + cz(k);
-            if (dx >= 0 && dx < b.nx && dy >= 0 && dy < b.ny && dz >= 0 && dz < b.nz &&
-                solid[((int64_t)dz * b.ny + dy) * b.nx + dx])
-                m |= 1u << k;
-        }
         return;
     }
     bool near = (x == b.nx - 1) || (z == b.nz - 1);
     bool general = z == b.nz - 1;
+    bool face = z == b.nz - 1;
     for (int i = 1; i < Q; ++i) {
         int sx = x - cx(i), sy = y - cy(i), sz = z - cz(i);
-        bool wrapped = false;
-        if (b.face[0] == FACE_PERIODIC && (sx < 0 || sx >= b.nx)) { sx = wrap1(sx, b.nx); wrapped = true; }
-        if (b.face[2] == FACE_PERIODIC && (sy < 0 || sy >= b.ny)) { sy = wrap1(sy, b.ny); wrapped = true; }
-        if (b.face[4] == FACE_PERIODIC && (sz < 0 || sz >= b.nz)) { sz = wrap1(sz, b.nz); wrapped = true; }
+        bool xw = false, yzw = false;
+        if (b.face[0] == FACE_PERIODIC && (sx < 0 || sx >= b.nx)) { sx = wrap1(sx, b.nx); xw = true; }
+        if (b.face[2] == FACE_PERIODIC && (sy < 0 || sy >= b.ny)) { sy = wrap1(sy, b.ny); yzw = true; }
+        if (b.face[4] == FACE_PERIODIC && (sz < 0 || sz >= b.nz)) { sz = wrap1(sz, b.nz); yzw = true; }
         const bool yz_out = sy < 0 || sy >= b.ny || sz < 0 || sz >= b.nz;
         const bool inside = sx >= 0 && sx < b.nx && !yz_out;
-        if (!inside || wrapped) near = true;
-        if (wrapped || yz_out) general = true;
+        if (!inside || xw || yzw) near = true;
+        if (xw || yzw || yz_out) general = true;
+        if (yzw || yz_out) face = true;
         const uint8_t kind = inside ? solid[((int64_t)sz * b.ny + sy) * b.nx + sx] : CELL_FLUID;
         if (kind != CELL_FLUID) {
             m |= 1u << i;
@@ -173,10 +165,11 @@ LBM_HD void cell_flags(const Box &b, const uint8_t *solid, int x, int y, int z, 
     }
     if (near) fl |= FL_NEAR;
     if (near && general) fl |= FL_GENERAL;
+    if (face) fl |= FL_FACE;
     if (x == 0) fl |= FL_XLO;
     if (x == b.nx - 1) fl |= FL_XHI;
-    if (x == 0 && b.face[0] == FACE_INLET) fl |= FL_INLET;
 }
+
 
 // ---------------------------------------------------------------------------
 // The same rules in relative form, for one compile-time direction: the source
@@ -206,6 +199,14 @@ struct RelLink {
 LBM_HD Preds preds_of(const Shape &s, int x, int y, int z, uint8_t fl)
 {
     return Preds{x == 0, x == s.nx - 1, y == 0, y == s.ny - 1, z == 0, z == s.nz - 1, (fl & FL_MANTLE) != 0};
+}
+
+// A cell without FL_FACE lies strictly inside the box in y and z, so the
+// y/z predicates of preds_of() are false for it; this form of the
+// predicates lets the compiler drop every y/z face term.
+LBM_HD Preds preds_xs(uint8_t fl)
+{
+    return Preds{(fl & FL_XLO) != 0, (fl & FL_XHI) != 0, false, false, false, false, (fl & FL_MANTLE) != 0};
 }
 
 // wrap correction of a periodic axis: moving by -1 from 0, or +1 from n-1

@@ -191,7 +191,7 @@ def test_scatter_is_inverse_and_race_free(faces, block):
         solid = _random_solid(nx, ny, nz, faces, seed)
         rc, stats = _check(nx, ny, nz, faces, solid, block)
         assert rc == 0, (faces, nx, ny, nz, rc, stats)
-        assert stats[0] > 0 and stats[6] > 0     # fill writes of solid cells exist and are exclusive
+        assert stats[0] > 0 and stats[6] > 0     # zero writes of solid cells exist, untouched by fluid cells
 
 
 @pytest.mark.parametrize("faces", FACE_SETS)
@@ -341,3 +341,35 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(got[name]) == ctypes.sizeof(cls), name
         for field, *_ in cls._fields_:
             assert int(got[f"{name}.{field}"]) == getattr(cls, field).offset, (name, field)
+
+
+FL = {"solid": 1, "near": 2, "probe": 4, "face": 8, "general": 16, "xlo": 32, "xhi": 64, "mantle": 128}
+
+
+def _flags(w, solid):
+    face = (ctypes.c_int * 6)(*[L.FACES[f] for f in w.faces])
+    out = np.zeros(w.nx * w.ny * w.nz, np.uint8)
+    s = np.ascontiguousarray(solid, np.uint8)
+    hostcheck().lbmhc_flags(w.nx, w.ny, w.nz, face, s.ctypes.data_as(ctypes.c_void_p),
+                            out.ctypes.data_as(ctypes.c_void_p))
+    return out.reshape(w.nz, w.ny, w.nx)
+
+
+@pytest.mark.parametrize("w", [inputs.scaled(inputs.cylinder_gpc(), 36, 36, 12, cylinder_radius=16.0),
+                               inputs.scaled(inputs.urban_les(), 64, 32, 24)])
+def test_face_flag_marks_exactly_the_face_layers(w):
+    """FL_FACE (a link crosses a y/z face, wraps in y/z, or meets the sky) is
+    set exactly on fluid cells of the first/last y and z layers: the
+    solid-neighbour wavefront path, which drops the y/z predicates, is then
+    taken only by cells strictly inside in y and z."""
+    solid = inputs.solid_mask(w)
+    fl = _flags(w, solid)
+    fluid = solid == 0
+    z, y, _ = np.indices(fl.shape)
+    edge = (z == 0) | (z == w.nz - 1) | (y == 0) | (y == w.ny - 1)
+    has_face = (fl & FL["face"]) != 0
+    assert np.array_equal(has_face[fluid], edge[fluid])
+    general = (fl & FL["general"]) != 0
+    assert (general & ~has_face & fluid).sum() > 0       # the reduced path has work
+    mantle = (fl & FL["mantle"]) != 0
+    assert mantle.any() == (w.cylinder_radius > 0)
