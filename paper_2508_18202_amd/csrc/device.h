@@ -75,6 +75,8 @@ __device__ __forceinline__ void stg(GLOBAL_AS T *base, uint32_t idx, T v)
     else *p = v;
 }
 
+__device__ __forceinline__ uint32_t umin_u32(uint32_t a, uint32_t b) { return a < b ? a : b; }
+
 // Workgroups are dispatched round-robin over the 8 XCDs; tile_order() (see
 // rules.h) chooses which tile each block index takes.
 __device__ __forceinline__ int xcd_tile() { return tile_order((int)blockIdx.x, (int)gridDim.x, 1); }
@@ -199,16 +201,21 @@ __device__ __forceinline__ Shape shape_of(const Geo &G)
 
 // Boundary-aware gather of all 19 populations f^n(x) from the swapped
 // post-collision values of step n-1, one compile-time direction at a time.
-template <bool NT = false, int... Is>
+// CLAMP: the neighbour index is clamped into the instance (speculative
+// gathers of lanes whose cell kind is not known yet).
+template <bool NT = false, bool CLAMP = false, int... Is>
 __device__ __forceinline__ void gather_all(const Geo &G, const Shape &S, const Preds &p, uint32_t sm, uint32_t c,
                                            float U, const InflowT &T, float g[Q], std::integer_sequence<int, Is...>)
 {
     const GLOBAL_AS float *__restrict__ f = gp(G.f);
     const uint32_t qs = (uint32_t)G.qs;
+    const uint32_t last = (uint32_t)G.ncells - 1u;
     (
         [&] {
             const RelLink l = gather_rel<Is>(S, p, sm);
-            const float v = ldg<NT>(f, (uint32_t)l.slot * qs + (uint32_t)((int32_t)c + l.delta));
+            uint32_t n = (uint32_t)((int32_t)c + l.delta);
+            if (CLAMP) n = umin_u32(n, last);
+            const float v = ldg<NT>(f, (uint32_t)l.slot * qs + n);
             g[Is] = l.inlet ? v + inlet_term(Is, U, T) : v;
         }(),
         ...);
@@ -494,19 +501,23 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
     GLOBAL_AS float *__restrict__ f = gp(G.f);
     const uint32_t qs = (uint32_t)G.qs;
     const int32_t base = (tile - G.tile0) * (BS * CPT) + (int32_t)threadIdx.x;
-    // all-solid lines of the tile carry no state and no neighbour's rule
-    // touches them: their cells are skipped like cells past the end
-    const uint64_t dead = a.dead ? a.dead[tile] : 0ull;
+    // per-tile words: all-solid lines (skipped like cells past the end: they
+    // carry no state and no neighbour's rule touches them) and the rule class
+    // of each wavefront (launch_tile_info)
+    const uint64_t dead = a.tinfo ? a.tinfo[2 * (size_t)tile] : 0ull;
+    const uint64_t wcls = a.tinfo ? a.tinfo[2 * (size_t)tile + 1] : ~0ull;
 
     uint32_t c[CPT];
     uint8_t fl[CPT];
-    bool act[CPT], fluid[CPT], near_wave[CPT], general_wave[CPT], face_wave[CPT], flow_wave[CPT];
+    int cls[CPT];
+    bool act[CPT], fluid[CPT], flow_wave[CPT];
     Preds pr[CPT];
     uint32_t sm[CPT];
     float U[CPT];
     float g[CPT][Q];
     Shape S;
     if (PARITY == 1) S = shape_of(G);
+    const uint32_t last = (uint32_t)G.ncells - 1u;
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         const int32_t lc = base + j * BS;
@@ -523,54 +534,69 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
 #pragma unroll
             for (int i = 0; i < Q; ++i) g[j][i] = ldg<NT>(f + (size_t)i * qs, c[j]);
         }
-        fl[j] = active ? gp(G.flags)[c[j]] : (uint8_t)FL_SOLID;
-        fluid[j] = !(fl[j] & FL_SOLID);
-        // odd steps, per wavefront: without boundary cells the plain stencil;
-        // with boundary cells only in the x = 0 / nx-1 columns the x rules;
-        // with solid neighbours but no y/z face, wrap or sky link the x and
-        // solid-link rules (y/z terms dropped at compile time); otherwise the
-        // full rules.  The inflow is evaluated only where a lane needs it.
-        const bool flow = fluid[j] && inflow_lane(G, fl[j]);
-        near_wave[j] = PARITY == 1 && __any(fluid[j] && (fl[j] & FL_NEAR));
-        general_wave[j] = PARITY == 1 && __any(fluid[j] && (fl[j] & FL_GENERAL));
-        face_wave[j] = PARITY == 1 && __any(fluid[j] && (fl[j] & FL_FACE));
-        flow_wave[j] = PARITY == 1 && __any(flow);
+        // Odd steps, per wavefront (class from the tile words): 0 the plain
+        // stencil; 1 the x rules (boundary cells only in the x = 0 / nx-1
+        // columns); 2 the x and solid-link rules (solid neighbours but no y/z
+        // face, wrap or sky link; y/z terms dropped at compile time); 3 the
+        // full rules.  Classes 0 and 1 take their addresses from the cell
+        // index alone, so their gathers are issued before the flag byte
+        // arrives, with the neighbour index clamped into the instance: lanes
+        // of solid cells stay in bounds and their values are dropped.  The
+        // inflow is evaluated only in wavefronts with a moving-wall lane.
+        cls[j] = PARITY == 1 ? (int)((wcls >> (2 * ((j * BS + (int)threadIdx.x) >> 6))) & 3ull) : 0;
         pr[j] = Preds{false, false, false, false, false, false, false};
         sm[j] = 0;
         U[j] = 0.0f;
-        if (face_wave[j] && fluid[j]) {
+        flow_wave[j] = false;
+        if (PARITY == 1 && cls[j] == 0) {
+            if (active) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    g[j][i] = ldg<NT>(f + (size_t)opp(i) * qs, umin_u32((uint32_t)((int32_t)c[j] - off_of(G, i)), last));
+            }
+        } else if (PARITY == 1 && cls[j] == 1) {
             int x, y, z;
             coords(G, c[j], x, y, z);
-            pr[j] = preds_of(S, x, y, z, fl[j]);
-            sm[j] = gp(G.smask)[c[j]];
-            U[j] = flow ? inflow_speed(G, z) : 0.0f;
-        } else if (general_wave[j] && fluid[j]) {
-            sm[j] = gp(G.smask)[c[j]];
-            pr[j] = preds_xs(fl[j]);
-            if (flow) U[j] = inflow_speed(G, (int)fdiv(c[j], G.dxy));
-        } else if (near_wave[j] && fluid[j]) {
-            pr[j].xlo = fl[j] & FL_XLO;
-            pr[j].xhi = fl[j] & FL_XHI;
-            if (flow) U[j] = inflow_speed(G, (int)fdiv(c[j], G.dxy));
+            pr[j].xlo = x == 0;
+            pr[j].xhi = x == S.nx - 1;
+            const bool inl = active && pr[j].xlo && S.face[0] == FACE_INLET;
+            flow_wave[j] = __any(inl);
+            if (inl) U[j] = inflow_speed(G, z);
+            if (active) {
+                const InflowT T = flow_wave[j] ? inflow_at(G, a.step - 1) : InflowT{0.f, 0.f, 0.f, 0.f};
+                const Preds px{pr[j].xlo, pr[j].xhi, false, false, false, false, false};
+                gather_all<NT, true>(G, S, px, 0u, c[j], U[j], T, g[j], Dirs{});
+            }
+        }
+        fl[j] = active ? gp(G.flags)[c[j]] : (uint8_t)FL_SOLID;
+        fluid[j] = !(fl[j] & FL_SOLID);
+        if (PARITY == 1 && cls[j] >= 2) {
+            const bool flow = fluid[j] && inflow_lane(G, fl[j]);
+            flow_wave[j] = __any(flow);
+            if (fluid[j]) {
+                sm[j] = gp(G.smask)[c[j]];
+                if (cls[j] == 3) {
+                    int x, y, z;
+                    coords(G, c[j], x, y, z);
+                    pr[j] = preds_of(S, x, y, z, fl[j]);
+                    if (flow) U[j] = inflow_speed(G, z);
+                } else {
+                    pr[j] = preds_xs(fl[j]);
+                    if (flow) U[j] = inflow_speed(G, (int)fdiv(c[j], G.dxy));
+                }
+            }
         }
     }
+    // classes 2 and 3: gathers after the flag byte and solid-link mask
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
-        if (!fluid[j] || PARITY == 0) continue;
-        if (!near_wave[j]) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) g[j][i] = ldg<NT>(f + (size_t)opp(i) * qs - off_of(G, i), c[j]);
-            continue;
-        }
+        if (PARITY == 0 || cls[j] < 2 || !fluid[j]) continue;
         const InflowT T = flow_wave[j] ? inflow_at(G, a.step - 1) : InflowT{0.f, 0.f, 0.f, 0.f};
-        if (face_wave[j]) {
+        if (cls[j] == 3) {
             gather_all<NT>(G, S, pr[j], sm[j], c[j], U[j], T, g[j], Dirs{});
-        } else if (general_wave[j]) {
+        } else {
             const Preds ps{pr[j].xlo, pr[j].xhi, false, false, false, false, pr[j].mantle};
             gather_all<NT>(G, S, ps, sm[j], c[j], U[j], T, g[j], Dirs{});
-        } else {
-            const Preds px{pr[j].xlo, pr[j].xhi, false, false, false, false, false};
-            gather_all<NT>(G, S, px, 0u, c[j], U[j], T, g[j], Dirs{});
         }
     }
 #pragma unroll
@@ -618,15 +644,15 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
             }
             continue;
         }
-        if (!near_wave[j]) {
+        if (cls[j] == 0) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) stg<NT>(f + (size_t)i * qs + off_of(G, i), c[j], g[j][i]);
             continue;
         }
         const InflowT T = flow_wave[j] ? inflow_at(G, a.step) : InflowT{0.f, 0.f, 0.f, 0.f};
-        if (face_wave[j]) {
+        if (cls[j] == 3) {
             scatter_all<NT>(G, S, pr[j], sm[j], c[j], U[j], T, g[j], Dirs{});
-        } else if (general_wave[j]) {
+        } else if (cls[j] == 2) {
             const Preds ps{pr[j].xlo, pr[j].xhi, false, false, false, false, pr[j].mantle};
             scatter_all<NT>(G, S, ps, sm[j], c[j], U[j], T, g[j], Dirs{});
         } else {
@@ -675,7 +701,8 @@ __device__ __forceinline__ void inflow_dtheta(const Geo &G, int z, int i, const 
 
 // mu_k = sum of lam^{n+1} over the destination links of direction k, and the
 // inflow-parameter gradient of the moving-wall links among them.
-template <int... Ks>
+// CLAMP: neighbour indices clamped into the instance (speculative gathers).
+template <bool CLAMP = false, int... Ks>
 __device__ __forceinline__ void adjoint_gather(const Geo &G, const Shape &S, const Preds &p, uint32_t sm, uint32_t c,
                                                int z, const InflowT &T, const GLOBAL_AS float *__restrict__ lin,
                                                float mu[Q],
@@ -683,14 +710,19 @@ __device__ __forceinline__ void adjoint_gather(const Geo &G, const Shape &S, con
                                                double &gr1, double &gr2, std::integer_sequence<int, Ks...>)
 {
     const uint32_t qs = (uint32_t)G.qs;
+    const uint32_t last = (uint32_t)G.ncells - 1u;
+    auto cell = [&](int32_t delta) {
+        const uint32_t n = (uint32_t)((int32_t)c + delta);
+        return CLAMP ? umin_u32(n, last) : n;
+    };
     (
         [&] {
             RelLink a, e;
             scatter_rel<Ks>(S, p, sm, a, e);
             float s = 0.0f;
-            if (e.valid) s += ldg(lin, (uint32_t)e.slot * qs + (uint32_t)((int32_t)c + e.delta));
+            if (e.valid) s += ldg(lin, (uint32_t)e.slot * qs + cell(e.delta));
             if (a.valid) {
-                const float l = ldg(lin, (uint32_t)a.slot * qs + (uint32_t)((int32_t)c + a.delta));
+                const float l = ldg(lin, (uint32_t)a.slot * qs + cell(a.delta));
                 s += l;
                 if (a.inlet) {
                     float dt[3];
@@ -709,12 +741,10 @@ __device__ __forceinline__ void adjoint_gather(const Geo &G, const Shape &S, con
 
 // One adjoint step of every instance, with the tiling of the step kernels:
 // a workgroup of BS threads owns BS * CPT consecutive cells of one instance.
-// Gather: wavefronts without boundary cells read lambda^{n+1} with the plain
-// shifted pattern; wavefronts whose boundary cells only sit in the inflow /
-// outflow columns evaluate the transposed x rules for all lanes; the others
-// the full transposed rules.  Then per cell the transposed collision and the
-// probe source; solid cells write zero (their lambda is never read) so the
-// stores cover whole lines.
+// Gather: per wavefront class the plain shifted pattern, the transposed x
+// rules, the transposed x and solid-link rules or the full transposed rules.
+// Then per cell the transposed collision and the probe source; solid cells
+// write zero (their lambda is never read) so the stores cover whole lines.
 template <int BS, int CPT, int MODEL>
 __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
                                                 int32_t n_tiles, int32_t xcd_remap, AdjArgs a)
@@ -727,59 +757,81 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
     const GLOBAL_AS float *__restrict__ lin = gp(a.lam_in[ii]);
     GLOBAL_AS float *__restrict__ lout = gp(a.lam_out[ii]);
     const int32_t base = (tile - G.tile0) * (BS * CPT) + (int32_t)threadIdx.x;
+    const uint64_t wcls = a.tinfo ? a.tinfo[2 * (size_t)tile + 1] : ~0ull;
+    const uint32_t last = (uint32_t)G.ncells - 1u;
     double gr0 = 0.0, gr1 = 0.0, gr2 = 0.0;
     bool inlet_lane = false;
 
     uint32_t c[CPT];
     uint8_t fl[CPT];
-    bool act[CPT], fluid[CPT], near_wave[CPT], general_wave[CPT], face_wave[CPT];
+    int cls[CPT];
+    bool act[CPT], fluid[CPT];
     float mu[CPT][Q];
+    double sg[CPT][3];             // gradient of a speculative x-rule gather
     f32x4 st[CPT];                 // (rho, ux, uy, uz) of a kind-1 record
     float gs[CPT][Q];              // populations of a kind-2 record
     const Shape S = shape_of(G);
-    // flags and records of all of the thread's cells first: loads retire in
-    // order, so no cell's classification may wait behind another's gather
+    // mu = P^T lam^{n+1}: the sum over the destination links of each
+    // post-collision value.  Wavefronts of class 0 (plain) and 1 (x rules
+    // only, see launch_tile_info) take their addresses from the cell index
+    // alone and issue their gathers at once, with the neighbour index
+    // clamped into the instance (values and gradients of solid lanes are
+    // dropped); flags and records of all of the thread's cells follow, and
+    // classes 2 and 3 gather after them.
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         const int32_t lc = base + j * BS;
         act[j] = lc < G.ncells;
         c[j] = act[j] ? (uint32_t)lc : 0u;
+        cls[j] = (int)((wcls >> (2 * ((j * BS + (int)threadIdx.x) >> 6))) & 3ull);
+        sg[j][0] = sg[j][1] = sg[j][2] = 0.0;
+        if (cls[j] == 0) {
+            if (act[j]) {
+#pragma unroll
+                for (int k = 0; k < Q; ++k)
+                    mu[j][k] = ldg(lin + (size_t)k * qs, umin_u32((uint32_t)((int32_t)c[j] + off_of(G, k)), last));
+            }
+        } else if (cls[j] == 1) {
+            int x, y, z;
+            coords(G, c[j], x, y, z);
+            const Preds px{x == 0, x == S.nx - 1, false, false, false, false, false};
+            const bool inl = act[j] && px.xlo && S.face[0] == FACE_INLET;
+            const InflowT Tx = __any(inl) ? inflow_at(G, a.step) : InflowT{0.f, 0.f, 0.f, 0.f};
+            if (act[j]) adjoint_gather<true>(G, S, px, 0u, c[j], z, Tx, lin, mu[j], sg[j][0], sg[j][1], sg[j][2], Dirs{});
+        }
         fl[j] = act[j] ? gp(G.flags)[c[j]] : (uint8_t)FL_SOLID;
         if (a.record == 1 && act[j])
             st[j] = ((const GLOBAL_AS f32x4 *)gp(a.rec[ii]))[(size_t)a.rec_slot * (size_t)G.ncells + c[j]];
     }
+    bool flow2 = false;
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         fluid[j] = !(fl[j] & FL_SOLID);
-        if (fluid[j] && inflow_lane(G, fl[j])) inlet_lane = true;
-        near_wave[j] = __any(fluid[j] && (fl[j] & FL_NEAR));
-        general_wave[j] = __any(fluid[j] && (fl[j] & FL_GENERAL));
-        face_wave[j] = __any(fluid[j] && (fl[j] & FL_FACE));
+        const bool flow = fluid[j] && inflow_lane(G, fl[j]);
+        if (flow) inlet_lane = true;
+        if (cls[j] >= 2 && flow) flow2 = true;
+        if (cls[j] == 1 && fluid[j]) {
+            gr0 += sg[j][0];
+            gr1 += sg[j][1];
+            gr2 += sg[j][2];
+        }
     }
     // the inflow only where a lane of the wavefront has moving-wall links
-    const InflowT T = __any(inlet_lane) ? inflow_at(G, a.step) : InflowT{0.f, 0.f, 0.f, 0.f};
+    const InflowT T = __any(flow2) ? inflow_at(G, a.step) : InflowT{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         if (!fluid[j]) continue;
-        // mu = P^T lam^{n+1}: sum over the destination links of each post-collision value
-        if (!near_wave[j]) {
-#pragma unroll
-            for (int k = 0; k < Q; ++k) mu[j][k] = ldg(lin + (size_t)k * qs + off_of(G, k), c[j]);
-        } else if (face_wave[j]) {
+        if (cls[j] == 3) {
             int x, y, z;
             coords(G, c[j], x, y, z);
             const Preds pr = preds_of(S, x, y, z, fl[j]);
             const uint32_t sm = gp(G.smask)[c[j]];
             adjoint_gather(G, S, pr, sm, c[j], z, T, lin, mu[j], gr0, gr1, gr2, Dirs{});
-        } else if (general_wave[j]) {
+        } else if (cls[j] == 2) {
             const Preds ps = preds_xs(fl[j]);
             const uint32_t sm = gp(G.smask)[c[j]];
             const int z = inflow_lane(G, fl[j]) ? (int)fdiv(c[j], G.dxy) : 0;
             adjoint_gather(G, S, ps, sm, c[j], z, T, lin, mu[j], gr0, gr1, gr2, Dirs{});
-        } else {
-            const Preds px{(fl[j] & FL_XLO) != 0, (fl[j] & FL_XHI) != 0, false, false, false, false, false};
-            const int z = inflow_lane(G, fl[j]) ? (int)fdiv(c[j], G.dxy) : 0;
-            adjoint_gather(G, S, px, 0u, c[j], z, T, lin, mu[j], gr0, gr1, gr2, Dirs{});
         }
         if (a.record != 1) {
             const GLOBAL_AS float *rp = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)Q * G.qs;

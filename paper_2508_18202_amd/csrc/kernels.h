@@ -46,8 +46,7 @@ struct StepArgs {
     int32_t xcd_remap;         // tile order over the XCDs (set from the variant, see tile_of)
     float *const *rec;         // device array [n_inst] of record buffer bases
     int64_t rec_slot;          // slot index n % n_slots
-    const uint64_t *dead;      // per tile: bit l set = cells [32 l, 32 l + 32) of the tile are all
-                               // solid (one 128-byte line of every plane); null: none skipped
+    const uint64_t *tinfo;     // per tile, two words (see launch_tile_info)
 };
 
 // Launch shape of the step kernels: threads per workgroup, cells per
@@ -83,9 +82,14 @@ int launch_init_geometry(const Box &b, const uint8_t *solid, uint8_t *flags, uin
 int launch_capture(int tcells, int parity, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
                    int64_t step, int32_t *health, hipStream_t s);
 int launch_flush(int tcells, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, hipStream_t s);
-// per-tile masks of all-solid 32-cell lines (StepArgs::dead) for tiles of tcells <= 2048 cells
-int launch_dead_lines(int tcells, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, uint64_t *out,
-                      hipStream_t s);
+// Per-tile words for tiles of tcells <= 2048 cells, out[2 t] and out[2 t + 1]:
+//   dead  bit l set = cells [32 l, 32 l + 32) of the tile are all solid or past
+//         the end (one 128-byte line of every plane); the step kernels skip them;
+//   class bits 2w, 2w+1 = rule class of the wavefront of cells [64 w, 64 w + 64):
+//         0 no fluid cell with FL_NEAR, 1 some FL_NEAR but no FL_GENERAL, 2 some
+//         FL_GENERAL but no FL_FACE, 3 some FL_FACE (fluid cells only).
+int launch_tile_info(int tcells, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, uint64_t *out,
+                     hipStream_t s);
 int launch_fields(int parity, const Geo *geo, int32_t inst, const Geo &g, int64_t step,
                   float *out, int32_t mode, hipStream_t s);
 int launch_average(const Geo &g, double inv_count, float *out, float *pout, hipStream_t s);
@@ -110,6 +114,7 @@ struct AdjArgs {
     const double *const *pw;   // [n_inst] probe weights (entries may be null)
     double *grad;              // [n_inst][3]
     double *part;              // [n_tiles][3] per-tile gradient partials of this step
+    const uint64_t *tinfo;     // per tile, two words (see launch_tile_info)
 };
 
 int launch_adjoint(const Variant &v, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,

@@ -50,12 +50,12 @@ __global__ __launch_bounds__(1024) void k_flush(const Geo *__restrict__ geo, con
     *p = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-// Lines (32 consecutive cells: one 128-byte line of each population plane)
-// whose cells are all solid or past the end of the instance.  One wavefront
-// per tile, one lane per line; lines of a plane start at multiples of 32
-// cells because tiles and plane strides are multiples of 64 cells.
-__global__ __launch_bounds__(64) void k_dead_lines(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
-                                                  int32_t n_tiles, int32_t tcells, uint64_t *__restrict__ out)
+// Per-tile words (launch_tile_info): all-solid 32-cell lines and the rule
+// class of each 64-cell wavefront.  One wavefront per tile, one lane per line;
+// lines and wavefronts of a plane start at multiples of 32 / 64 cells because
+// tiles and plane strides are multiples of 64 cells.
+__global__ __launch_bounds__(64) void k_tile_info(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
+                                                 int32_t n_tiles, int32_t tcells, uint64_t *__restrict__ out)
 {
     const int tile = blockIdx.x;
     if (tile >= n_tiles) return;
@@ -64,15 +64,31 @@ __global__ __launch_bounds__(64) void k_dead_lines(const Geo *__restrict__ geo, 
     const int lines = tcells >> 5;
     const int l = threadIdx.x;
     bool dead = true;
+    int cls = 0;
     if (l < lines) {
         const int32_t c0 = (tile - G.tile0) * tcells + 32 * l;
-        for (int k = 0; k < 32 && dead; ++k) {
+        for (int k = 0; k < 32; ++k) {
             const int32_t c = c0 + k;
-            if (c < G.ncells && !(gp(G.flags)[c] & FL_SOLID)) dead = false;
+            if (c >= G.ncells) break;
+            const uint8_t fl = gp(G.flags)[c];
+            if (fl & FL_SOLID) continue;
+            dead = false;
+            const int k_cls = (fl & FL_FACE) ? 3 : ((fl & FL_GENERAL) ? 2 : ((fl & FL_NEAR) ? 1 : 0));
+            cls = k_cls > cls ? k_cls : cls;
         }
     }
-    const uint64_t m = __ballot(l < lines && dead);
-    if (l == 0) out[tile] = m;
+    const uint64_t d = __ballot(l < lines && dead);
+    const uint64_t m1 = __ballot(cls >= 1), m2 = __ballot(cls >= 2), m3 = __ballot(cls >= 3);
+    if (l == 0) {
+        uint64_t w = 0;
+        for (int v = 0; v < (lines >> 1); ++v) {
+            const uint64_t pair = 3ull << (2 * v);
+            const uint64_t code = (m3 & pair) ? 3 : ((m2 & pair) ? 2 : ((m1 & pair) ? 1 : 0));
+            w |= code << (2 * v);
+        }
+        out[2 * (size_t)tile] = d;
+        out[2 * (size_t)tile + 1] = w;
+    }
 }
 
 // mode 0: fields (ux, uy, uz, |u|) [ncells][4]; mode 1: populations [19][qs]
@@ -305,12 +321,12 @@ int launch_flush(int tcells, const Geo *geo, const int32_t *tile_inst, int32_t n
     return (int)hipGetLastError();
 }
 
-int launch_dead_lines(int tcells, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, uint64_t *out,
-                      hipStream_t s)
+int launch_tile_info(int tcells, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles, uint64_t *out,
+                     hipStream_t s)
 {
-    if (tcells < 32 || tcells > 2048 || (tcells & 31)) return (int)hipErrorInvalidValue;
+    if (tcells < 64 || tcells > 2048 || (tcells & 63)) return (int)hipErrorInvalidValue;
     if (n_tiles <= 0) return 0;
-    hipLaunchKernelGGL(k_dead_lines, dim3(n_tiles), dim3(64), 0, s, geo, tile_inst, n_tiles, tcells, out);
+    hipLaunchKernelGGL(k_tile_info, dim3(n_tiles), dim3(64), 0, s, geo, tile_inst, n_tiles, tcells, out);
     return (int)hipGetLastError();
 }
 

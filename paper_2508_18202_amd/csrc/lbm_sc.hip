@@ -134,7 +134,7 @@ struct lbm_plan {
     std::vector<Geo> geo_h;
     Geo *geo_d = nullptr;
     int32_t *tiles_d = nullptr;
-    uint64_t *dead_d = nullptr;   // per tile: all-solid 32-cell lines (StepArgs::dead)
+    uint64_t *tinfo_d = nullptr;  // per tile: all-solid lines and wavefront classes (launch_tile_info)
     int32_t n_tiles = 0;
     int32_t *health_d = nullptr;
     int64_t step = 0;
@@ -169,12 +169,12 @@ int build_tiles(lbm_plan *p)
     HIPCHK(hipMemcpy(p->tiles_d, tiles.data(), sizeof(int32_t) * tiles.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(p->geo_d, p->geo_h.data(), sizeof(Geo) * p->n_inst, hipMemcpyHostToDevice));
     // the flags may still be in flight on the caller's geometry stream
-    if (p->dead_d) HIPCHK(hipFree(p->dead_d));
-    p->dead_d = nullptr;
-    HIPCHK(hipMalloc(&p->dead_d, sizeof(uint64_t) * std::max<size_t>(1, tiles.size())));
+    if (p->tinfo_d) HIPCHK(hipFree(p->tinfo_d));
+    p->tinfo_d = nullptr;
+    HIPCHK(hipMalloc(&p->tinfo_d, 2 * sizeof(uint64_t) * std::max<size_t>(1, tiles.size())));
     HIPCHK(hipDeviceSynchronize());
-    if (launch_dead_lines(p->v.tile(), p->geo_d, p->tiles_d, p->n_tiles, p->dead_d, nullptr))
-        return fail(LBM_E_HIP, "dead-line launch failed");
+    if (launch_tile_info(p->v.tile(), p->geo_d, p->tiles_d, p->n_tiles, p->tinfo_d, nullptr))
+        return fail(LBM_E_HIP, "tile-info launch failed");
     HIPCHK(hipDeviceSynchronize());
     if (p->gexec) {
         HIPCHK(hipGraphExecDestroy(p->gexec));
@@ -258,7 +258,7 @@ int ensure_graph(lbm_plan *p)
     HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     StepArgs a{};
     a.step = (p->steady_from + 1) / 2 * 2 + 2;
-    a.dead = p->dead_d;
+    a.tinfo = p->tinfo_d;
     HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < p->graph_pairs; ++k) {
         launch_step(p->v, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, cap);
@@ -301,7 +301,7 @@ int run_steps(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_d, i
         }
         StepArgs a{};
         a.step = n;
-        a.dead = p->dead_d;
+        a.tinfo = p->tinfo_d;
         // recording runs re-play steps for the adjoint and leave the QoI sums alone
         a.accumulate = (kind == 0 && step_accumulates(p, n)) ? 1 : 0;
         a.record = kind;
@@ -682,7 +682,7 @@ void lbm_plan_destroy(lbm_plan *p)
     for (auto &kv : p->tables) (void)hipFree(kv.second);
     if (p->geo_d) (void)hipFree(p->geo_d);
     if (p->tiles_d) (void)hipFree(p->tiles_d);
-    if (p->dead_d) (void)hipFree(p->dead_d);
+    if (p->tinfo_d) (void)hipFree(p->tinfo_d);
     if (p->health_d) (void)hipFree(p->health_d);
     if (p->gpart_d) (void)hipFree(p->gpart_d);
     delete p;
@@ -860,6 +860,7 @@ int lbm_adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float
         p->gpart_tiles = p->n_tiles;
     }
     a.part = p->gpart_d;
+    a.tinfo = p->tinfo_d;
     // the adjoint keeps more live state per cell than a step: it runs one
     // cell per thread over the same tiles (whole tile per workgroup, up to
     // 512 threads), which holds more wavefronts per SIMD in flight
@@ -943,7 +944,7 @@ int lbm_plan_autotune(lbm_plan *p, hipStream_t s, int32_t variant_out[4])
             if (rc) return rc;
             StepArgs a{};
             a.step = p->steady_from + 2;
-            a.dead = p->dead_d;
+            a.tinfo = p->tinfo_d;
             for (int w = 0; w < 2 + pairs; ++w) {
                 if (w == 2) HIPCHK(hipEventRecord(e0, s));
                 launch_step(v, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
