@@ -193,3 +193,34 @@ def test_cylinder_rejections():
     bad[w.nz - 1, w.ny // 2, w.nx // 2 - 3] = 1    # a building under the free-slip sky
     with pytest.raises(L.LbmError):
         init(bad)
+
+
+def test_full_size_cylinder_first_steps():
+    """The paper's domain at its size (radius 270, height 40, 544x544x40
+    box, two central blocks, series wind on the mantle, Smagorinsky) in the
+    bench's launch shape: three of the 121 Gauss-Hermite nodes in one plan,
+    full inflow from step 0, the first 12 steps of the two extreme nodes
+    against the oracle at full size."""
+    w = inputs.cylinder_gpc()
+    solid = inputs.solid_mask(w)
+    x, a, th = sc.collocation(w)
+    sel = [0, 60, 120]
+    w0 = inputs.scaled(w, w.nx, w.ny, w.nz, ramp=0)
+    cg = sc.make_geometry(w0, solid)
+    ens = sc.Ensemble([cg], [th[sel]], use_graph=True, variant=(128, 2, 1, 0))
+    try:
+        _say("full-size cylinder: GPU 12 steps")
+        ens.advance(12)
+        fluid = cg.fluid
+        xo, ao = orc.collocation(w)
+        for k, j in ((0, 0), (2, 120)):
+            _say(f"full-size cylinder: oracle node {j}")
+            case = oracle_case(w0, solid, orc.node_params(w, xo[j]))
+            res = orc.run(case, 12)
+            u = ens.fields(k).cpu().numpy()
+            errs = per_channel_rel(u, res["final"], fluid)
+            assert max(errs[:2] + errs[3:]) < FIELD_TOL, (j, errs)
+            assert errs[2] < 10 * FIELD_TOL, (j, errs)     # u_z is small this early
+        assert ens.health() == -1
+    finally:
+        ens.close()
