@@ -228,6 +228,31 @@ static double basis_coef(int k, const double *u)
     }
 }
 
+/* g[a] = d A_k(u) / d u_a of the coefficient above. */
+static void basis_coef_grad(int k, const double *u, double g[3])
+{
+    const double x = u[0], y = u[1], z = u[2];
+    g[0] = g[1] = g[2] = 0.0;
+    switch (k) {
+    case 0: break;
+    case 1: g[0] = 1.0; break;
+    case 2: g[1] = 1.0; break;
+    case 3: g[2] = 1.0; break;
+    case 4: g[0] = 2.0 * x; break;
+    case 5: g[1] = 2.0 * y; break;
+    case 6: g[2] = 2.0 * z; break;
+    case 7: g[0] = y; g[1] = x; break;
+    case 8: g[0] = z; g[2] = x; break;
+    case 9: g[1] = z; g[2] = y; break;
+    case 10: g[0] = 2.0 * x * y; g[1] = x * x + z * z; g[2] = 2.0 * y * z; break;
+    case 11: g[0] = 2.0 * x * y; g[1] = x * x - z * z; g[2] = -2.0 * y * z; break;
+    case 12: g[0] = z * z + y * y; g[1] = 2.0 * x * y; g[2] = 2.0 * x * z; break;
+    case 13: g[0] = z * z - y * y; g[1] = -2.0 * x * y; g[2] = 2.0 * x * z; break;
+    case 14: g[0] = 2.0 * x * z; g[1] = 2.0 * y * z; g[2] = y * y + x * x; break;
+    default: g[0] = -2.0 * x * z; g[1] = 2.0 * y * z; g[2] = y * y - x * x; break;
+    }
+}
+
 /* P[k][i] = P_k(c_i) and N[k] = sum_i w_i P_k(c_i)^2. */
 void orc_rr3_basis(double *P, double *N)
 {
@@ -576,12 +601,17 @@ void orc_link_rules(const orc_case *k, int *rules)
 }
 
 /* Jacobian J[i][k] = d fstar_i / d f_k of the local collision (no body force),
- * by the chain rule through rho, u, f_eq and (Smagorinsky) tau_eff. */
+ * by the chain rule through rho, u, f_eq and (Smagorinsky) tau_eff.  For the
+ * regularised model, f* = f_eq3 + (1 - om) R (f - f_eq3) with the linear
+ * projector R_ij = w_i sum_{order 2, 3} P_b(c_i) P_b(c_j) / N_b, so
+ * J = A + (1 - om) R (I - A) - (R (f - f_eq3)) d om / d f with A = d f_eq3 / d f. */
 static void collision_jacobian(const orc_case *k, const double *f, double J[NQ][NQ])
 {
     double rho, u[3], feq[NQ], pi[3][3];
+    const int rr3 = k->model == M_RR3;
     moments(k, f, &rho, u);
-    orc_equilibrium(rho, u, feq);
+    if (rr3) orc_equilibrium3(rho, u, feq);
+    else orc_equilibrium(rho, u, feq);
     const double cs2 = 1.0 / 3.0;
     double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
 
@@ -592,12 +622,25 @@ static void collision_jacobian(const orc_case *k, const double *f, double J[NQ][
 
     /* d feq_i / d f_k */
     double dfeq[NQ][NQ];
+    double P[NB * NQ], N[NB];
+    orc_rr3_basis(P, N);
     for (int i = 0; i < NQ; ++i) {
-        double cu = C[i][0] * u[0] + C[i][1] * u[1] + C[i][2] * u[2];
-        double drho = weight(i) * (1.0 + cu / cs2 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
-        double dua[3];
-        for (int a = 0; a < 3; ++a)
-            dua[a] = weight(i) * rho * (C[i][a] / cs2 + cu * C[i][a] / (cs2 * cs2) - u[a] / cs2);
+        double drho, dua[3];
+        if (rr3) {
+            /* f_eq3_i = w_i rho sum_b P_b(c_i) A_b(u) / N_b */
+            drho = feq[i] / rho;
+            dua[0] = dua[1] = dua[2] = 0.0;
+            for (int b = 0; b < NB; ++b) {
+                double g[3];
+                basis_coef_grad(b, u, g);
+                for (int a = 0; a < 3; ++a) dua[a] += weight(i) * rho * P[b * NQ + i] * g[a] / N[b];
+            }
+        } else {
+            double cu = C[i][0] * u[0] + C[i][1] * u[1] + C[i][2] * u[2];
+            drho = weight(i) * (1.0 + cu / cs2 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+            for (int a = 0; a < 3; ++a)
+                dua[a] = weight(i) * rho * (C[i][a] / cs2 + cu * C[i][a] / (cs2 * cs2) - u[a] / cs2);
+        }
         for (int kk = 0; kk < NQ; ++kk)
             dfeq[i][kk] = drho + dua[0] * du[0][kk] + dua[1] * du[1][kk] + dua[2] * du[2][kk];
     }
@@ -605,7 +648,7 @@ static void collision_jacobian(const orc_case *k, const double *f, double J[NQ][
     double tau = k->tau0;
     double dom[NQ];
     for (int kk = 0; kk < NQ; ++kk) dom[kk] = 0.0;
-    if (k->model == M_SMAG) {
+    if (k->model == M_SMAG || rr3) {
         double q = neq_norm(f, feq, pi);
         tau = orc_tau_eff(k->tau0, k->cs, rho, q);
         double K = 18.0 * sqrt(2.0) * k->cs * k->cs;
@@ -628,9 +671,31 @@ static void collision_jacobian(const orc_case *k, const double *f, double J[NQ][
         }
     }
     double om = 1.0 / tau;
+    if (!rr3) {
+        for (int i = 0; i < NQ; ++i)
+            for (int kk = 0; kk < NQ; ++kk)
+                J[i][kk] = (i == kk ? 1.0 - om : 0.0) + om * dfeq[i][kk] - (f[i] - feq[i]) * dom[kk];
+        return;
+    }
+    double R[NQ][NQ], Rf1[NQ], IA[NQ][NQ];
     for (int i = 0; i < NQ; ++i)
-        for (int kk = 0; kk < NQ; ++kk)
-            J[i][kk] = (i == kk ? 1.0 - om : 0.0) + om * dfeq[i][kk] - (f[i] - feq[i]) * dom[kk];
+        for (int j = 0; j < NQ; ++j) {
+            double r = 0.0;
+            for (int b = 0; b < NB; ++b)
+                if (basis_order(b) >= 2) r += P[b * NQ + i] * P[b * NQ + j] / N[b];
+            R[i][j] = weight(i) * r;
+            IA[i][j] = (i == j ? 1.0 : 0.0) - dfeq[i][j];
+        }
+    for (int i = 0; i < NQ; ++i) {
+        Rf1[i] = 0.0;
+        for (int j = 0; j < NQ; ++j) Rf1[i] += R[i][j] * (f[j] - feq[j]);
+    }
+    for (int i = 0; i < NQ; ++i)
+        for (int kk = 0; kk < NQ; ++kk) {
+            double rj = 0.0;
+            for (int j = 0; j < NQ; ++j) rj += R[i][j] * IA[j][kk];
+            J[i][kk] = dfeq[i][kk] + (1.0 - om) * rj - Rf1[i] * dom[kk];
+        }
 }
 
 void orc_collision_jacobian(const orc_case *k, const double *f, double *J)

@@ -398,16 +398,12 @@ class Case:
         return out
 
     def collision_jacobian(self, f19) -> np.ndarray:
-        if self.c.model == MODEL_CODES["rr3"]:
-            raise NotImplementedError("the oracle adjoint covers the BGK and Smagorinsky collisions")
         f = np.ascontiguousarray(f19, dtype=np.float64)
         J = np.zeros(NQ * NQ)
         lib().orc_collision_jacobian(ctypes.byref(self.c), _dp(f), _dp(J))
         return J.reshape(NQ, NQ)
 
     def adjoint_step(self, n: int, f_n, lam_next):
-        if self.c.model == MODEL_CODES["rr3"]:
-            raise NotImplementedError("the oracle adjoint covers the BGK and Smagorinsky collisions")
         lam = np.empty_like(lam_next)
         g = np.zeros(3)
         lib().orc_adjoint_step(ctypes.byref(self.c), n, _dp(f_n), _dp(lam_next), _dp(lam), _dp(g))

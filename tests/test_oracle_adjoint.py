@@ -30,7 +30,7 @@ def _state(case, steps=40):
     return f
 
 
-@pytest.mark.parametrize("model,cs", [("bgk", 0.0), ("smagorinsky", 0.2)])
+@pytest.mark.parametrize("model,cs", [("bgk", 0.0), ("smagorinsky", 0.2), ("rr3", 0.15)])
 def test_adjoint_step_dot_product(model, cs):
     nx, ny, nz = 20, 10, 9
     case = orc.Case(nx, ny, nz, FACES, _small_solid(nx, ny, nz), model=model, tau0=0.56, cs=cs,
@@ -59,6 +59,8 @@ def _probe_plane(nx, ny, nz, solid):
     ("bgk", 0.0, "uniform", (0.05, 0.0, 0.0), 0),
     ("bgk", 0.0, "loglaw", (0.012, 0.05, 0.5), 0),
     ("smagorinsky", 0.1, "loglaw", (0.012, -0.07, 0.5), 30),
+    ("rr3", 0.1, "loglaw", (0.012, 0.04, 0.5), 30),
+    ("rr3", 0.0, "uniform", (0.05, -0.03, 0.0), 0),
 ])
 def test_adjoint_gradient_matches_central_differences(model, cs, inflow, theta, ramp):
     nx, ny, nz = 20, 10, 9

@@ -130,12 +130,15 @@ def test_tau_eff_positive_root():
         assert abs(t * t - 0.51 * t - 9 * 0.01 * q / np.sqrt(2.0)) < 1e-15
 
 
-@pytest.mark.parametrize("model,cs", [("bgk", 0.0), ("smagorinsky", 0.2)])
+@pytest.mark.parametrize("model,cs", [("bgk", 0.0), ("smagorinsky", 0.2), ("rr3", 0.0), ("rr3", 0.15)])
 def test_collision_jacobian_matches_finite_differences(model, cs):
     rng = np.random.default_rng(5)
     _, w, _ = orc.lattice()
     case = _one_cell(model, 0.55, cs)
     f = orc.equilibrium(1.01, [0.03, -0.02, 0.01]) + 2e-3 * w * rng.standard_normal(19)
+    if model == "rr3":
+        # ghost components too: the regularisation must remove their response
+        f = orc.equilibrium3(1.01, [0.05, -0.03, 0.02]) + 2e-3 * w * rng.standard_normal(19)
     J = case.collision_jacobian(f)
     h = 1e-6
     for k in range(19):
