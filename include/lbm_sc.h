@@ -242,8 +242,8 @@ int lbm_collide_stream(lbm_plan *plan, int32_t n_steps, hipStream_t stream);
 /* Same, and also record the state of every step n for the adjoint sweep
  * (recording runs do not add to the QoI sums):
  * record_kind 1 saves (rho, u) as [slot][ncells][4] floats (BGK adjoint),
- * record_kind 2 saves f - w as [slot][19][stride] floats (Smagorinsky
- * adjoint); slot = n % n_slots; rec_dev[i] is instance i's buffer. */
+ * record_kind 2 saves f - w as [slot][19][stride] floats (Smagorinsky and
+ * regularised adjoints); slot = n % n_slots; rec_dev[i] is instance i's buffer. */
 int lbm_collide_stream_record(lbm_plan *plan, int32_t n_steps, int32_t record_kind,
                               float *const *rec_dev_host, int32_t n_slots, hipStream_t stream);
 
@@ -299,19 +299,21 @@ int lbm_gpc_coefficients(const float *q_dev, const double *wphi_dev, int32_t n_n
  * Discrete adjoint of one step n -> n+1 for every instance of the plan
  * (not in the paper):
  *   lam^n = (dC/df |f^n)^T P^T lam^{n+1} + dj_n/df^n,
- *   dJdtheta[i][k] += sum over inlet links (x,q) of
+ *   dJdtheta[i][k] += sum over inlet and mantle links (x,q) of
  *                     lam^{n+1}_q(x) * 6 w_q c_q . d u_in / d theta_k * r(n)   (FP64),
  * with P the streaming/boundary map, C the local collision, and
  * j_n = sum_p pw[p] * u_x(f^n, p) / count for n inside the QoI window
  * (count = avg_end - avg_begin).  Buffers per instance (device pointers in
  * host arrays of length n_inst): lam_in (lam^{n+1}) and lam_out (lam^n),
  * [19][stride] floats; rec, the state recorded by
- * lbm_collide_stream_record for step n (kind 1 for BGK, 2 for Smagorinsky,
- * slot n % n_slots); pw, [n_probes] FP64 probe weights or NULL;
+ * lbm_collide_stream_record for step n (kind 1 for BGK, 2 for the
+ * Smagorinsky and regularised models, slot n % n_slots); pw, [n_probes] FP64 probe weights or NULL;
  * dJdtheta_dev, [n_inst][3] FP64 accumulated in place, in a fixed summation
  * order (per-tile partials in a plan-owned buffer, then one sum per
  * instance), so repeated sweeps give identical gradients.  lam^n of solid
- * cells is written as zero. */
+ * cells is written as zero.  The regularised model's transposed collision
+ * is the chain rule through f_eq3, the regularisation projector and the
+ * Smagorinsky tau_eff, in Hermite moments. */
 int lbm_adjoint_step(lbm_plan *plan, int64_t step, float *const *lam_in_host,
                      float *const *lam_out_host, float *const *rec_host, int32_t record_kind,
                      int32_t n_slots, const double *const *pw_host, double *dJdtheta_dev,

@@ -1,5 +1,5 @@
-// adjoint.hip -- launches of the adjoint step kernels (BGK and Smagorinsky,
-// every launch shape); the kernels themselves are in device.h.
+// adjoint.hip -- launches of the adjoint step kernels (BGK, Smagorinsky and
+// the regularised collision, every launch shape); the kernels are in device.h.
 #include "device.h"
 
 namespace lbmsc {
@@ -16,10 +16,14 @@ void adjoint_c(const Variant &v, const Geo *geo, const int32_t *ti, int32_t nt, 
         if (v.cpt == 1) LBM_ADJ(1, 0);
         else if (v.cpt == 2) LBM_ADJ(2, 0);
         else LBM_ADJ(4, 0);
-    } else {
+    } else if (a.model == 1) {
         if (v.cpt == 1) LBM_ADJ(1, 1);
         else if (v.cpt == 2) LBM_ADJ(2, 1);
         else LBM_ADJ(4, 1);
+    } else {
+        if (v.cpt == 1) LBM_ADJ(1, 2);
+        else if (v.cpt == 2) LBM_ADJ(2, 2);
+        else LBM_ADJ(4, 2);
     }
 #undef LBM_ADJ
 }

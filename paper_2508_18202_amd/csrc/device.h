@@ -699,6 +699,133 @@ __device__ __forceinline__ void inflow_dtheta(const Geo &G, int z, int i, const 
     }
 }
 
+// lambda = J^T mu of the regularised collision f* = f_eq3 + (1 - om) R f1,
+// f1 = f - f_eq3, R the regularisation (second-order stress and third-order
+// projections): with nu = R^T mu and x = mu - (1 - om) nu,
+//   lambda_k = s_rho(x) + (c_k - u).t(x) + (1 - om) nu_k + (mu.R f1 / tau^2) dtau/df_k,
+// where s_rho + (c - u).t is the transposed derivative of f_eq3 (orders 0..3)
+// and every sum is a Hermite moment.  srcw: objective weight of u_x (the
+// source srcw (c_kx - u_x) / rho is added).
+__device__ __forceinline__ void adjoint_rr3(const Geo &G, const float g[Q], const float mu[Q], float srcw,
+                                            float lam[Q])
+{
+    const PairSums ps = pair_sums(g);
+    const Macro m = macro_of(g, ps);
+    float P[6];
+    neq_stress(ps, m, P);
+    const float qn = stress_norm(P);
+    const float R = sqrtf(G.tau0 * G.tau0 + G.kcs * qn / m.rho);
+    const float tau = 0.5f * (G.tau0 + R);
+    const float keep = 1.0f - 1.0f / tau;
+    const float ux = m.ux, uy = m.uy, uz = m.uz, rho = m.rho;
+    // Maxwellian coefficients of the six third-order polynomials and their u-gradients
+    const float A3[6] = {ux * ux * uy + uy * uz * uz, ux * ux * uy - uy * uz * uz,
+                         ux * uz * uz + ux * uy * uy, ux * uz * uz - ux * uy * uy,
+                         uy * uy * uz + ux * ux * uz, uy * uy * uz - ux * ux * uz};
+    const float dA3[6][3] = {{2.f * ux * uy, ux * ux + uz * uz, 2.f * uy * uz},
+                             {2.f * ux * uy, ux * ux - uz * uz, -2.f * uy * uz},
+                             {uz * uz + uy * uy, 2.f * ux * uy, 2.f * ux * uz},
+                             {uz * uz - uy * uy, -2.f * ux * uy, 2.f * ux * uz},
+                             {2.f * ux * uz, 2.f * uy * uz, uy * uy + ux * ux},
+                             {-2.f * ux * uz, 2.f * uy * uz, uy * uy - ux * ux}};
+    // third-order projections a1 of f1 (odd: per opposite pair)
+    float a1[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int i = 2 * k + 1;
+        const float cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
+        float t = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            if (herm3(j, i) != 0.0f) t += herm3(j, i) * herm3_inv_norm(j) * A3[j];
+        const float D = ps.d[k] - 2.0f * (3.0f * wgt(i) * rho * cu + wgt(i) * rho * t);
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            if (herm3(j, i) != 0.0f) a1[j] += herm3(j, i) * D;
+    }
+    // moments of w mu: order 0, 2 (raw c_a c_b) and the third-order basis
+    float M0 = 0.f, Mxx = 0.f, Myy = 0.f, Mzz = 0.f, Mxy = 0.f, Mxz = 0.f, Myz = 0.f;
+    float b[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const float wm = wgt(i) * mu[i];
+        M0 += wm;
+        if (cx(i)) Mxx += wm;
+        if (cy(i)) Myy += wm;
+        if (cz(i)) Mzz += wm;
+        if (cx(i) && cy(i)) Mxy += cx(i) * cy(i) * wm;
+        if (cx(i) && cz(i)) Mxz += cx(i) * cz(i) * wm;
+        if (cy(i) && cz(i)) Myz += cy(i) * cz(i) * wm;
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            if (herm3(j, i) != 0.0f) b[j] += herm3(j, i) * wm;
+    }
+    const float trP = P[0] + P[1] + P[2];
+    float sR = 4.5f * (Mxx * P[0] + Myy * P[1] + Mzz * P[2] + 2.0f * (Mxy * P[3] + Mxz * P[4] + Myz * P[5])) -
+               1.5f * M0 * trP;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) sR += herm3_inv_norm(j) * a1[j] * b[j];
+    // nu = R^T mu, x = mu - keep nu, and the moments of w x
+    float nu[Q];
+    float m0 = 0.f, m1x = 0.f, m1y = 0.f, m1z = 0.f;
+    float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
+    float X[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const float X_ = (float)cx(i), Y_ = (float)cy(i), Z_ = (float)cz(i);
+        const float cMc = X_ * X_ * Mxx + Y_ * Y_ * Myy + Z_ * Z_ * Mzz +
+                          2.0f * (X_ * Y_ * Mxy + X_ * Z_ * Mxz + Y_ * Z_ * Myz);
+        float n = 4.5f * cMc - 1.5f * (X_ * X_ + Y_ * Y_ + Z_ * Z_) * M0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            if (herm3(j, i) != 0.0f) n += herm3(j, i) * herm3_inv_norm(j) * b[j];
+        nu[i] = n;
+        const float wx = wgt(i) * (mu[i] - keep * n);
+        m0 += wx;
+        if (cx(i)) { m1x += cx(i) * wx; mxx += wx; }
+        if (cy(i)) { m1y += cy(i) * wx; myy += wx; }
+        if (cz(i)) { m1z += cz(i) * wx; mzz += wx; }
+        if (cx(i) && cy(i)) mxy += cx(i) * cy(i) * wx;
+        if (cx(i) && cz(i)) mxz += cx(i) * cz(i) * wx;
+        if (cy(i) && cz(i)) myz += cy(i) * cz(i) * wx;
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            if (herm3(j, i) != 0.0f) X[j] += herm3(j, i) * wx;
+    }
+    const float usq = ux * ux + uy * uy + uz * uz;
+    const float m2ux = mxx * ux + mxy * uy + mxz * uz;
+    const float m2uy = mxy * ux + myy * uy + myz * uz;
+    const float m2uz = mxz * ux + myz * uy + mzz * uz;
+    float srho = m0 * (1.0f - 1.5f * usq) + 3.0f * (m1x * ux + m1y * uy + m1z * uz) +
+                 4.5f * (ux * m2ux + uy * m2uy + uz * m2uz);
+    float tx = 3.0f * m1x + 9.0f * m2ux - 3.0f * ux * m0;
+    float ty = 3.0f * m1y + 9.0f * m2uy - 3.0f * uy * m0;
+    float tz = 3.0f * m1z + 9.0f * m2uz - 3.0f * uz * m0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const float h = herm3_inv_norm(j) * X[j];
+        srho += h * A3[j];
+        tx += h * dA3[j][0];
+        ty += h * dA3[j][1];
+        tz += h * dA3[j][2];
+    }
+    // Smagorinsky tau_eff: + (mu.R f1 / tau^2) dtau/df_k
+    float sa = 0.0f, sb = 0.0f;
+    if (qn > 0.0f) {
+        const float pre = sR / (tau * tau) * G.kcs / (4.0f * R);
+        sa = pre / (rho * qn);
+        sb = -pre * qn / (rho * rho) - sa * trP * (1.0f / 3.0f);
+    }
+    const float src = srcw / rho;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const float ex = cx(k) - ux, ey = cy(k) - uy, ez = cz(k) - uz;
+        const float quad = ex * (P[0] * ex + P[3] * ey + P[4] * ez) + ey * (P[3] * ex + P[1] * ey + P[5] * ez) +
+                           ez * (P[4] * ex + P[5] * ey + P[2] * ez);
+        lam[k] = srho + ex * tx + ey * ty + ez * tz + keep * nu[k] + sa * quad + sb + src * ex;
+    }
+}
+
 // mu_k = sum of lam^{n+1} over the destination links of direction k, and the
 // inflow-parameter gradient of the moving-wall links among them.
 // CLAMP: neighbour indices clamped into the instance (speculative gathers).
@@ -845,6 +972,17 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
         if (!fluid[j]) {
 #pragma unroll
             for (int k = 0; k < Q; ++k) stg(lout + (size_t)k * qs, c[j], 0.0f);
+            continue;
+        }
+        if constexpr (MODEL == 2) {
+            float srcw = 0.0f, lam[Q];
+            if (a.in_window && (fl[j] & FL_PROBE) && a.pw[ii]) {
+                const int p = probe_index(G, (int32_t)c[j]);
+                if (p >= 0) srcw = (float)(a.pw[ii][p] * a.inv_count);
+            }
+            adjoint_rr3(G, gs[j], mu[j], srcw, lam);
+#pragma unroll
+            for (int k = 0; k < Q; ++k) stg(lout + (size_t)k * qs, c[j], lam[k]);
             continue;
         }
         // state of step n

@@ -833,9 +833,8 @@ int lbm_adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float
     if (!lam_in_host || !lam_out_host || !rec_host || !pw_host || !dJdtheta_dev || n_slots < 1 || step < 0)
         return fail(LBM_E_INVALID, "bad adjoint arguments");
     if (kind != 1 && kind != 2) return fail(LBM_E_INVALID, "record kind must be 1 or 2");
-    if (p->model == LBM_RR3) return fail(LBM_E_UNSUPPORTED, "the adjoint covers the BGK and Smagorinsky models");
-    if (p->model == LBM_SMAGORINSKY && kind != 2)
-        return fail(LBM_E_INVALID, "the Smagorinsky adjoint needs recorded populations (kind 2)");
+    if (p->model != LBM_BGK && kind != 2)
+        return fail(LBM_E_INVALID, "the Smagorinsky and regularised adjoints need recorded populations (kind 2)");
     for (int i = 0; i < p->n_inst; ++i)
         if (!lam_in_host[i] || !lam_out_host[i] || !rec_host[i] || lam_in_host[i] == lam_out_host[i])
             return fail(LBM_E_INVALID, "instance %d: missing or aliased adjoint buffers", i);
@@ -878,7 +877,6 @@ int lbm_adjoint_init(lbm_plan *p, float *const *lam_out_host, const double *cons
     int r = check_plan(p);
     if (r) return r;
     if (!lam_out_host || !pw_host) return fail(LBM_E_INVALID, "bad adjoint arguments");
-    if (p->model == LBM_RR3) return fail(LBM_E_UNSUPPORTED, "the adjoint covers the BGK and Smagorinsky models");
     if (p->step & 1) return fail(LBM_E_INVALID, "the adjoint starts from an even step");
     for (int i = 0; i < p->n_inst; ++i)
         if (!lam_out_host[i]) return fail(LBM_E_INVALID, "instance %d: NULL adjoint buffer", i);

@@ -126,23 +126,28 @@ def test_adjoint_series_inflow():
     _compare(w, solid, thetas, 90, 60, 30, "series adjoint")
 
 
-def test_adjoint_rejects_the_regularised_model():
-    """The adjoint kernels cover BGK and Smagorinsky; a plan of the
-    regularised model is refused with LBM_E_UNSUPPORTED before any launch."""
-    from paper_2508_18202_amd import lbmsc as L
-    w, solid = _small("rr3", "loglaw")
-    probes = _plane_probes(w, solid)
-    cg = sc.make_geometry(w, solid, probes)
-    ens = sc.Ensemble([cg], [[(0.012, 0.0, 0.5)]], avg_begin=10, avg_end=20, use_graph=False)
-    try:
-        run = CheckpointedAdjoint(ens, 20, 10)
-        run.forward()
-        pw = torch.full((len(probes),), 1.0 / len(probes), dtype=torch.float64, device="cuda")
-        with pytest.raises(L.LbmError) as e:
-            run.backward([pw])
-        assert e.value.code == L.LBM_E_UNSUPPORTED
-    finally:
-        ens.close()
+@pytest.mark.parametrize("inflow,ramp", [("loglaw", 0), ("loglaw", 30), ("uniform", 0)])
+def test_adjoint_regularised(inflow, ramp):
+    """The regularised third-order collision with the Smagorinsky tau_eff:
+    gradients through the transposed collision (Hermite moments on the GPU,
+    the explicit chain rule in the oracle) against the oracle adjoint."""
+    w, solid = _small("rr3", inflow)
+    w = inputs.scaled(w, w.nx, w.ny, w.nz, ramp=ramp)
+    if inflow == "uniform":
+        thetas = [(0.05, 0.0, 0.0), (0.045, 0.08, 0.0)]
+    else:
+        thetas = [(0.012, 0.0, 0.5), (0.010, 0.07, 0.5), (0.014, -0.06, 0.4)]
+    _compare(w, solid, thetas, steps=90, avg_start=60, ckpt=30, label=f"rr3/{inflow}/{ramp}")
+
+
+def test_adjoint_regularised_cylinder():
+    """The paper's model in the paper's domain class: the regularised
+    collision in a small cylinder driven through its mantle."""
+    w = inputs.scaled(inputs.cylinder_gpc(), 22, 22, 10, inflow="loglaw", model="rr3", cs=0.1,
+                      tau0=0.56, ramp=10, cylinder_radius=9.0, buildings=(1, 1))
+    solid = inputs.solid_mask(w)
+    thetas = [(0.012, 0.4, 0.5), (0.010, 2.2, 0.5)]
+    _compare(w, solid, thetas, 90, 60, 30, "rr3 cylinder adjoint")
 
 
 def test_adjoint_cylinder():
