@@ -277,13 +277,16 @@ def cylinder_leg(variant, steps: int = 40, warm: int = 6, max_nodes: int = 121):
         ens.close()
 
 
-def adjoint_leg(variant, steps: int = 2000, avg_len: int = 500, ckpt: int = 100):
+def adjoint_leg(variant, steps: int = 2000, avg_len: int = 500, ckpt: int = 100, model: str = "bgk"):
     """Forward sweep (with snapshots) vs checkpointed adjoint sweep of the
-    adjoint workload: 13 Smolyak nodes of 128x64x48, BGK, probe-plane QoI."""
+    adjoint workload: 13 Smolyak nodes of 128x64x48, BGK (or the regularised
+    collision with the Smagorinsky tau_eff), probe-plane QoI."""
     import torch
     from paper_2508_18202_amd import inputs, sc
     from paper_2508_18202_amd.adjoint import CheckpointedAdjoint
     w = inputs.adjoint_case(steps=steps, avg_len=avg_len)
+    if model != "bgk":
+        w = inputs.scaled(w, w.nx, w.ny, w.nz, model=model, cs=0.1)
     solid = inputs.solid_mask(w)
     probes = inputs.probe_cells(w, solid)
     x, a, th = sc.collocation(w)
@@ -304,11 +307,38 @@ def adjoint_leg(variant, steps: int = 2000, avg_len: int = 500, ckpt: int = 100)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         fluid = int((solid == 0).sum())
-        return {"workload": "13 Smolyak nodes x 128x64x48 BGK tau 0.6, log-law inflow, probe plane, "
+        # per-step kernel ratio: the adjoint steps of the first segment (its
+        # records are still in place) against plain forward steps
+        from paper_2508_18202_amd import lbmsc as L
+        s = sc.stream_handle()
+        k = len(ens)
+        lam_ptr = [[t.data_ptr() for t in run.lam[b][:k]] for b in range(2)]
+        rec_ptr = [t.data_ptr() for t in run.rec[:k]]
+        pw_ptr = [p.data_ptr() for p in pw]
+        g2 = torch.zeros(k, 3, dtype=torch.float64, device="cuda")
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for n in range(ckpt - 1, -1, -1):
+            L.lbm_adjoint_step(ens.plan, n, lam_ptr[(n + 1) % 2], lam_ptr[n % 2], rec_ptr, run.kind, ckpt,
+                               pw_ptr, g2.data_ptr(), s)
+        e1.record()
+        e1.synchronize()
+        t_adj = e0.elapsed_time(e1) / 1e3 / ckpt
+        ens.reset()
+        e0.record()
+        ens.advance(ckpt)
+        e1.record()
+        e1.synchronize()
+        t_fwd = e0.elapsed_time(e1) / 1e3 / ckpt
+        coll = "BGK tau 0.6" if model == "bgk" else "regularised third-order collision, Smagorinsky Cs=0.1, tau0 0.6"
+        return {"workload": f"13 Smolyak nodes x 128x64x48 {coll}, log-law inflow, probe plane, "
                             f"{steps} steps, objective over the last {avg_len}, snapshots every {ckpt}",
                 "forward_s": round(t1 - t0, 4), "adjoint_s": round(t2 - t1, 4),
                 "ratio": round((t2 - t1) / (t1 - t0), 3),
                 "forward_mlups": round(len(ens) * fluid * steps / (t1 - t0) / 1e6, 1),
+                "adjoint_step_us": round(t_adj * 1e6, 1), "forward_step_us": round(t_fwd * 1e6, 1),
+                "kernel_ratio": round(t_adj / t_fwd, 3),
                 "grad_finite": bool(torch.isfinite(g).all())}
     finally:
         ens.close()
@@ -496,6 +526,7 @@ def main():
         out["cylinder"] = cylinder_leg(variant)
     if not args.no_adjoint:
         out["adjoint_vs_forward"] = adjoint_leg(variant)
+        out["adjoint_vs_forward_regularised"] = adjoint_leg(variant, model="rr3")
     if not args.no_uneven:
         out["batched_vs_one_at_a_time"] = uneven_leg(variant)
     if not args.no_cpu:
