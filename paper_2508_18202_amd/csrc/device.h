@@ -765,13 +765,9 @@ __device__ __forceinline__ void adjoint_rr3(const Geo &G, const float g[Q], cons
                1.5f * M0 * trP;
 #pragma unroll
     for (int j = 0; j < 6; ++j) sR += herm3_inv_norm(j) * a1[j] * b[j];
-    // nu = R^T mu, x = mu - keep nu, and the moments of w x
-    float nu[Q];
-    float m0 = 0.f, m1x = 0.f, m1y = 0.f, m1z = 0.f;
-    float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
-    float X[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    // nu = R^T mu (recomputed where needed rather than held), x = mu - keep nu,
+    // and the moments of w x
+    auto nu_of = [&](int i) {
         const float X_ = (float)cx(i), Y_ = (float)cy(i), Z_ = (float)cz(i);
         const float cMc = X_ * X_ * Mxx + Y_ * Y_ * Myy + Z_ * Z_ * Mzz +
                           2.0f * (X_ * Y_ * Mxy + X_ * Z_ * Mxz + Y_ * Z_ * Myz);
@@ -779,8 +775,14 @@ __device__ __forceinline__ void adjoint_rr3(const Geo &G, const float g[Q], cons
 #pragma unroll
         for (int j = 0; j < 6; ++j)
             if (herm3(j, i) != 0.0f) n += herm3(j, i) * herm3_inv_norm(j) * b[j];
-        nu[i] = n;
-        const float wx = wgt(i) * (mu[i] - keep * n);
+        return n;
+    };
+    float m0 = 0.f, m1x = 0.f, m1y = 0.f, m1z = 0.f;
+    float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
+    float X[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const float wx = wgt(i) * (mu[i] - keep * nu_of(i));
         m0 += wx;
         if (cx(i)) { m1x += cx(i) * wx; mxx += wx; }
         if (cy(i)) { m1y += cy(i) * wx; myy += wx; }
@@ -822,7 +824,7 @@ __device__ __forceinline__ void adjoint_rr3(const Geo &G, const float g[Q], cons
         const float ex = cx(k) - ux, ey = cy(k) - uy, ez = cz(k) - uz;
         const float quad = ex * (P[0] * ex + P[3] * ey + P[4] * ez) + ey * (P[3] * ex + P[1] * ey + P[5] * ez) +
                            ez * (P[4] * ex + P[5] * ey + P[2] * ez);
-        lam[k] = srho + ex * tx + ey * ty + ez * tz + keep * nu[k] + sa * quad + sb + src * ex;
+        lam[k] = srho + ex * tx + ey * ty + ez * tz + keep * nu_of(k) + sa * quad + sb + src * ex;
     }
 }
 
