@@ -55,8 +55,9 @@ enum {
 };
 
 /* Boundary kind of each box face, order -x, +x, -y, +y, -z, +z (Sec. 2.2
- * boundary list, on a box instead of the paper's cylinder: inflow through
- * the -x face, outflow through +x).
+ * boundary list on a box: inflow through the -x face, outflow through +x;
+ * the paper's cylindrical domain is a box of WALL side faces whose exterior
+ * cells carry the mask code of the mantle, see lbm_init_geometry).
  *   WALL      half-way bounce-back (no-slip building walls and ground);
  *   INLET     local velocity condition as moving-wall bounce-back with
  *             rho_w = 1: f_i = f*_opp(i) + 6 w_i c_i.u_in (only on -x);
@@ -74,8 +75,8 @@ enum { LBM_WALL = 0, LBM_INLET = 1, LBM_OUTLET = 2, LBM_FREESLIP = 3, LBM_PERIOD
  * non-equilibrium part expanded to third order (coefficients of
  * Eq. hermiteCoeff) in the Hermite polynomials orthogonal on D3Q19, i.e. up
  * to second order plus H_xxy +- H_yzz, H_xzz +- H_xyy, H_yyz +- H_xxz, each
- * term divided by its norm on the velocity set.  The adjoint covers the first
- * two models. */
+ * term divided by its norm on the velocity set.  The adjoint covers all
+ * three models. */
 enum { LBM_BGK = 0, LBM_SMAGORINSKY = 1, LBM_RR3 = 2 };
 
 /* Inflow profiles (Sec. 3, log-law wind profile): theta = (speed, phi, z0).
@@ -152,7 +153,7 @@ typedef struct lbm_plan lbm_plan;
 const char *lbm_last_error(void);
 const char *lbm_version(void);
 
-/* ------------------------------------------------------- collocation (a1/a2)
+/* ------------------------------------------------------------ collocation
  * lbm_quadrature: nodes [n][dim] (row-major) and probability weights [n] of
  *   LBM_QUAD_GAUSS_LEGENDRE (level = number of points, dim must be 1; xi ~ U(-1,1)),
  *   LBM_QUAD_SMOLYAK_CC (level L >= 0, dim >= 1; nested Clenshaw-Curtis
@@ -172,7 +173,7 @@ int lbm_quadrature(int32_t kind, int32_t level, int32_t dim, double *nodes_host,
 int lbm_node_params(const double *xi_host, int32_t dim, double base, double rel,
                     double angle_deg, double z0, float theta_out[3]);
 
-/* ---------------------------------------------------------- geometry (a3)
+/* --------------------------------------------------------------- geometry
  * Sizes the caller must allocate: the geometry buffer in bytes and the
  * population plane stride in floats (f_dev holds 19 planes).
  * lbm_init_geometry validates the case, builds per-cell flags and solid-link
@@ -199,7 +200,7 @@ int lbm_init_geometry(const lbm_domain *dom, const uint8_t *solid_host,
                       const int32_t *probe_host, int32_t n_probes, void *geom_dev,
                       float *f_dev, hipStream_t stream);
 
-/* ------------------------------------------------------ batched plan (a5)
+/* ----------------------------------------------------------- batched plan
  * A plan binds a batch of instances (any sizes, one collision model) that
  * advance together, one launch per time step over a flattened tile list.
  * lbm_plan_create copies the instance table; device buffers stay owned by
@@ -224,7 +225,7 @@ int lbm_check_health(lbm_plan *plan, hipStream_t stream, int32_t *bad_inst);
 int lbm_plan_variant(const lbm_plan *plan, int32_t variant_out[4]);
 int lbm_plan_autotune(lbm_plan *plan, hipStream_t stream, int32_t variant_out[4]);
 
-/* --------------------------------------------- collide and stream (a4/a6)
+/* ----------------------------------------------------- collide and stream
  * Advance every instance of the plan by n_steps time steps of Eq.
  * (deterministicLBE): per cell read 19 populations, form rho, u
  * (+ Smagorinsky tau_eff), relax, and write the 19 populations to their
@@ -256,7 +257,7 @@ int lbm_read_populations(lbm_plan *plan, int32_t inst, float *out_dev, hipStream
 int lbm_qoi_average(lbm_plan *plan, int32_t inst, float *out_dev, float *probe_out_dev,
                     hipStream_t stream);
 
-/* ---------------------------------------------------------- moments (a7)
+/* ---------------------------------------------------------------- moments
  * Eq. (quad_moments) per element e < n_elems of the node-major input
  * q_dev[n_nodes][n_elems] (FP32):
  *   mean[e] = sum_j w_j q[j][e],  var[e] = sum_j w_j (q[j][e] - mean[e])^2,
@@ -269,7 +270,7 @@ int lbm_sc_moments(const float *q_dev, const double *w_host, int32_t n_nodes, in
                    double *mean_dev, double *var_dev, unsigned long long *n_negative_dev,
                    hipStream_t stream);
 
-/* ------------------------------------------- gPC coefficients (NEXT f2)
+/* ------------------------------------------------------- gPC coefficients
  * Sec. 2.3: the expansion of a QoI in polynomials orthonormal under the
  * input distribution, coefficients by projection with the collocation rule,
  * c_alpha = sum_j a_j Q_j Phi_alpha(Z^(j)); for Gaussian inputs the
@@ -295,7 +296,7 @@ int lbm_gpc_coefficients(const float *q_dev, const double *wphi_dev, int32_t n_n
                          int64_t n_elems, double *coef_dev, double *var_dev, double *band_dev,
                          hipStream_t stream);
 
-/* ---------------------------------------------------------- adjoint (a8)
+/* ---------------------------------------------------------------- adjoint
  * Discrete adjoint of one step n -> n+1 for every instance of the plan
  * (not in the paper):
  *   lam^n = (dC/df |f^n)^T P^T lam^{n+1} + dj_n/df^n,
