@@ -569,12 +569,15 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
             }
         }
         fl[j] = active ? gp(G.flags)[c[j]] : (uint8_t)FL_SOLID;
+        // classes 2 and 3 need the solid-link mask as well: issued with the
+        // flag byte (the mask of a solid cell is zero)
+        const uint32_t smv = (PARITY == 1 && cls[j] >= 2 && active) ? gp(G.smask)[c[j]] : 0u;
         fluid[j] = !(fl[j] & FL_SOLID);
         if (PARITY == 1 && cls[j] >= 2) {
             const bool flow = fluid[j] && inflow_lane(G, fl[j]);
             flow_wave[j] = __any(flow);
             if (fluid[j]) {
-                sm[j] = gp(G.smask)[c[j]];
+                sm[j] = smv;
                 if (cls[j] == 3) {
                     int x, y, z;
                     coords(G, c[j], x, y, z);
@@ -897,6 +900,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
     bool act[CPT], fluid[CPT];
     float mu[CPT][Q];
     double sg[CPT][3];             // gradient of a speculative x-rule gather
+    uint32_t smv[CPT];             // solid-link mask (classes 2 and 3)
     f32x4 st[CPT];                 // (rho, ux, uy, uz) of a kind-1 record
     float gs[CPT][Q];              // populations of a kind-2 record
     const Shape S = shape_of(G);
@@ -929,6 +933,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
             if (act[j]) adjoint_gather<true>(G, S, px, 0u, c[j], z, Tx, lin, mu[j], sg[j][0], sg[j][1], sg[j][2], Dirs{});
         }
         fl[j] = act[j] ? gp(G.flags)[c[j]] : (uint8_t)FL_SOLID;
+        smv[j] = (cls[j] >= 2 && act[j]) ? gp(G.smask)[c[j]] : 0u;
         if (a.record == 1 && act[j])
             st[j] = ((const GLOBAL_AS f32x4 *)gp(a.rec[ii]))[(size_t)a.rec_slot * (size_t)G.ncells + c[j]];
     }
@@ -954,13 +959,11 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
             int x, y, z;
             coords(G, c[j], x, y, z);
             const Preds pr = preds_of(S, x, y, z, fl[j]);
-            const uint32_t sm = gp(G.smask)[c[j]];
-            adjoint_gather(G, S, pr, sm, c[j], z, T, lin, mu[j], gr0, gr1, gr2, Dirs{});
+            adjoint_gather(G, S, pr, smv[j], c[j], z, T, lin, mu[j], gr0, gr1, gr2, Dirs{});
         } else if (cls[j] == 2) {
             const Preds ps = preds_xs(fl[j]);
-            const uint32_t sm = gp(G.smask)[c[j]];
             const int z = inflow_lane(G, fl[j]) ? (int)fdiv(c[j], G.dxy) : 0;
-            adjoint_gather(G, S, ps, sm, c[j], z, T, lin, mu[j], gr0, gr1, gr2, Dirs{});
+            adjoint_gather(G, S, ps, smv[j], c[j], z, T, lin, mu[j], gr0, gr1, gr2, Dirs{});
         }
         if (a.record != 1) {
             const GLOBAL_AS float *rp = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)Q * G.qs;
