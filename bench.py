@@ -237,9 +237,11 @@ def cylinder_leg(variant, steps: int = 40, warm: int = 6, max_nodes: int = 121):
     mantle carries an hourly-series wind, two central blocks, Smagorinsky LES;
     the 121 Gauss-Hermite nodes (11 x 11) in one plan when HBM holds them
     (about 0.9 GB each), else as many as fit; probe-line sums accumulated over
-    the timed steps."""
+    the timed steps.  Without a given launch shape the autotuner picks one on
+    four nodes of the same geometry."""
     import torch
     from paper_2508_18202_amd import inputs, sc
+    from paper_2508_18202_amd import lbmsc as L
     w = inputs.cylinder_gpc()
     solid = inputs.solid_mask(w)
     n_fluid = int((solid == 0).sum())
@@ -249,6 +251,11 @@ def cylinder_leg(variant, steps: int = 40, warm: int = 6, max_nodes: int = 121):
     per_inst = 19 * cg.qs * 4 + 16 * len(probes)
     free, _ = torch.cuda.mem_get_info()
     k = int(max(1, min(max_nodes, len(th), (free - (16 << 30)) // per_inst)))
+    if variant is None:
+        # launch shape tuned on four nodes of the same geometry (cached per box size)
+        small = sc.Ensemble([cg], [th[:4]], use_graph=False)
+        variant = tuple(L.lbm_plan_autotune(small.plan, sc.stream_handle()))
+        small.close()
     ens = sc.Ensemble([cg], [th[:k]], avg_begin=warm, avg_end=warm + steps, fields=False,
                       use_graph=True, variant=variant)
     try:
@@ -269,6 +276,8 @@ def cylinder_leg(variant, steps: int = 40, warm: int = 6, max_nodes: int = 121):
                             f"probe lines, {steps} timed steps",
                 "instances": k, "fluid_cells_per_instance": n_fluid,
                 "fluid_fraction_of_box": round(n_fluid / cg.ncells, 4),
+                "launch": {"block": variant[0], "cells_per_thread": variant[1], "nontemporal": variant[2],
+                           "xcd_order": variant[3]},
                 "step_ms": round(t * 1e3, 3),
                 "kernel_mlups": round(k * n_fluid / t / 1e6, 1),
                 "frac": round(launch_bytes / t / 1e9 / HBM_PEAK_GBS, 4),
@@ -523,7 +532,7 @@ def main():
         out["series_inflow"] = series_leg(variant)
         out["gauss_hermite_gpc"] = gauss_hermite_leg(variant)
     if not args.no_cylinder:
-        out["cylinder"] = cylinder_leg(variant)
+        out["cylinder"] = cylinder_leg(None if not args.block else variant)
     if not args.no_adjoint:
         out["adjoint_vs_forward"] = adjoint_leg(variant)
         out["adjoint_vs_forward_regularised"] = adjoint_leg(variant, model="rr3")
