@@ -271,9 +271,28 @@ def cylinder_leg(variant, steps: int = 40, warm: int = 6, max_nodes: int = 121):
             raise RuntimeError("cylinder leg went unstable")
         t = e0.elapsed_time(e1) / 1e3 / steps
         launch_bytes = BYTES_PER_CELL_UPDATE * k * n_fluid
+        # the paper's output: order-5 gPC of the probe-line averages over all
+        # nodes (needs the whole rule), mean and 95 % band per probe
+        gpc_ms = None
+        if k == len(th):
+            pq = torch.empty(k, len(probes), dtype=torch.float32, device="cuda")
+            for j in range(k):
+                ens.averages_into(j, None, pq[j])
+            sc.gpc(pq, x, a, 5)
+            torch.cuda.synchronize()
+            g0 = torch.cuda.Event(enable_timing=True)
+            g1 = torch.cuda.Event(enable_timing=True)
+            g0.record()
+            r = sc.gpc(pq, x, a, 5)
+            g1.record()
+            g1.synchronize()
+            gpc_ms = round(g0.elapsed_time(g1), 3)
+            if not bool(torch.isfinite(r["band"]).all()):
+                raise RuntimeError("cylinder leg: non-finite gPC band")
         return {"workload": f"{k} of the 121 Gauss-Hermite nodes x cylinder r=270 h=40 (544x544x40 box), "
                             "mantle velocity condition with an hourly-series wind, Smagorinsky Cs=0.1, "
-                            f"probe lines, {steps} timed steps",
+                            f"probe lines, {steps} timed steps; order-5 gPC of the probe-line averages",
+                "probes": int(len(probes)), "gpc_ms": gpc_ms,
                 "instances": k, "fluid_cells_per_instance": n_fluid,
                 "fluid_fraction_of_box": round(n_fluid / cg.ncells, 4),
                 "launch": {"block": variant[0], "cells_per_thread": variant[1], "nontemporal": variant[2],
