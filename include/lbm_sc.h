@@ -192,8 +192,10 @@ int lbm_node_params(const double *xi_host, int32_t dim, double base, double rel,
  * Rejected (LBM_E_INVALID): face kinds outside the list above, unpaired
  * periodic faces, mask codes above 2, building cells in the top layer under a
  * free-slip sky, solid cells in the last two x columns or an odd nx with an
- * outlet, a fluid cell bordering a building and a mantle cell at once, more
- * than 2^31 - 1 cells. */
+ * outlet, a fluid cell bordering a building and a mantle cell at once, a box
+ * whose 19 population planes exceed 4 GiB (the kernels use 32-bit byte
+ * offsets within an instance: at most about 56.5 M cells per instance; a
+ * batch holds any number of instances). */
 int64_t lbm_geometry_bytes(const lbm_domain *dom, int32_t n_probes);
 int64_t lbm_population_stride(const lbm_domain *dom);
 int lbm_init_geometry(const lbm_domain *dom, const uint8_t *solid_host,

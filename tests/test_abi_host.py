@@ -115,10 +115,18 @@ def test_sizes_and_validation():
         L.domain(32, 16, 16, ("inlet", "outlet", "periodic", "wall", "wall", "wall")),    # unpaired periodic
         L.domain(32, 16, 16, ("inlet", "outlet", "wall", "wall", "freeslip", "wall")),    # free-slip ground
         L.domain(0, 16, 16, inputs.BOX_FACES),
+        L.domain(2048, 2048, 512, inputs.URBAN_FACES),                                   # 2^31 cells
     ]
     for b in bad:
         with pytest.raises(L.LbmError):
             L.lbm_population_stride(b)
+    # the kernels address the 19 planes of an instance with 32-bit byte
+    # offsets: 19 * stride * 4 B must stay below 4 GiB (about 56.5 M cells)
+    big = L.domain(512, 512, 215, inputs.URBAN_FACES)
+    qs = L.lbm_population_stride(big)
+    assert qs >= 512 * 512 * 215 and 19 * qs * 4 < 2 ** 32
+    with pytest.raises(L.LbmError):
+        L.lbm_population_stride(L.domain(512, 512, 216, inputs.URBAN_FACES))
 
 
 # ---------------------------------------------------------------- link rules
