@@ -69,16 +69,17 @@ def kernel_sha() -> str:
 
 
 def load_traffic(launch_bytes_alg: float):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    """HBM bytes per launch from the committed rocprofv3 counter summary and
+    the launch shape the counters were taken in, if they were taken on the
+    current kernel source; else (None, None)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
-        return None
+        return None, None
     if t.get("kernel_sha") != kernel_sha():
-        return None
-    return t.get("hbm_bytes_per_launch")
+        return None, None
+    return t.get("hbm_bytes_per_launch"), t.get("launch")
 
 
 def cpu_baseline(w, solid, theta, seconds: float):
@@ -499,7 +500,7 @@ def main():
     avg_launch_s = float(np.mean(kern_ms)) / 1e3 if launches else float("nan")
     launch_bytes = BYTES_PER_CELL_UPDATE * n_inst * n_fluid
     achieved = launch_bytes / avg_launch_s / 1e9 if launches else float("nan")
-    traffic = load_traffic(launch_bytes)
+    traffic, traffic_launch = load_traffic(launch_bytes)
     copy_gbs = copy_ceiling()
     props = torch.cuda.get_device_properties(0)
 
@@ -538,6 +539,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            "traffic_launch": traffic_launch,
             "avg_launch_us": round(avg_launch_s * 1e6, 2),
             "algorithmic_bytes_per_launch": launch_bytes,
             "copy_ceiling": {"value": round(copy_gbs, 1), "unit": "GB/s",

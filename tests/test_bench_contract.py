@@ -22,9 +22,10 @@ def test_counter_profile_matches_the_kernel_sources():
     sources, so the bench line reports its traffic (it reports null after
     any change to them until the counters are taken again)."""
     alg = 152 * 13 * 1942272
-    t = bench.load_traffic(alg)
+    t, launch = bench.load_traffic(alg)
     assert t is not None
     assert 1.0 < t / alg < 1.5
+    assert set(launch) == {"block", "cells_per_thread", "nontemporal", "xcd_order"}
 
 
 def test_binding_fails_loudly_without_the_library(tmp_path):
