@@ -219,31 +219,54 @@ __global__ __launch_bounds__(256) void k_moments_arg_shift(const float *__restri
 
 
 // grad[i][k] += sum of part[tile][k] over instance i's tiles: one workgroup
-// per instance, strided partial sums then a tree in shared memory.
+// per instance; each thread sums tiles t, t + 256, ... in increasing order,
+// then a fixed butterfly per wavefront and the four wavefront sums in order
+// (deterministic).  The partials were written by every XCD, so each load
+// misses this XCD's L2: all of a thread's loads are issued together.
 __global__ __launch_bounds__(256) void k_grad_reduce(const Geo *__restrict__ geo, int32_t tile_cells,
                                                      const double *__restrict__ part, double *__restrict__ grad)
 {
     const int ii = blockIdx.x;
     const Geo &G = geo[ii];
     const int32_t nt = (G.ncells + tile_cells - 1) / tile_cells;
-    __shared__ double sh[3][256];
+    __shared__ double sh[3][4];
     double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-    for (int32_t t = threadIdx.x; t < nt; t += 256) {
-        const double *q = part + 3 * (size_t)(G.tile0 + t);
-        t0 += q[0];
-        t1 += q[1];
-        t2 += q[2];
+    constexpr int U = 16;
+    for (int32_t tb = threadIdx.x; tb < nt; tb += 256 * U) {
+        double v[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t t = tb + 256 * u;
+            if (t < nt) {
+                const double *q = part + 3 * (size_t)(G.tile0 + t);
+                v[u][0] = q[0];
+                v[u][1] = q[1];
+                v[u][2] = q[2];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (tb + 256 * u < nt) {
+                t0 += v[u][0];
+                t1 += v[u][1];
+                t2 += v[u][2];
+            }
+        }
     }
-    sh[0][threadIdx.x] = t0;
-    sh[1][threadIdx.x] = t1;
-    sh[2][threadIdx.x] = t2;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        t0 += __shfl_xor(t0, o, 64);
+        t1 += __shfl_xor(t1, o, 64);
+        t2 += __shfl_xor(t2, o, 64);
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][wv] = t0;
+        sh[1][wv] = t1;
+        sh[2][wv] = t2;
+    }
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h)
-            for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x < 3) grad[3 * ii + threadIdx.x] += sh[threadIdx.x][0];
+    if (threadIdx.x < 3) grad[3 * ii + threadIdx.x] += ((sh[threadIdx.x][0] + sh[threadIdx.x][1]) + sh[threadIdx.x][2]) + sh[threadIdx.x][3];
 }
 
 // lam^N = dj_N / df^N from the (even, naturally stored) current state.
