@@ -161,3 +161,45 @@ def test_adjoint_cylinder():
     assert (solid == 1).any() and (solid == 2).any()
     thetas = [(0.012, 0.4, 0.5), (0.010, 2.2, 0.5), (0.014, -1.3, 0.4)]
     _compare(w, solid, thetas, 90, 60, 30, "cylinder adjoint")
+
+
+def test_full_size_adjoint_first_steps():
+    """The adjoint workload at its size (13 Smolyak nodes of 128x64x48, BGK,
+    building array) in one plan, in the launch shape and graph replay the
+    bench times: 30 steps with snapshots every 10 and a weighted objective
+    over the last 10 on a probe plane the inflow reaches in that time
+    (x = 6); the gradients of the first and last node against the oracle
+    adjoint, and the probe averages of all 13 against the oracle's."""
+    w = inputs.adjoint_case()
+    solid = inputs.solid_mask(w)
+    xp = 6
+    probes = np.asarray([(z * w.ny + y) * w.nx + xp for z in range(w.nz // 3)
+                         for y in range(w.ny // 4, (3 * w.ny) // 4) if not solid[z, y, xp]], dtype=np.int64)
+    steps, avg_start, ckpt = 30, 20, 10
+    x, a, th = sc.collocation(w)
+    pw = np.linspace(0.5, 1.5, len(probes)) / len(probes)
+    cg = sc.make_geometry(w, solid, probes)
+    ens = sc.Ensemble([cg], [th], avg_begin=avg_start, avg_end=steps, fields=False, use_graph=True,
+                      variant=(128, 1, 1, 1))
+    try:
+        _say("full-size adjoint: GPU forward and adjoint sweeps")
+        run = CheckpointedAdjoint(ens, steps, ckpt)
+        q = [t.cpu().numpy() for t in run.forward()]
+        g = run.backward([torch.from_numpy(pw).cuda() for _ in range(len(ens))]).cpu().numpy()
+    finally:
+        ens.close()
+    assert g.shape == (13, 3)
+    xo, _ = orc.collocation(w)
+    go = []
+    for j in (0, 12):
+        _say(f"full-size adjoint: oracle node {j}")
+        case = oracle_case(w, solid, orc.node_params(w, xo[j]))
+        gj, _ = orc.adjoint(case, steps, avg_start, probes, pw, ckpt=ckpt)
+        go.append(gj)
+        res = orc.run(case, steps, avg_start=avg_start, probes=probes)
+        assert np.abs(q[j] - res["probe"]).max() < 1e-5 * np.abs(res["probe"]).max()
+    go = np.array(go)
+    assert np.abs(go[:, 0]).min() > 1.0            # the inflow has reached the probes
+    for k in range(3):
+        err = np.abs(g[[0, 12], k] - go[:, k]).max() / np.abs(go[:, k]).max()
+        assert err < GRAD_TOL, (k, err, g[[0, 12], k], go[:, k])
