@@ -1,0 +1,96 @@
+"""GPU parity at the full sizes of the batched-uneven and data-assimilation
+workloads, on sampled instances the FP64 oracle can step one by one.
+
+Both start from rest with the full inflow from step 0 (no ramp), so that the
+first steps already carry the boundary rules; the fields of the sampled
+instances are compared per velocity channel (relative L2 over fluid cells
+<= 1e-5; u_z, still small this early, <= 1e-4).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as orc
+from paper_2508_18202_amd import inputs, sc
+from gpu_util import oracle_case, per_channel_rel
+
+pytestmark = pytest.mark.gpu
+FIELD_TOL = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _check(ens, i, w0, solid, theta, steps, label):
+    _say(f"{label}: oracle instance {i}")
+    res = orc.run(oracle_case(w0, solid, theta), steps)
+    u = ens.fields(i).cpu().numpy()
+    errs = per_channel_rel(u, res["final"], solid.reshape(-1) == 0)
+    assert max(errs[:2] + errs[3:]) < FIELD_TOL, (label, i, errs)
+    assert errs[2] < 10 * FIELD_TOL, (label, i, errs)
+
+
+def test_full_size_uneven_batch_first_steps():
+    """All 48 uneven cases x 13 Smolyak nodes (624 instances, 0.67 G cells) in
+    one plan, in the launch shape of the batched leg of the bench: 24 steps,
+    then one sampled instance of each box size against the oracle."""
+    steps = 24
+    cases = inputs.uneven_cases()
+    cgs, ths, w0s, solids = [], [], [], []
+    for w in cases:
+        s = inputs.solid_mask(w)
+        w0 = inputs.scaled(w, w.nx, w.ny, w.nz, ramp=0)
+        cgs.append(sc.make_geometry(w0, s))
+        ths.append(sc.collocation(w0)[2])
+        w0s.append(w0)
+        solids.append(s)
+    assert sum(len(t) for t in ths) == 624
+    ens = sc.Ensemble(cgs, ths, use_graph=False, variant=(128, 1, 1, 1))
+    try:
+        _say("full-size uneven batch: GPU 24 steps")
+        ens.advance(steps)
+        assert ens.health() == -1
+        xo, _ = orc.collocation(cases[0])
+        for case, node in ((0, 0), (20, 6), (47, 12)):
+            i = ens.instances_of(case)[node]
+            assert (w0s[case].nx, w0s[case].ny, w0s[case].nz) == inputs.UNEVEN_SIZES[case // 16]
+            _check(ens, i, w0s[case], solids[case], orc.node_params(w0s[case], xo[node]), steps,
+                   f"uneven case {case} node {node}")
+    finally:
+        ens.close()
+
+
+def test_full_size_assimilation_first_steps():
+    """The data-assimilation scale (13 Smolyak nodes of 512x256x128,
+    Smagorinsky, 10x6 building array; 16.6 GB of populations) in one plan
+    with graph replay: 12 steps, then the first and last node against the
+    oracle at full size."""
+    steps = 12
+    w = inputs.assimilation_case()
+    solid = inputs.solid_mask(w)
+    w0 = inputs.scaled(w, w.nx, w.ny, w.nz, ramp=0)
+    x, a, th = sc.collocation(w0)
+    cg = sc.make_geometry(w0, solid)
+    ens = sc.Ensemble([cg], [th], use_graph=True, variant=(128, 1, 1, 1))
+    try:
+        _say("full-size assimilation: GPU 12 steps")
+        ens.advance(steps)
+        assert ens.health() == -1
+        xo, _ = orc.collocation(w0)
+        for j in (0, 12):
+            _check(ens, j, w0, solid, orc.node_params(w0, xo[j]), steps, f"assimilation node {j}")
+    finally:
+        ens.close()
