@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--xcd-order", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost leg")
+    ap.add_argument("--adjoint-steps", type=int, default=2000,
+                    help="run length of the adjoint/forward cost legs (objective over the last quarter)")
     ap.add_argument("--no-rr3", action="store_true",
                     help="skip the regularised-collision, series-inflow and Gauss-Hermite/gPC legs")
     ap.add_argument("--no-uneven", action="store_true", help="skip the batched vs one-at-a-time leg")
@@ -555,8 +557,11 @@ def main():
     if not args.no_cylinder:
         out["cylinder"] = cylinder_leg(None if not args.block else variant)
     if not args.no_adjoint:
-        out["adjoint_vs_forward"] = adjoint_leg(variant)
-        out["adjoint_vs_forward_regularised"] = adjoint_leg(variant, model="rr3")
+        n_adj = args.adjoint_steps
+        if n_adj < 200 or n_adj % 100:
+            raise SystemExit("--adjoint-steps must be a multiple of 100, at least 200")
+        out["adjoint_vs_forward"] = adjoint_leg(variant, steps=n_adj, avg_len=n_adj // 4)
+        out["adjoint_vs_forward_regularised"] = adjoint_leg(variant, steps=n_adj, avg_len=n_adj // 4, model="rr3")
     if not args.no_uneven:
         out["batched_vs_one_at_a_time"] = uneven_leg(variant)
     if not args.no_cpu:
