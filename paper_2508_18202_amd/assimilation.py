@@ -94,6 +94,11 @@ class Assimilation:
             g = g.detach()
             lval = float(L.detach())
             gn2 = float((g * g).sum())
+            if gn2 == 0.0:
+                # a stationary point (with exact observations, the truth)
+                hist.append({"iter": it, "mu": float(params[0]), "s": float(params[1]), "loss": lval,
+                             "grad": [0.0, 0.0], "step": step, "accepted": False})
+                break
             accepted = False
             for _ in range(max_backtrack):
                 trial = params - step * g

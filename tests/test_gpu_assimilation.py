@@ -3,7 +3,9 @@
 The gradient of the assimilation loss is pinned by the same loss built on
 the FP64 oracle (oracle forward for the observations and the node QoIs,
 oracle adjoint for the node gradients, chained through the quadrature
-moments by hand).  The recovered parameters themselves are not pinned.
+moments by hand).  The recovered parameters are pinned only for exact
+observations, where the hidden truth is a zero of the loss; under the 5 %
+observation noise they are not.
 """
 import numpy as np
 import pytest
@@ -75,7 +77,7 @@ def test_assimilation_gradient_matches_oracle_chain():
         (g,) = torch.autograd.grad(L, p)
         g = g.numpy()
         Lo, go = _oracle_loss_grad(w, solid, probes, truth, params, noise)
-        assert abs(float(L) - Lo) < 1e-4 * Lo
+        assert abs(float(L.detach()) - Lo) < 1e-4 * Lo
         assert np.abs(g - go).max() < 1e-4 * np.abs(go).max(), (g, go)
     finally:
         da.close()
@@ -107,5 +109,20 @@ def test_descent_reduces_loss():
         losses = [h["loss"] for h in hist]
         assert losses[-1] < losses[0]
         assert all(np.isfinite(losses))
+    finally:
+        da.close()
+
+
+def test_noise_free_descent_recovers_the_truth():
+    """With exact observations (no noise) the loss vanishes at the hidden
+    truth (1.08, 0.22): the descent from (1.0, 0.15) must end there."""
+    w, solid, probes = _case()
+    da = Assimilation(w, w.steps, w.steps - w.avg_start, ckpt=20, solid=solid, probes=probes)
+    try:
+        da.observe((1.08, 0.22), np.zeros(2 * len(probes)))
+        hist = da.run((1.0, 0.15), iters=60, step0=1e-4)
+        last = hist[-1]
+        assert abs(last["mu"] - 1.08) < 1e-6 and abs(last["s"] - 0.22) < 1e-6, last
+        assert last["loss"] < 1e-8 * hist[0]["loss"]
     finally:
         da.close()
