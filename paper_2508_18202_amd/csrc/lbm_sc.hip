@@ -16,6 +16,8 @@
 #include <string>
 #include <vector>
 
+#include <sys/stat.h>
+
 #include "lbm_sc.h"
 #include "kernels.h"
 #include "quadrature.h"
@@ -394,11 +396,15 @@ std::map<std::string, int> read_tune_cache()
 void write_tune_cache(const std::map<std::string, int> &m)
 {
     const std::string path = tune_path();
-    const size_t slash = path.rfind('/');
-    if (slash != std::string::npos) {
-        std::string dir = path.substr(0, slash);
-        std::string cmd = "mkdir -p '" + dir + "'";
-        if (std::system(cmd.c_str()) != 0) return;
+    // create the missing directories of the path one by one (no shell)
+    for (size_t slash = path.find('/', 1); slash != std::string::npos; slash = path.find('/', slash + 1)) {
+        struct stat st;
+        const std::string dir = path.substr(0, slash);
+        if (stat(dir.c_str(), &st) == 0) {
+            if (!S_ISDIR(st.st_mode)) return;
+            continue;
+        }
+        if (mkdir(dir.c_str(), 0755) != 0 && stat(dir.c_str(), &st) != 0) return;
     }
     std::ofstream out(path + ".tmp");
     out << "{\n";

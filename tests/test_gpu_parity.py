@@ -243,8 +243,10 @@ def test_autotune_restores_state(tmp_path, monkeypatch):
     """The launch-shape autotuner times every shape on the live batch and then
     restores populations and step counter: continuing afterwards gives the
     same populations bit for bit as a plan that was never tuned; the second
-    call is served from the cache file."""
-    monkeypatch.setenv("LBMSC_TUNE_CACHE", str(tmp_path / "tune.json"))
+    call is served from the cache file, written into directories the library
+    creates."""
+    cache = tmp_path / "cache" / "lbmsc" / "tune.json"
+    monkeypatch.setenv("LBMSC_TUNE_CACHE", str(cache))
     w = inputs.scaled(inputs.urban_les(), 64, 32, 24, ramp=4)
     solid = inputs.solid_mask(w)
     _, _, th = sc.collocation(w)
@@ -262,7 +264,7 @@ def test_autotune_restores_state(tmp_path, monkeypatch):
                 for a, b in zip(before, [ens.populations(i).cpu().numpy() for i in range(3)]):
                     assert np.array_equal(a, b)
                 assert L.lbm_plan_autotune(ens.plan, sc.stream_handle()) == v     # cached
-                assert (tmp_path / "tune.json").exists()
+                assert cache.exists() and '"' in cache.read_text()
             ens.advance(31)
             assert ens.health() < 0
             outs.append([ens.populations(i).cpu().numpy() for i in range(3)])
