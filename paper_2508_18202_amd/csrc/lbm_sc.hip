@@ -47,6 +47,21 @@ int fail(int code, const char *fmt, ...)
 
 int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
 
+// Clears n words with a kernel: entry points that a caller may capture into
+// a graph record no memset nodes.
+__global__ __launch_bounds__(256) void k_clear_i32(int32_t *__restrict__ p, int32_t n)
+{
+    const int32_t e = blockIdx.x * 256 + (int32_t)threadIdx.x;
+    if (e < n) p[e] = 0;
+}
+
+hipError_t clear_i32(int32_t *p, int32_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_clear_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
 int64_t ncells_of(const lbm_domain *d) { return (int64_t)d->nx * d->ny * d->nz; }
 
 int64_t stride_of(int64_t ncells)
@@ -726,7 +741,7 @@ int lbm_plan_reset_qoi(lbm_plan *p, hipStream_t s)
     if (r) return r;
     for (int i = 0; i < p->n_inst; ++i)
         if (launch_zero_qoi(p->geo_h[i], s)) return fail(LBM_E_HIP, "zero launch failed");
-    HIPCHK(hipMemsetAsync(p->health_d, 0, sizeof(int32_t) * p->n_inst, s));
+    HIPCHK(clear_i32(p->health_d, p->n_inst, s));
     p->pending = 0;
     return LBM_OK;
 }
@@ -995,7 +1010,7 @@ int lbm_plan_autotune(lbm_plan *p, hipStream_t s, int32_t variant_out[4])
             HIPCHK(hipMemcpyAsync(p->geo_h[i].f, save + off, bytes[i], hipMemcpyDeviceToDevice, s));
             off += bytes[i];
         }
-        HIPCHK(hipMemsetAsync(p->health_d, 0, sizeof(int32_t) * p->n_inst, s));
+        HIPCHK(clear_i32(p->health_d, p->n_inst, s));
         HIPCHK(hipStreamSynchronize(s));
         HIPCHK(hipFree(save));
         HIPCHK(hipEventDestroy(e0));
