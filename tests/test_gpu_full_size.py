@@ -94,3 +94,51 @@ def test_full_size_assimilation_first_steps():
             _check(ens, j, w0, solid, orc.node_params(w0, xo[j]), steps, f"assimilation node {j}")
     finally:
         ens.close()
+
+
+def _full_size_nodes(w0, solid, nodes, steps, label, variant=(128, 1, 1, 1)):
+    x, a, th = sc.collocation(w0)
+    cg = sc.make_geometry(w0, solid)
+    ens = sc.Ensemble([cg], [th], use_graph=True, variant=variant)
+    try:
+        _say(f"{label}: GPU {steps} steps of {len(th)} nodes")
+        ens.advance(steps)
+        assert ens.health() == -1
+        xo, _ = orc.collocation(w0)
+        for j in nodes:
+            _check(ens, j, w0, solid, orc.node_params(w0, xo[j]), steps, f"{label} node {j}")
+    finally:
+        ens.close()
+
+
+def test_full_size_regularised_urban_first_steps():
+    """The regularised-collision leg of the bench (13 Smolyak nodes of the
+    256x128x64 urban box, regularised third-order collision with the
+    Smagorinsky tau_eff) in its launch shape: 24 steps, first and last node
+    against the oracle."""
+    w = inputs.scaled(inputs.urban_les(), 256, 128, 64, model="rr3")
+    solid = inputs.solid_mask(w)
+    _full_size_nodes(inputs.scaled(w, w.nx, w.ny, w.nz, ramp=0), solid, (0, 12), 24, "regularised urban")
+
+
+def test_full_size_series_urban_through_an_hour_change():
+    """The series-inflow leg of the bench in its launch configuration (13
+    nodes of 256x128x64, hourly series), with hours of 100 steps and blends
+    of 40 and no ramp, so that 160 steps run through the first change of the
+    hourly wind; the first and last node against the oracle.  (After an
+    impulsive start the FP32 fields drift from the FP64 ones by about 4e-8
+    per step on u_y at this size, with or without the series, so the
+    horizon stays well under 250 steps.)"""
+    w = inputs.urban_series(hours=4, hour_steps=100, blend_steps=40)
+    solid = inputs.solid_mask(w)
+    _full_size_nodes(inputs.scaled(w, w.nx, w.ny, w.nz, ramp=0), solid, (0, 12), 160, "series urban")
+
+
+def test_full_size_gauss_hermite_first_steps():
+    """The Gauss-Hermite leg of the bench (121 nodes of the 128x64x48 urban
+    box, series inflow) in its launch shape: 24 steps, the first, middle and
+    last node against the oracle."""
+    w = inputs.scaled(inputs.urban_gpc(hours=4, hour_steps=100, blend_steps=30), 128, 64, 48, ramp=0,
+                      ref_height=48.0)
+    solid = inputs.solid_mask(w)
+    _full_size_nodes(w, solid, (0, 60, 120), 24, "Gauss-Hermite urban")
