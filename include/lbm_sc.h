@@ -316,7 +316,10 @@ int lbm_gpc_coefficients(const float *q_dev, const double *wphi_dev, int32_t n_n
  * instance), so repeated sweeps give identical gradients.  lam^n of solid
  * cells is written as zero.  The regularised model's transposed collision
  * is the chain rule through f_eq3, the regularisation projector and the
- * Smagorinsky tau_eff, in Hermite moments. */
+ * Smagorinsky tau_eff, in Hermite moments.  Rejected (LBM_E_INVALID): a
+ * missing buffer, lam_in and lam_out the same buffer (the step reads
+ * neighbours' lam^{n+1} while writing lam^n), a record kind other than 1 or
+ * 2, kind 1 for a non-BGK plan, n_slots < 1 or a negative step. */
 int lbm_adjoint_step(lbm_plan *plan, int64_t step, float *const *lam_in_host,
                      float *const *lam_out_host, float *const *rec_host, int32_t record_kind,
                      int32_t n_slots, const double *const *pw_host, double *dJdtheta_dev,
