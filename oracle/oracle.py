@@ -18,9 +18,22 @@ Contents, each following arXiv 2508.18202:
   additive perturbation; here with uniform xi on [-1, 1]).
 * ``moments``         -- Eq. (quad_moments): E = sum a_j Q_j,
   Var = sum a_j (Q_j - E)^2, two passes in float64.
+* ``gauss_hermite`` / ``tensor_gauss_hermite`` -- the probabilists' Gauss-
+  Hermite rule (numpy's hermegauss, weights normalised to probabilities) and
+  its tensor product, for the Gaussian germ of Sec. 3 (11 x 11 = 121 nodes).
+* ``gpc_multi_indices`` / ``hermite_he`` / ``gpc_basis`` / ``gpc`` -- the
+  orthonormal Hermite chaos of total degree <= order and the projection of
+  Sec. 2.3 (coefficients by quadrature, mean, variance, 95 % band).
+* ``equilibrium`` / ``equilibrium3`` / ``rr3_basis`` / ``tau_eff`` -- the
+  second- and third-order equilibria, the Hermite basis orthogonal on D3Q19
+  and the Smagorinsky relaxation time of Sec. 2.2 (from the C oracle).
 * ``Case`` / ``run`` / ``adjoint`` -- drive the C oracle: time stepping with
-  QoI capture (final fields, time averages, probe means; Sec. 2.4 step 6)
-  and the discrete adjoint with checkpointed recomputation.
+  QoI capture (final fields, time averages, probe means; Sec. 2.4 step 6),
+  the hourly-series inflow of Sec. 3, the cylindrical domain, and the
+  discrete adjoint with checkpointed recomputation.
+
+Every function is pinned by tests/test_oracle_*.py to closed forms,
+invariants or brute force; none is "parity unpinned".
 """
 from __future__ import annotations
 
