@@ -343,7 +343,7 @@ def adjoint_leg(variant, steps: int = 2000, avg_len: int = 500, ckpt: int = 100,
         from paper_2508_18202_amd import lbmsc as L
         s = sc.stream_handle()
         k = len(ens)
-        lam_ptr = [[t.data_ptr() for t in run.lam[b][:k]] for b in range(2)]
+        lam_ptr = [[t.data_ptr() for t in run.lam[b][:k]] for b in range(1 if run.inplace else 2)]
         rec_ptr = [t.data_ptr() for t in run.rec[:k]]
         pw_ptr = [p.data_ptr() for p in pw]
         g2 = torch.zeros(k, 3, dtype=torch.float64, device="cuda")
@@ -351,8 +351,12 @@ def adjoint_leg(variant, steps: int = 2000, avg_len: int = 500, ckpt: int = 100,
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         for n in range(ckpt - 1, -1, -1):
-            L.lbm_adjoint_step(ens.plan, n, lam_ptr[(n + 1) % 2], lam_ptr[n % 2], rec_ptr, run.kind, ckpt,
-                               pw_ptr, g2.data_ptr(), s)
+            if run.inplace:
+                L.lbm_adjoint_step_inplace(ens.plan, n, lam_ptr[0], rec_ptr, run.kind, ckpt, pw_ptr,
+                                           g2.data_ptr(), s)
+            else:
+                L.lbm_adjoint_step(ens.plan, n, lam_ptr[(n + 1) % 2], lam_ptr[n % 2], rec_ptr, run.kind, ckpt,
+                                   pw_ptr, g2.data_ptr(), s)
         e1.record()
         e1.synchronize()
         t_adj = e0.elapsed_time(e1) / 1e3 / ckpt
@@ -370,6 +374,7 @@ def adjoint_leg(variant, steps: int = 2000, avg_len: int = 500, ckpt: int = 100,
                 "forward_mlups": round(len(ens) * fluid * steps / (t1 - t0) / 1e6, 1),
                 "adjoint_step_us": round(t_adj * 1e6, 1), "forward_step_us": round(t_fwd * 1e6, 1),
                 "kernel_ratio": round(t_adj / t_fwd, 3),
+                "lambda_buffers": "one, in place" if run.inplace else "two",
                 "grad_finite": bool(torch.isfinite(g).all())}
     finally:
         ens.close()

@@ -324,6 +324,22 @@ int lbm_adjoint_step(lbm_plan *plan, int64_t step, float *const *lam_in_host,
                      float *const *lam_out_host, float *const *rec_host, int32_t record_kind,
                      int32_t n_slots, const double *const *pw_host, double *dJdtheta_dev,
                      hipStream_t stream);
+/* The same adjoint step on one lambda buffer per instance, updated in place
+ * ([19][stride] floats, device; lam_host a host array of n_inst pointers):
+ * the transpose of the in-place streaming of the populations.  lam^{n+1}
+ * is read in the storage layout the populations have after step n (natural
+ * for even n + 1, as written by lbm_adjoint_init), and lam^n is left in the
+ * layout they have after step n - 1: the adjoint of an odd step reads each
+ * cell's lambda at the slots that step scattered to and writes it to the
+ * slots it gathered from (the outflow column's zero-gradient links handed
+ * to the upstream neighbour within the wavefront, the column's extra
+ * destinations zeroed); the adjoint of an even step swaps each cell's own
+ * slots back.  Every slot is read and written by one thread, so no other
+ * buffer is needed.  The gradient and everything else as lbm_adjoint_step;
+ * calls must run n = N-1, N-2, ..., in order, on one buffer. */
+int lbm_adjoint_step_inplace(lbm_plan *plan, int64_t step, float *const *lam_host, float *const *rec_host,
+                             int32_t record_kind, int32_t n_slots, const double *const *pw_host,
+                             double *dJdtheta_dev, hipStream_t stream);
 /* lam^N = dj_N/df^N from the plan's current (even) state N; lam_out as above. */
 int lbm_adjoint_init(lbm_plan *plan, float *const *lam_out_host, const double *const *pw_host,
                      hipStream_t stream);

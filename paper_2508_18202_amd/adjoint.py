@@ -36,7 +36,8 @@ class CheckpointedAdjoint:
     j_n = sum_p pw[p] u_x(f^n, p) / count; avg_end must equal the run length.
     """
 
-    def __init__(self, ens: Ensemble, steps: int, ckpt: int = 100, group_size: Optional[int] = None):
+    def __init__(self, ens: Ensemble, steps: int, ckpt: int = 100, group_size: Optional[int] = None,
+                 inplace: Optional[bool] = None):
         if steps % 2 or ckpt % 2:
             raise ValueError("run length and checkpoint spacing must be even")
         if ens.avg_end != steps:
@@ -44,11 +45,16 @@ class CheckpointedAdjoint:
         self.ens = ens
         self.steps = steps
         self.ckpt = ckpt
+        self.model = ens.instances[0].model
+        # one lambda buffer per instance updated in place (lbm_adjoint_step_inplace)
+        # instead of two alternating ones: half the memory; by default for the
+        # models that record populations, where it is also faster (for BGK the
+        # two-buffer kernel is about 2 % faster)
+        self.inplace = (self.model != L.BGK) if inplace is None else bool(inplace)
         n = len(ens)
         self.groups = [list(range(n))] if not group_size else \
             [list(range(k, min(n, k + group_size))) for k in range(0, n, group_size)]
         self.grouped = bool(group_size) and group_size < n
-        self.model = ens.instances[0].model
         self.kind = L.RECORD_MACROS if self.model == L.BGK else L.RECORD_POPULATIONS
         self.marks = list(range(0, steps, ckpt))
         self.snaps: List[List[torch.Tensor]] = []
@@ -61,7 +67,7 @@ class CheckpointedAdjoint:
             per_slot = max(4 * cg.ncells if self.kind == L.RECORD_MACROS else 19 * cg.qs for cg in cgs)
             lam_len = max(19 * cg.qs for cg in cgs)
             self.rec.append(torch.empty(ckpt * per_slot, dtype=torch.float32, device="cuda"))
-            for b in range(2):
+            for b in range(1 if inplace else 2):
                 self.lam[b].append(torch.empty(lam_len, dtype=torch.float32, device="cuda"))
         self.grad = torch.zeros(n, 3, dtype=torch.float64, device="cuda")
         self._subplans = {}
@@ -106,11 +112,11 @@ class CheckpointedAdjoint:
     def _sweep(self, plan, members: Sequence[int], pw_ptr, grad: torch.Tensor):
         s = stream_handle()
         k = len(members)
-        lam_ptr = [[t.data_ptr() for t in self.lam[b][:k]] for b in range(2)]
+        lam_ptr = [[t.data_ptr() for t in self.lam[b][:k]] for b in range(1 if self.inplace else 2)]
         rec_ptr = [t.data_ptr() for t in self.rec[:k]]
         fs = [self.ens.f[i] for i in members]
         N = self.steps
-        L.lbm_adjoint_init(plan, lam_ptr[N % 2], pw_ptr, s)
+        L.lbm_adjoint_init(plan, lam_ptr[0 if self.inplace else N % 2], pw_ptr, s)
         for m in reversed(range(len(self.marks))):
             s0 = self.marks[m]
             s1 = min(s0 + self.ckpt, N)
@@ -119,8 +125,12 @@ class CheckpointedAdjoint:
             L.lbm_plan_set_step(plan, s0)
             L.lbm_collide_stream_record(plan, s1 - s0, self.kind, rec_ptr, self.ckpt, s)
             for n in range(s1 - 1, s0 - 1, -1):
-                L.lbm_adjoint_step(plan, n, lam_ptr[(n + 1) % 2], lam_ptr[n % 2], rec_ptr,
-                                   self.kind, self.ckpt, pw_ptr, grad.data_ptr(), s)
+                if self.inplace:
+                    L.lbm_adjoint_step_inplace(plan, n, lam_ptr[0], rec_ptr, self.kind, self.ckpt, pw_ptr,
+                                               grad.data_ptr(), s)
+                else:
+                    L.lbm_adjoint_step(plan, n, lam_ptr[(n + 1) % 2], lam_ptr[n % 2], rec_ptr,
+                                       self.kind, self.ckpt, pw_ptr, grad.data_ptr(), s)
 
     def backward(self, pweights: Sequence[Optional[torch.Tensor]]):
         """dJ/dtheta [n_inst, 3] (FP64) of J_i = sum_p pweights[i][p] <u_x(p)>.

@@ -871,13 +871,75 @@ __device__ __forceinline__ void adjoint_gather(const Geo &G, const Shape &S, con
         ...);
 }
 
+// In-place adjoint of the odd step, one direction at a time: the lambda
+// of the cell's gathered (pre-collision) population I goes into the slot
+// the forward step gathered it from, with the moving-wall gradient of a
+// gathered inlet link (inflow of step n-1).  On the outflow column, the
+// links with c_x = -1 that do not bounce back (the zero-gradient outlet, and
+// the free-slip sky whose source is clamped to the column) gather from a
+// slot that the upstream neighbour gathers from too: their lambda goes one
+// lane down (rows start at even cells, so the pair shares a wavefront) and
+// the neighbour adds it before it stores.  The extra destinations of the
+// outflow column, which the forward step writes and none of its gathers
+// reads, are zeroed.  Every slot is thus read (as a scatter destination) and
+// written by one lane.  plain: a wavefront without boundary rules (class 0),
+// whose gathered slots are the plain shifted ones.
+template <class F, int... Is>
+__device__ __forceinline__ void adjoint_emit(const Geo &G, const Shape &S, const Preds &p, uint32_t sm, uint32_t c,
+                                             int z, const InflowT &T, GLOBAL_AS float *lam, bool plain,
+                                             bool wave_out, bool outflow, bool owner, F lk_of, double &gr0,
+                                             double &gr1, double &gr2, std::integer_sequence<int, Is...>)
+{
+    const uint32_t qs = (uint32_t)G.qs;
+    (
+        [&] {
+            float v = lk_of(Is);
+            if (plain) {
+                stg(lam + (size_t)opp(Is) * qs, (uint32_t)((int32_t)c - off_of(G, Is)), v);
+                return;
+            }
+            const RelLink l = gather_rel<Is>(S, p, sm);
+            bool shared = false;
+            if constexpr (cx(Is) == -1) {
+                if (wave_out) {
+                    shared = outflow && l.slot != Is;
+                    const float recv = __shfl_down(shared ? v : 0.0f, 1, 64);
+                    if (owner) v += recv;
+                }
+            }
+            if (!shared) stg(lam, (uint32_t)l.slot * qs + (uint32_t)((int32_t)c + l.delta), v);
+            if (l.inlet) {
+                float dt[3];
+                inflow_dtheta(G, z, Is, T, dt);
+                const double f6 = 6.0 * (double)wgt(Is) * (double)v;
+                gr0 += f6 * dt[0];
+                gr1 += f6 * dt[1];
+                gr2 += f6 * dt[2];
+            }
+            if constexpr (cx(Is) == -1) {
+                if (wave_out && outflow) {
+                    RelLink pr, ex;
+                    scatter_rel<Is>(S, p, sm, pr, ex);
+                    if (ex.valid) stg(lam, (uint32_t)ex.slot * qs + (uint32_t)((int32_t)c + ex.delta), 0.0f);
+                }
+            }
+        }(),
+        ...);
+}
+
 // One adjoint step of every instance, with the tiling of the step kernels:
 // a workgroup of BS threads owns BS * CPT consecutive cells of one instance.
 // Gather: per wavefront class the plain shifted pattern, the transposed x
 // rules, the transposed x and solid-link rules or the full transposed rules.
 // Then per cell the transposed collision and the probe source; solid cells
 // write zero (their lambda is never read) so the stores cover whole lines.
-template <int BS, int CPT, int MODEL>
+// MODE 0: lambda^{n+1} and lambda^n in two buffers, both in the natural
+// layout.  MODE 1 and 2: one buffer updated in place, in the storage layout
+// of the populations (the transposed in-place streaming): MODE 1 is the
+// adjoint of an odd step (lambda read at the slots the step scattered to,
+// written to the slots it gathered from), MODE 2 of an even step (own
+// slots, swapped back).
+template <int BS, int CPT, int MODEL, int MODE>
 __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
                                                 int32_t n_tiles, int32_t xcd_remap, AdjArgs a)
 {
@@ -888,6 +950,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
     const uint32_t qs = (uint32_t)G.qs;
     const GLOBAL_AS float *__restrict__ lin = gp(a.lam_in[ii]);
     GLOBAL_AS float *__restrict__ lout = gp(a.lam_out[ii]);
+    GLOBAL_AS float *lbuf = gp(a.lam_out[ii]);   // MODE 1, 2: read and written in place (no restrict)
     const int32_t base = (tile - G.tile0) * (BS * CPT) + (int32_t)threadIdx.x;
     const uint64_t wcls = a.tinfo ? a.tinfo[2 * (size_t)tile + 1] : ~0ull;
     const uint32_t last = (uint32_t)G.ncells - 1u;
@@ -918,11 +981,19 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
         c[j] = act[j] ? (uint32_t)lc : 0u;
         cls[j] = (int)((wcls >> (2 * ((j * BS + (int)threadIdx.x) >> 6))) & 3ull);
         sg[j][0] = sg[j][1] = sg[j][2] = 0.0;
-        if (cls[j] == 0) {
+        if (MODE == 2) {
+            // adjoint of an even step: the cell's own slots, swapped
+            cls[j] = 0;
+            if (act[j]) {
+#pragma unroll
+                for (int k = 0; k < Q; ++k) mu[j][k] = ldg(lbuf + (size_t)opp(k) * qs, c[j]);
+            }
+        } else if (cls[j] == 0) {
             if (act[j]) {
 #pragma unroll
                 for (int k = 0; k < Q; ++k)
-                    mu[j][k] = ldg(lin + (size_t)k * qs, umin_u32((uint32_t)((int32_t)c[j] + off_of(G, k)), last));
+                    mu[j][k] = ldg((MODE == 0 ? lin : lbuf) + (size_t)k * qs,
+                                   umin_u32((uint32_t)((int32_t)c[j] + off_of(G, k)), last));
             }
         } else if (cls[j] == 1) {
             int x, y, z;
@@ -930,7 +1001,9 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
             const Preds px{x == 0, x == S.nx - 1, false, false, false, false, false};
             const bool inl = act[j] && px.xlo && S.face[0] == FACE_INLET;
             const InflowT Tx = __any(inl) ? inflow_at(G, a.step) : InflowT{0.f, 0.f, 0.f, 0.f};
-            if (act[j]) adjoint_gather<true>(G, S, px, 0u, c[j], z, Tx, lin, mu[j], sg[j][0], sg[j][1], sg[j][2], Dirs{});
+            if (act[j])
+                adjoint_gather<true>(G, S, px, 0u, c[j], z, Tx, MODE == 0 ? lin : lbuf, mu[j], sg[j][0], sg[j][1],
+                                     sg[j][2], Dirs{});
         }
         fl[j] = act[j] ? gp(G.flags)[c[j]] : (uint8_t)FL_SOLID;
         smv[j] = (cls[j] >= 2 && act[j]) ? gp(G.smask)[c[j]] : 0u;
@@ -959,11 +1032,11 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
             int x, y, z;
             coords(G, c[j], x, y, z);
             const Preds pr = preds_of(S, x, y, z, fl[j]);
-            adjoint_gather(G, S, pr, smv[j], c[j], z, T, lin, mu[j], gr0, gr1, gr2, Dirs{});
+            adjoint_gather(G, S, pr, smv[j], c[j], z, T, MODE == 0 ? lin : lbuf, mu[j], gr0, gr1, gr2, Dirs{});
         } else if (cls[j] == 2) {
             const Preds ps = preds_xs(fl[j]);
             const int z = inflow_lane(G, fl[j]) ? (int)fdiv(c[j], G.dxy) : 0;
-            adjoint_gather(G, S, ps, smv[j], c[j], z, T, lin, mu[j], gr0, gr1, gr2, Dirs{});
+            adjoint_gather(G, S, ps, smv[j], c[j], z, T, MODE == 0 ? lin : lbuf, mu[j], gr0, gr1, gr2, Dirs{});
         }
         if (a.record != 1) {
             const GLOBAL_AS float *rp = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)Q * G.qs;
@@ -971,12 +1044,40 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
             for (int i = 0; i < Q; ++i) gs[j][i] = ldg(rp + (size_t)i * qs, c[j]);
         }
     }
+    // MODE 1: the rules of each cell's stores (see adjoint_emit)
+    Preds pg[MODE == 1 ? CPT : 1];
+    int zg[MODE == 1 ? CPT : 1];
+    bool wout[MODE == 1 ? CPT : 1], outflow[MODE == 1 ? CPT : 1], owner[MODE == 1 ? CPT : 1];
+    InflowT Tg{0.f, 0.f, 0.f, 0.f};
+    if constexpr (MODE == 1) {
+        const bool out_face = S.face[1] == FACE_OUTLET;
+        bool flowg = false;
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            pg[j] = Preds{false, false, false, false, false, false, false};
+            zg[j] = 0;
+            owner[j] = false;
+            if (act[j] && fluid[j] && cls[j] >= 1) {
+                int x, y, z;
+                coords(G, c[j], x, y, z);
+                zg[j] = z;
+                pg[j] = cls[j] == 3 ? preds_of(S, x, y, z, fl[j])
+                                    : (cls[j] == 2 ? preds_xs(fl[j])
+                                                   : Preds{x == 0, x == S.nx - 1, false, false, false, false, false});
+                owner[j] = out_face && x == S.nx - 2;
+                if (inflow_lane(G, fl[j])) flowg = true;
+            }
+            outflow[j] = act[j] && fluid[j] && out_face && pg[j].xhi;
+            wout[j] = __any(outflow[j]);
+        }
+        if (__any(flowg)) Tg = inflow_at(G, a.step - 1);
+    }
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         if (!act[j]) continue;
         if (!fluid[j]) {
 #pragma unroll
-            for (int k = 0; k < Q; ++k) stg(lout + (size_t)k * qs, c[j], 0.0f);
+            for (int k = 0; k < Q; ++k) stg((MODE == 0 ? lout : lbuf) + (size_t)k * qs, c[j], 0.0f);
             continue;
         }
         if constexpr (MODEL == 2) {
@@ -986,8 +1087,13 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
                 if (p >= 0) srcw = (float)(a.pw[ii][p] * a.inv_count);
             }
             adjoint_rr3(G, gs[j], mu[j], srcw, lam);
+            if constexpr (MODE == 1) {
+                adjoint_emit(G, S, pg[j], smv[j], c[j], zg[j], Tg, lbuf, cls[j] == 0, wout[j], outflow[j], owner[j],
+                             [&](int k) { return lam[k]; }, gr0, gr1, gr2, Dirs{});
+            } else {
 #pragma unroll
-            for (int k = 0; k < Q; ++k) stg(lout + (size_t)k * qs, c[j], lam[k]);
+                for (int k = 0; k < Q; ++k) stg((MODE == 0 ? lout : lbuf) + (size_t)k * qs, c[j], lam[k]);
+            }
             continue;
         }
         // state of step n
@@ -1054,8 +1160,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
             const int p = probe_index(G, (int32_t)c[j]);
             if (p >= 0) src = (float)(a.pw[ii][p] * a.inv_count) / rho;
         }
-#pragma unroll
-        for (int k = 0; k < Q; ++k) {
+        auto lk_of = [&](int k) {
             const float ex = cx(k) - ux, ey = cy(k) - uy, ez = cz(k) - uz;
             float lk = (1.0f - om) * mu[j][k] + om * (srho + ex * tx + ey * ty + ez * tz);
             if (MODEL == 1) {
@@ -1064,8 +1169,14 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
                                    ez * (P[4] * ex + P[5] * ey + P[2] * ez);
                 lk += sa * quad + sb;
             }
-            lk += src * ex;
-            stg(lout + (size_t)k * qs, c[j], lk);
+            return lk + src * ex;
+        };
+        if constexpr (MODE == 1) {
+            adjoint_emit(G, S, pg[j], smv[j], c[j], zg[j], Tg, lbuf, cls[j] == 0, wout[j], outflow[j], owner[j],
+                         lk_of, gr0, gr1, gr2, Dirs{});
+        } else {
+#pragma unroll
+            for (int k = 0; k < Q; ++k) stg((MODE == 0 ? lout : lbuf) + (size_t)k * qs, c[j], lk_of(k));
         }
     }
     // gradient: wavefront sums, then one partial per tile (the per-instance

@@ -117,8 +117,10 @@ struct AdjArgs {
     const uint64_t *tinfo;     // per tile, two words (see launch_tile_info)
 };
 
+// mode 0: lam_in -> lam_out, both in the natural layout; mode 1 / 2: one
+// buffer (lam_in == lam_out) updated in place, adjoint of an odd / even step
 int launch_adjoint(const Variant &v, const Geo *geo, const int32_t *tile_inst, int32_t n_tiles,
-                   const AdjArgs &a, hipStream_t s);
+                   const AdjArgs &a, int mode, hipStream_t s);
 // grad[i][k] += sum over instance i's tiles of part[tile][k], in a fixed order
 int launch_grad_reduce(int tile_cells, const Geo *geo_h, int32_t n_inst, const Geo *geo, const double *part,
                        double *grad, hipStream_t s);

@@ -845,9 +845,12 @@ int lbm_sc_moments(const float *q_dev, const double *w_host, int32_t n_nodes, in
     return LBM_OK;
 }
 
-int lbm_adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float *const *lam_out_host,
-                     float *const *rec_host, int32_t kind, int32_t n_slots, const double *const *pw_host,
-                     double *dJdtheta_dev, hipStream_t s)
+namespace {
+
+// mode 0: two buffers (natural layout); mode 1 / 2: one buffer in place
+int adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float *const *lam_out_host,
+                 float *const *rec_host, int32_t kind, int32_t n_slots, const double *const *pw_host,
+                 double *dJdtheta_dev, int mode, hipStream_t s)
 {
     int r = check_plan(p);
     if (r) return r;
@@ -857,7 +860,7 @@ int lbm_adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float
     if (p->model != LBM_BGK && kind != 2)
         return fail(LBM_E_INVALID, "the Smagorinsky and regularised adjoints need recorded populations (kind 2)");
     for (int i = 0; i < p->n_inst; ++i)
-        if (!lam_in_host[i] || !lam_out_host[i] || !rec_host[i] || lam_in_host[i] == lam_out_host[i])
+        if (!lam_in_host[i] || !lam_out_host[i] || !rec_host[i] || (mode == 0 && lam_in_host[i] == lam_out_host[i]))
             return fail(LBM_E_INVALID, "instance %d: missing or aliased adjoint buffers", i);
     AdjArgs a{};
     r = table_of(p, (float *const *)lam_in_host, (float ***)&a.lam_in);
@@ -887,10 +890,27 @@ int lbm_adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float
     Variant va = p->v;
     va.bs = std::min(p->v.tile(), 512);
     va.cpt = p->v.tile() / va.bs;
-    if (launch_adjoint(va, p->geo_d, p->tiles_d, p->n_tiles, a, s) ||
+    if (launch_adjoint(va, p->geo_d, p->tiles_d, p->n_tiles, a, mode, s) ||
         launch_grad_reduce(p->v.tile(), p->geo_h.data(), p->n_inst, p->geo_d, p->gpart_d, dJdtheta_dev, s))
         return fail(LBM_E_HIP, "adjoint launch failed: %s", hipGetErrorString(hipGetLastError()));
     return LBM_OK;
+}
+
+}  // namespace
+
+int lbm_adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float *const *lam_out_host,
+                     float *const *rec_host, int32_t kind, int32_t n_slots, const double *const *pw_host,
+                     double *dJdtheta_dev, hipStream_t s)
+{
+    return adjoint_step(p, step, lam_in_host, lam_out_host, rec_host, kind, n_slots, pw_host, dJdtheta_dev, 0, s);
+}
+
+int lbm_adjoint_step_inplace(lbm_plan *p, int64_t step, float *const *lam_host, float *const *rec_host,
+                             int32_t kind, int32_t n_slots, const double *const *pw_host, double *dJdtheta_dev,
+                             hipStream_t s)
+{
+    return adjoint_step(p, step, lam_host, lam_host, rec_host, kind, n_slots, pw_host, dJdtheta_dev,
+                        (step & 1) ? 1 : 2, s);
 }
 
 int lbm_adjoint_init(lbm_plan *p, float *const *lam_out_host, const double *const *pw_host, hipStream_t s)

@@ -96,6 +96,8 @@ _SIGS = [
                                             _P]),
     ("lbm_adjoint_step", ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P, ctypes.c_int32,
                                         ctypes.c_int32, _P, _P, _P]),
+    ("lbm_adjoint_step_inplace", ctypes.c_int, [_P, ctypes.c_int64, _P, _P, ctypes.c_int32, ctypes.c_int32,
+                                                _P, _P, _P]),
     ("lbm_adjoint_init", ctypes.c_int, [_P, _P, _P, _P]),
 ]
 
@@ -296,6 +298,12 @@ def lbm_adjoint_step(plan, step: int, lam_in: Sequence[int], lam_out: Sequence[i
                      grad_dev: int, stream: int):
     _check(lib().lbm_adjoint_step(plan, step, _ptr_array(lam_in), _ptr_array(lam_out), _ptr_array(rec),
                                   kind, n_slots, _ptr_array(pw), grad_dev, stream))
+
+
+def lbm_adjoint_step_inplace(plan, step: int, lam: Sequence[int], rec: Sequence[int], kind: int, n_slots: int,
+                             pw: Sequence[Optional[int]], grad_dev: int, stream: int):
+    _check(lib().lbm_adjoint_step_inplace(plan, step, _ptr_array(lam), _ptr_array(rec), kind, n_slots,
+                                          _ptr_array(pw), grad_dev, stream))
 
 
 def lbm_adjoint_init(plan, lam_out: Sequence[int], pw: Sequence[Optional[int]], stream: int):

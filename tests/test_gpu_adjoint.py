@@ -32,12 +32,19 @@ def _plane_probes(w, solid):
     return np.asarray(cells, dtype=np.int64)
 
 
-def _compare(w, solid, thetas, steps, avg_start, ckpt, label):
+@pytest.fixture(params=[False, True], ids=["two_buffers", "in_place"])
+def inplace(request):
+    """Both adjoint paths: two alternating lambda buffers, and one buffer
+    updated in place (the transposed in-place streaming)."""
+    return request.param
+
+
+def _compare(w, solid, thetas, steps, avg_start, ckpt, label, inplace=False):
     probes = _plane_probes(w, solid)
     cg = sc.make_geometry(w, solid, probes)
     ens = sc.Ensemble([cg], [thetas], avg_begin=avg_start, avg_end=steps, use_graph=False)
     try:
-        run = CheckpointedAdjoint(ens, steps, ckpt)
+        run = CheckpointedAdjoint(ens, steps, ckpt, inplace=inplace)
         q = run.forward()
         pw = np.full(len(probes), 1.0 / len(probes))
         g = run.backward([torch.from_numpy(pw).cuda() for _ in thetas]).cpu().numpy()
@@ -71,16 +78,16 @@ def _small(model, inflow):
 
 
 @pytest.mark.parametrize("model,inflow", [("bgk", "loglaw"), ("bgk", "uniform"), ("smagorinsky", "loglaw")])
-def test_adjoint_small(model, inflow):
+def test_adjoint_small(model, inflow, inplace):
     w, solid = _small(model, inflow)
     if inflow == "uniform":
         thetas = [(0.05, 0.0, 0.0), (0.045, 0.08, 0.0), (0.055, -0.05, 0.0)]
     else:
         thetas = [(0.012, 0.0, 0.5), (0.010, 0.07, 0.5), (0.014, -0.06, 0.4)]
-    _compare(w, solid, thetas, steps=90, avg_start=60, ckpt=20, label=f"{model}/{inflow}")
+    _compare(w, solid, thetas, steps=90, avg_start=60, ckpt=20, label=f"{model}/{inflow}", inplace=inplace)
 
 
-def test_adjoint_urban_recipe_reduced():
+def test_adjoint_urban_recipe_reduced(inplace):
     """The adjoint workload recipe (BGK tau 0.6, log-law inflow, building
     array, probe plane) on a 48x24x20 box: three of the 13 Smolyak nodes,
     300 steps, objective over the last 100, snapshots every 100."""
@@ -88,7 +95,8 @@ def test_adjoint_urban_recipe_reduced():
     solid = inputs.solid_mask(w)
     x, a, th = sc.collocation(w)
     sel = [0, 6, 12]
-    _compare(w, solid, [th[j] for j in sel], steps=300, avg_start=200, ckpt=100, label="adjoint-recipe-reduced")
+    _compare(w, solid, [th[j] for j in sel], steps=300, avg_start=200, ckpt=100, label="adjoint-recipe-reduced",
+             inplace=inplace)
 
 
 def test_autograd_wrapper_matches_direct_adjoint():
@@ -114,7 +122,7 @@ def test_autograd_wrapper_matches_direct_adjoint():
         ens.close()
 
 
-def test_adjoint_series_inflow():
+def test_adjoint_series_inflow(inplace):
     """Gradient w.r.t. (speed multiplier, direction offset, z0) of the
     hourly-series inflow (hours of 20 steps, blends of 8, ramp 10) against the
     oracle adjoint."""
@@ -123,11 +131,11 @@ def test_adjoint_series_inflow():
     solid = np.zeros((w.nz, w.ny, w.nx), np.uint8)
     solid[0:5, 3:7, 6:10] = 1
     thetas = [(1.05, 0.03, 0.1), (0.93, -0.06, 0.12), (1.0, 0.0, 0.1)]
-    _compare(w, solid, thetas, 90, 60, 30, "series adjoint")
+    _compare(w, solid, thetas, 90, 60, 30, "series adjoint", inplace=inplace)
 
 
 @pytest.mark.parametrize("inflow,ramp", [("loglaw", 0), ("loglaw", 30), ("uniform", 0)])
-def test_adjoint_regularised(inflow, ramp):
+def test_adjoint_regularised(inflow, ramp, inplace):
     """The regularised third-order collision with the Smagorinsky tau_eff:
     gradients through the transposed collision (Hermite moments on the GPU,
     the explicit chain rule in the oracle) against the oracle adjoint."""
@@ -137,20 +145,20 @@ def test_adjoint_regularised(inflow, ramp):
         thetas = [(0.05, 0.0, 0.0), (0.045, 0.08, 0.0)]
     else:
         thetas = [(0.012, 0.0, 0.5), (0.010, 0.07, 0.5), (0.014, -0.06, 0.4)]
-    _compare(w, solid, thetas, steps=90, avg_start=60, ckpt=30, label=f"rr3/{inflow}/{ramp}")
+    _compare(w, solid, thetas, steps=90, avg_start=60, ckpt=30, label=f"rr3/{inflow}/{ramp}", inplace=inplace)
 
 
-def test_adjoint_regularised_cylinder():
+def test_adjoint_regularised_cylinder(inplace):
     """The paper's model in the paper's domain class: the regularised
     collision in a small cylinder driven through its mantle."""
     w = inputs.scaled(inputs.cylinder_gpc(), 22, 22, 10, inflow="loglaw", model="rr3", cs=0.1,
                       tau0=0.56, ramp=10, cylinder_radius=9.0, buildings=(1, 1))
     solid = inputs.solid_mask(w)
     thetas = [(0.012, 0.4, 0.5), (0.010, 2.2, 0.5)]
-    _compare(w, solid, thetas, 90, 60, 30, "rr3 cylinder adjoint")
+    _compare(w, solid, thetas, 90, 60, 30, "rr3 cylinder adjoint", inplace=inplace)
 
 
-def test_adjoint_cylinder():
+def test_adjoint_cylinder(inplace):
     """Gradient w.r.t. (speed, direction, z0) of a log-law wind entering a
     cylinder through its mantle (radius 9, one central block, Smagorinsky)
     against the oracle adjoint: every mantle link carries the inflow
@@ -160,11 +168,11 @@ def test_adjoint_cylinder():
     solid = inputs.solid_mask(w)
     assert (solid == 1).any() and (solid == 2).any()
     thetas = [(0.012, 0.4, 0.5), (0.010, 2.2, 0.5), (0.014, -1.3, 0.4)]
-    _compare(w, solid, thetas, 90, 60, 30, "cylinder adjoint")
+    _compare(w, solid, thetas, 90, 60, 30, "cylinder adjoint", inplace=inplace)
 
 
 @pytest.mark.parametrize("model,nodes", [("bgk", (0, 12)), ("rr3", (12,))])
-def test_full_size_adjoint_first_steps(model, nodes):
+def test_full_size_adjoint_first_steps(model, nodes, inplace):
     """The adjoint workload at its size (13 Smolyak nodes of 128x64x48,
     building array; BGK, and the regularised collision with the Smagorinsky
     tau_eff of the bench's second adjoint leg) in one plan, in the launch
@@ -187,7 +195,7 @@ def test_full_size_adjoint_first_steps(model, nodes):
                       variant=(128, 1, 1, 1))
     try:
         _say(f"full-size adjoint ({model}): GPU forward and adjoint sweeps")
-        run = CheckpointedAdjoint(ens, steps, ckpt)
+        run = CheckpointedAdjoint(ens, steps, ckpt, inplace=inplace)
         q = [t.cpu().numpy() for t in run.forward()]
         g = run.backward([torch.from_numpy(pw).cuda() for _ in range(len(ens))]).cpu().numpy()
     finally:
