@@ -11,6 +11,7 @@
 //     writes.
 // It also exposes the per-link rule kinds so they can be compared with an
 // independent implementation.
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <unordered_map>
@@ -208,6 +209,113 @@ void lbmhc_lattice(int *c, float *w, int *o, int *zf)
         o[i] = opp(i);
         zf[i] = zflip(i);
     }
+}
+
+}  // extern "C"
+
+namespace {
+
+// One direction K of the in-place adjoint of the odd step, as the kernel
+// evaluates it (relative rules): phase 0 the reads at the scatter
+// destinations, 1 the hand-over of the outflow column's shared links to the
+// upstream cell, 2 the stores at the gathered slots and the zeroed extras.
+template <int K>
+void adj_dir(int phase, const Geo3 &g, const Shape &S, int64_t c, int x, int y, int z, const std::vector<double> &in,
+             std::vector<double> &out, std::vector<std::vector<double>> &nu)
+{
+    const int64_t n = g.n;
+    const Preds p = preds_of(S, x, y, z, g.fl[c]);
+    const uint32_t sm = g.m[c];
+    if (phase == 0) {
+        RelLink a, e;
+        scatter_rel<K>(S, p, sm, a, e);
+        double v = 0.0;
+        if (a.valid) v += in[(int64_t)a.slot * n + c + a.delta];
+        if (e.valid) v += in[(int64_t)e.slot * n + c + e.delta];
+        nu[c][K] = v;
+        return;
+    }
+    const RelLink l = gather_rel<K>(S, p, sm);
+    const bool shared = cx(K) == -1 && p.xhi && S.face[1] == FACE_OUTLET && l.slot != K;
+    if (phase == 1) {
+        if (shared) nu[c - 1][K] += nu[c][K];
+        return;
+    }
+    if (!shared) out[(int64_t)l.slot * n + c + l.delta] = nu[c][K];
+    RelLink a, e;
+    scatter_rel<K>(S, p, sm, a, e);
+    if (e.valid) out[(int64_t)e.slot * n + c + e.delta] = 0.0;
+}
+
+template <int... Ks>
+void adj_all(int phase, const Geo3 &g, const Shape &S, int64_t c, int x, int y, int z, const std::vector<double> &in,
+             std::vector<double> &out, std::vector<std::vector<double>> &nu, std::integer_sequence<int, Ks...>)
+{
+    (adj_dir<Ks>(phase, g, S, c, x, y, z, in, out, nu), ...);
+}
+
+}  // namespace
+
+extern "C" {
+
+// The in-place adjoint of the odd step (identity collision, so that only the
+// storage map is tested) against the exact transpose of that step's slot map
+// built from pull_src / push_dsts: lam_in [19][n] is the adjoint after the
+// step, both results are the adjoint before it.  Returns the number of slots
+// where the kernel's rules (read at the scatter destinations, hand the
+// outflow column's shared links to the upstream cell, store at the gathered
+// slots, zero the extra destinations, solid cells zero) differ from the
+// transpose by more than 1e-12.
+int64_t lbmhc_check_adjoint_inplace(int nx, int ny, int nz, const int *face, const uint8_t *solid,
+                                    const double *lam_in)
+{
+    Geo3 g;
+    build(g, nx, ny, nz, face, solid);
+    const int64_t n = g.n;
+    Shape S;
+    S.nx = nx;
+    S.ny = ny;
+    S.nz = nz;
+    S.offy = nx;
+    S.offz = nx * ny;
+    for (int k = 0; k < 6; ++k) S.face[k] = face[k];
+    std::vector<double> in(lam_in, lam_in + (size_t)Q * n), ref((size_t)Q * n, 0.0), out(in);
+    // exact transpose: the forward step sets next[W(x,k)] = cur[R(x,k)]
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int64_t c = g.cell(x, y, z);
+                if (g.fl[c] & FL_SOLID) continue;
+                for (int k = 0; k < Q; ++k) {
+                    const Link s = pull_src(g.b, x, y, z, k, g.m[c], mantle_of(g, c));
+                    double mu = 0.0;
+                    if (k == 0) {
+                        mu = in[c];
+                    } else {
+                        Link d[2];
+                        const int nd = push_dsts(g.b, x, y, z, k, g.m[c], mantle_of(g, c), d[0], d[1]);
+                        for (int j = 0; j < nd; ++j) mu += in[(int64_t)d[j].pop * n + g.cell(d[j].x, d[j].y, d[j].z)];
+                    }
+                    ref[(int64_t)opp(s.pop) * n + g.cell(s.x, s.y, s.z)] += mu;
+                }
+            }
+    std::vector<std::vector<double>> nu((size_t)n, std::vector<double>(Q, 0.0));
+    for (int phase = 0; phase < 3; ++phase)
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    const int64_t c = g.cell(x, y, z);
+                    if (g.fl[c] & FL_SOLID) {
+                        if (phase == 2)
+                            for (int k = 0; k < Q; ++k) out[(int64_t)k * n + c] = 0.0;
+                        continue;
+                    }
+                    adj_all(phase, g, S, c, x, y, z, in, out, nu, std::make_integer_sequence<int, Q>{});
+                }
+    int64_t bad = 0;
+    for (int64_t sl = 0; sl < (int64_t)Q * n; ++sl)
+        if (std::fabs(out[sl] - ref[sl]) > 1e-12) ++bad;
+    return bad;
 }
 
 }  // extern "C"
