@@ -674,32 +674,39 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// c_i . d u_in / d theta_t for link i at height z and step n (T = inflow_at(n),
-// ramp included): (c . dir) dU/dtheta_t for the speed parameter and z0,
-// U (c . d dir / d phi) for the direction.
-__device__ __forceinline__ void inflow_dtheta(const Geo &G, int z, int i, const InflowT &T, float out[3])
+// Gradient of the moving-wall momentum of a cell's inlet links: with link
+// weights s_q (the adjoint value of each link times 6 w_q), the sum over the
+// links of s_q c_q . d u_in / d theta_t at height z and step n (T =
+// inflow_at(n), ramp included).  The derivative is linear in (c_qx, c_qy),
+// so only Sx = sum s_q c_qx and Sy = sum s_q c_qy enter: the speed parameter
+// and z0 through c . dir, the direction through U c . d dir / d phi.
+__device__ __forceinline__ void inflow_grad(const Geo &G, int z, const InflowT &T, double sx, double sy, double &g0,
+                                            double &g1, double &g2)
 {
-    const float cd = (float)cx(i) * T.cphi + (float)cy(i) * T.sphi;
-    const float cdd = -(float)cx(i) * T.sphi + (float)cy(i) * T.cphi;
+    const double cd = sx * (double)T.cphi + sy * (double)T.sphi;
+    const double cdd = -sx * (double)T.sphi + sy * (double)T.cphi;
+    float a0, b1, a2;
     if (G.inflow == 0) {
-        out[0] = T.base * cd;
-        out[1] = T.base * G.speed * cdd;
-        out[2] = 0.0f;
+        a0 = T.base;
+        b1 = T.base * G.speed;
+        a2 = 0.0f;
     } else if (G.inflow == 1) {
         const float L = logf(((float)z + 0.5f) / G.z0);
-        const float U = G.speed * KAPPA_INV * L;
-        out[0] = T.base * KAPPA_INV * L * cd;
-        out[1] = T.base * U * cdd;
-        out[2] = -T.base * G.speed * KAPPA_INV / G.z0 * cd;
+        a0 = T.base * KAPPA_INV * L;
+        b1 = T.base * G.speed * KAPPA_INV * L;
+        a2 = -T.base * G.speed * KAPPA_INV / G.z0;
     } else {
         // u = base zeta1 A / B-normalised: A = ln((h + z0)/z0), 1/B in base
         const float h = (float)z + 0.5f;
         const float A = logf((h + G.z0) / G.z0);
         const float dA = 1.0f / (h + G.z0) - 1.0f / G.z0;
-        out[0] = T.base * A * cd;
-        out[1] = T.scale * A * cdd;
-        out[2] = T.scale * (dA - A * G.dlog_h * G.inv_log_h) * cd;
+        a0 = T.base * A;
+        b1 = T.scale * A;
+        a2 = T.scale * (dA - A * G.dlog_h * G.inv_log_h);
     }
+    g0 += (double)a0 * cd;
+    g1 += (double)b1 * cdd;
+    g2 += (double)a2 * cd;
 }
 
 // lambda = J^T mu of the regularised collision f* = f_eq3 + (1 - om) R f1,
@@ -847,6 +854,8 @@ __device__ __forceinline__ void adjoint_gather(const Geo &G, const Shape &S, con
         const uint32_t n = (uint32_t)((int32_t)c + delta);
         return CLAMP ? umin_u32(n, last) : n;
     };
+    double sx = 0.0, sy = 0.0;
+    bool inl = false;
     (
         [&] {
             RelLink a, e;
@@ -857,18 +866,17 @@ __device__ __forceinline__ void adjoint_gather(const Geo &G, const Shape &S, con
                 const float l = ldg(lin, (uint32_t)a.slot * qs + cell(a.delta));
                 s += l;
                 if (a.inlet) {
-                    float dt[3];
                     constexpr int q = opp(Ks);
-                    inflow_dtheta(G, z, q, T, dt);
                     const double f6 = 6.0 * (double)wgt(q) * (double)l;
-                    gr0 += f6 * dt[0];
-                    gr1 += f6 * dt[1];
-                    gr2 += f6 * dt[2];
+                    sx += (double)cx(q) * f6;
+                    sy += (double)cy(q) * f6;
+                    inl = true;
                 }
             }
             mu[Ks] = s;
         }(),
         ...);
+    if (inl) inflow_grad(G, z, T, sx, sy, gr0, gr1, gr2);
 }
 
 // In-place adjoint of the odd step, one direction at a time: the lambda
@@ -891,6 +899,8 @@ __device__ __forceinline__ void adjoint_emit(const Geo &G, const Shape &S, const
                                              double &gr1, double &gr2, std::integer_sequence<int, Is...>)
 {
     const uint32_t qs = (uint32_t)G.qs;
+    double sx = 0.0, sy = 0.0;
+    bool inl = false;
     (
         [&] {
             float v = lk_of(Is);
@@ -909,12 +919,10 @@ __device__ __forceinline__ void adjoint_emit(const Geo &G, const Shape &S, const
             }
             if (!shared) stg(lam, (uint32_t)l.slot * qs + (uint32_t)((int32_t)c + l.delta), v);
             if (l.inlet) {
-                float dt[3];
-                inflow_dtheta(G, z, Is, T, dt);
                 const double f6 = 6.0 * (double)wgt(Is) * (double)v;
-                gr0 += f6 * dt[0];
-                gr1 += f6 * dt[1];
-                gr2 += f6 * dt[2];
+                sx += (double)cx(Is) * f6;
+                sy += (double)cy(Is) * f6;
+                inl = true;
             }
             if constexpr (cx(Is) == -1) {
                 if (wave_out && outflow) {
@@ -925,6 +933,7 @@ __device__ __forceinline__ void adjoint_emit(const Geo &G, const Shape &S, const
             }
         }(),
         ...);
+    if (inl) inflow_grad(G, z, T, sx, sy, gr0, gr1, gr2);
 }
 
 // One adjoint step of every instance, with the tiling of the step kernels:
