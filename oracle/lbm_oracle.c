@@ -36,6 +36,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NQ 19
 
@@ -755,4 +758,17 @@ void orc_adjoint_step(const orc_case *k, long step, const double *f_n,
         }
     }
     free(mu);
+}
+
+/* Thread count of the OpenMP loops over cells (timing of the CPU baseline on
+ * one core and on all cores); returns the count now in effect. */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

@@ -101,8 +101,15 @@ def lib():
         L.orc_collision_jacobian.argtypes = [P(_Case), dp, dp]
         L.orc_adjoint_step.argtypes = [P(_Case), ctypes.c_long, dp, dp, dp, dp]
         L.orc_inflow_velocity.argtypes = [P(_Case), ctypes.c_int, ctypes.c_long, dp]
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's loops over cells (n <= 0: leave as is); returns the count in effect."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def _dp(a: np.ndarray):

@@ -26,7 +26,7 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import lbmsc as L
-from .sc import Ensemble, init_populations, stream_handle
+from .sc import Ensemble, stream_handle
 
 
 class CheckpointedAdjoint:
@@ -67,7 +67,7 @@ class CheckpointedAdjoint:
             per_slot = max(4 * cg.ncells if self.kind == L.RECORD_MACROS else 19 * cg.qs for cg in cgs)
             lam_len = max(19 * cg.qs for cg in cgs)
             self.rec.append(torch.empty(ckpt * per_slot, dtype=torch.float32, device="cuda"))
-            for b in range(1 if inplace else 2):
+            for b in range(1 if self.inplace else 2):
                 self.lam[b].append(torch.empty(lam_len, dtype=torch.float32, device="cuda"))
         self.grad = torch.zeros(n, 3, dtype=torch.float64, device="cuda")
         self._subplans = {}
@@ -135,7 +135,8 @@ class CheckpointedAdjoint:
     def backward(self, pweights: Sequence[Optional[torch.Tensor]]):
         """dJ/dtheta [n_inst, 3] (FP64) of J_i = sum_p pweights[i][p] <u_x(p)>.
 
-        Leaves every instance at step 0 in the rest state."""
+        Leaves every instance at step 0 in the rest state, with cleared QoI
+        sums (the populations are re-initialised after the sweep)."""
         ens = self.ens
         pw = [p.to(torch.float64).contiguous() if p is not None else None for p in pweights]
         pw_ptr = [p.data_ptr() if p is not None else None for p in pw]
@@ -149,15 +150,20 @@ class CheckpointedAdjoint:
                 plan = self._subplan(gi)
                 for i in members:
                     L.lbm_plan_set_theta(plan, members.index(i), list(ens.instances[i].theta))
-                    init_populations(ens.cases[ens.index[i][0]], ens.f[i])
+                    ens.f[i].zero_()          # the rest state (f - w = 0); geometry unchanged
                 L.lbm_plan_set_step(plan, 0)
                 self._advance_with_snapshots(plan, [ens.f[i] for i in members])
                 g = torch.zeros(len(members), 3, dtype=torch.float64, device="cuda")
                 self._sweep(plan, members, [pw_ptr[i] for i in members], g)
                 self.grad[members[0]:members[-1] + 1] = g
                 self.snaps = []
-        # the first snapshot is the rest state at step 0
+        # the sweep leaves the populations at the end of the first segment's
+        # re-run (and, grouped, in the subplans' state): back to the rest
+        # state, which is f - w = 0 in every slot, at step 0
+        for f in ens.f:
+            f.zero_()
         L.lbm_plan_set_step(ens.plan, 0)
+        L.lbm_plan_reset_qoi(ens.plan, stream_handle())
         return self.grad.clone()
 
     def close(self):

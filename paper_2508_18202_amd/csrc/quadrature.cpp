@@ -104,7 +104,6 @@ bool gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
     return true;
 }
 
-// Solve A y = b (dense, partial pivoting).
 // Golub-Welsch for the standard normal: the orthonormal probabilists'
 // Hermite recurrence has zero diagonal and off-diagonal sqrt(k).
 bool gauss_hermite(int n, std::vector<double> &x, std::vector<double> &w)

@@ -15,6 +15,10 @@ analytic solutions that any correct implementation must reproduce:
   (nu0 + Cs^2 |u'|) u' = -F (y - y_c);
 * Taylor-Green decay rate 2 nu k^2 and its second-order convergence;
 * a uniform stream through inlet/outlet/periodic faces is an exact fixed point;
+* the zero-gradient outlet continues an x-invariant state as if the domain
+  went on periodically in x: a state varying in y and z only gives, next to
+  the outlet, exactly the values of the x-periodic box (pins the source cell
+  (nx-1, s_y, s_z) of a diagonal outlet link; a source at (nx-1, y, z) fails);
 * the free-slip sky equals the mirror image of a channel twice as high;
 * the small block case is mirror-symmetric in y.
 """
@@ -204,3 +208,41 @@ def test_small_block_mirror_symmetry():
     assert np.abs(u[2] - u[2][:, ::-1, :]).max() < 1e-12 * scale
     assert np.abs(u[1] + u[1][:, ::-1, :]).max() < 1e-12 * scale
     assert np.isfinite(u).all() and scale > 0.01
+
+
+@pytest.mark.parametrize("model", ["bgk", "smagorinsky"])
+def test_outlet_continues_an_x_invariant_state(model):
+    """Zero normal gradient at the outlet: for a state that does not vary in
+    x, the ghost cell beyond the last column holds the same post-collision
+    values as the last column at the same (y, z), i.e. those of the
+    x-periodic continuation.  Starting from a random x-invariant state
+    (varying in y and z), k steps of a box with a wall at -x and the outlet
+    at +x equal k steps of the x-periodic box on every column the wall has
+    not reached yet (x >= k), the outlet column included, bit for bit."""
+    nx, ny, nz = 8, 6, 5
+    rng = np.random.default_rng(11)
+    w = orc.lattice()[1]
+    pert = 0.05 * rng.standard_normal((19, nz, ny))
+    f0 = (w[:, None, None, None] * (1.0 + pert[:, :, :, None])) * np.ones((1, 1, 1, nx))
+    f0 = f0.reshape(19, -1).copy()
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    kw = dict(model=model, tau0=0.58, cs=0.15)
+    out = orc.Case(nx, ny, nz, ["wall", "outlet", "periodic", "periodic", "periodic", "periodic"], solid, **kw)
+    per = orc.Case(nx, ny, nz, ["periodic"] * 6, solid, **kw)
+    fa, fb = f0.copy(), f0.copy()
+    for k in range(1, nx):
+        fa = out.step(k - 1, fa)
+        fb = per.step(k - 1, fb)
+        a = fa.reshape(19, nz, ny, nx)[:, :, :, k:]
+        b = fb.reshape(19, nz, ny, nx)[:, :, :, k:]
+        assert np.array_equal(a, b), k
+    # the state's y/z variation is large enough that a source at (nx-1, y, z)
+    # would change the diagonal outlet links: compare the post-collision
+    # values of the last column at (y, z) and at the link source (y - c_y, z - c_z)
+    c = orc.lattice()[0]
+    fs = np.stack([out.collide_cell(f0.reshape(19, nz, ny, nx)[:, z, y, nx - 1])
+                   for z in range(nz) for y in range(ny)], axis=1).reshape(19, nz, ny)
+    for i in range(19):
+        if c[i][0] == -1 and (c[i][1] or c[i][2]):
+            moved = np.roll(fs[i], (c[i][2], c[i][1]), axis=(0, 1))
+            assert np.abs(moved - fs[i]).max() > 1e-3 * w[i]
