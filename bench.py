@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -56,7 +58,8 @@ def parse():
                     help="skip the regularised-collision, series-inflow and Gauss-Hermite/gPC legs")
     ap.add_argument("--no-uneven", action="store_true", help="skip the batched vs one-at-a-time leg")
     ap.add_argument("--no-cylinder", action="store_true", help="skip the paper-size cylinder leg")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=16.0,
+                    help="time budget of the urban LES samples of the CPU baseline")
     ap.add_argument("--profile-calib", action="store_true",
                     help="also run a plain copy of known size (HBM counter calibration)")
     return ap.parse_args()
@@ -84,26 +87,112 @@ def load_traffic(launch_bytes_alg: float):
     return t.get("hbm_bytes_per_launch"), t.get("launch")
 
 
+def _host_cpu():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, solid, theta, seconds: float):
-    """The FP64 oracle as it stands, on one node of the same workload."""
-    cores = len(os.sched_getaffinity(0))
-    cores = max(1, min(cores, 16))
-    os.environ["OMP_NUM_THREADS"] = str(cores)
+    """The FP64 oracle as it stands, timed on the host on bounded samples of
+    the workloads: the headline urban LES case (one node; on every thread the
+    process may use and on one thread), the small block case in full, one
+    instance of each uneven box size, one node of the data-assimilation box,
+    and one node of the adjoint case forward and backward.  MLUPS count fluid
+    cells."""
     from oracle import oracle as orc
-    case = orc.Case.from_workload(w, solid, theta)
-    f = case.init()
+    from paper_2508_18202_amd import inputs
+    visible = len(os.sched_getaffinity(0))
+    omp = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    threads = omp if omp > 0 else visible
+    orc.set_threads(threads)
+    used = orc.set_threads(0)
+
+    def rate(case, n_fluid, step0, budget, max_steps, f=None):
+        f = case.init() if f is None else f
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            f = case.step(step0 + n, f)
+            n += 1
+            dt = time.perf_counter() - t0
+            if dt >= budget or n >= max_steps:
+                break
+        return n_fluid * n / dt / 1e6, n, dt
+
     fluid = int((solid == 0).sum())
-    n = 0
+    case = orc.Case.from_workload(w, solid, theta)
+    v_all, n_all, t_all = rate(case, fluid, 1000, 0.5 * seconds, 400)
+    orc.set_threads(1)
+    v_one, n_one, t_one = rate(case, fluid, 1000, 0.25 * seconds, 100)
+    orc.set_threads(threads)
+    legs = {"urban_les_one_thread": {"value": round(v_one, 2), "unit": "MLUPS", "threads": 1,
+                                     "sample": f"1 of 13 nodes, {n_one} steps past the ramp, {t_one:.1f} s"}}
+    # small block case in full: 5 Gauss-Legendre nodes x 1000 steps
+    sb = inputs.small_block()
+    sbs = inputs.solid_mask(sb)
+    xs, _ = orc.collocation(sb)
     t0 = time.perf_counter()
-    while True:
-        f = case.step(1000 + n, f)
-        n += 1
-        dt = time.perf_counter() - t0
-        if dt >= seconds or n >= 400:
-            break
-    return {"value": fluid * n / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle (gcc -O2, OpenMP), 1 of 13 nodes of the 256x128x64 urban LES case, "
-                      f"{n} time steps past the inflow ramp, {dt:.1f} s"}
+    for xi in xs:
+        orc.run(orc.Case.from_workload(sb, sbs, orc.node_params(sb, xi)), sb.steps)
+    dt = time.perf_counter() - t0
+    legs["small_block_full"] = {"value": round(len(xs) * int((sbs == 0).sum()) * sb.steps / dt / 1e6, 2),
+                                "unit": "MLUPS", "threads": used,
+                                "sample": f"all 5 nodes x 1000 steps (the whole case), {dt:.2f} s"}
+    # one instance per uneven box size
+    tot, tt = 0, 0.0
+    seen = set()
+    for uw in inputs.uneven_cases():
+        if (uw.nx, uw.ny, uw.nz) in seen:
+            continue
+        seen.add((uw.nx, uw.ny, uw.nz))
+        us = inputs.solid_mask(uw)
+        xu, _ = orc.collocation(uw)
+        r, n, dt = rate(orc.Case.from_workload(uw, us, orc.node_params(uw, xu[0])), int((us == 0).sum()), 1000,
+                        0.05 * seconds, 20)
+        tot += int((us == 0).sum()) * n
+        tt += dt
+    legs["uneven_one_per_size"] = {"value": round(tot / tt / 1e6, 2), "unit": "MLUPS", "threads": used,
+                                   "sample": "1 instance of each of 128x64x32, 192x96x48, 256x128x64, "
+                                             f"up to 20 steps each, {tt:.1f} s"}
+    # data-assimilation box: one node, a few steps
+    aw = inputs.assimilation_case()
+    asol = inputs.solid_mask(aw)
+    xa, _ = orc.collocation(aw)
+    r, n, dt = rate(orc.Case.from_workload(aw, asol, orc.node_params(aw, xa[0])), int((asol == 0).sum()), 1000,
+                    0.1 * seconds, 5)
+    legs["assimilation_one_node"] = {"value": round(r, 2), "unit": "MLUPS", "threads": used,
+                                     "sample": f"1 of 13 nodes of 512x256x128, {n} steps, {dt:.1f} s"}
+    # adjoint case: one node, forward with snapshots and the checkpointed adjoint
+    dw = inputs.adjoint_case(steps=20, avg_len=5)
+    dsol = inputs.solid_mask(dw)
+    probes = inputs.probe_cells(dw, dsol)
+    xd, _ = orc.collocation(dw)
+    dcase = orc.Case.from_workload(dw, dsol, orc.node_params(dw, xd[0]))
+    dfl = int((dsol == 0).sum())
+    t0 = time.perf_counter()
+    orc.run(dcase, dw.steps, avg_start=dw.avg_start, probes=probes)
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    orc.adjoint(dcase, dw.steps, dw.avg_start, probes, np.full(len(probes), 1.0 / len(probes)), ckpt=dw.steps)
+    t_adj = time.perf_counter() - t0
+    legs["adjoint_case_one_node"] = {"forward_mlups": round(dfl * dw.steps / t_fwd / 1e6, 2),
+                                     "adjoint_mlups": round(dfl * dw.steps / t_adj / 1e6, 2),
+                                     "adjoint_vs_forward": round(t_adj / t_fwd, 2), "threads": used,
+                                     "sample": f"1 of 13 nodes of 128x64x48, {dw.steps} steps forward, then the "
+                                               f"adjoint (forward re-run from the snapshot included), "
+                                               f"{t_fwd:.1f} s + {t_adj:.1f} s"}
+    return {"value": round(v_all, 2), "unit": "MLUPS", "cores": used, "kind": "oracle",
+            "sample": f"FP64 oracle (gcc -O2, OpenMP, {used} threads: the CPU share this process may use), "
+                      f"1 of 13 nodes of the 256x128x64 urban LES case, {n_all} time steps past the inflow ramp, "
+                      f"{t_all:.1f} s",
+            "host": {"cpu": _host_cpu(), "logical_cpus_visible": visible, "logical_cpus_total": os.cpu_count()},
+            "configs": legs}
 
 
 def copy_ceiling(nbytes: int = 2 << 30, reps: int = 5) -> float:
@@ -366,7 +455,21 @@ def adjoint_leg(variant, steps: int = 2000, avg_len: int = 500, ckpt: int = 100,
         e1.record()
         e1.synchronize()
         t_fwd = e0.elapsed_time(e1) / 1e3 / ckpt
-        coll = "BGK tau 0.6" if model == "bgk" else "regularised third-order collision, Smagorinsky Cs=0.1, tau0 0.6"
+        coll = {"bgk": "BGK tau 0.6",
+                "smagorinsky": "Smagorinsky Cs=0.1, tau0 0.6",
+                "rr3": "regularised third-order collision, Smagorinsky Cs=0.1, tau0 0.6"}[model]
+        gcpu = g.cpu().numpy()
+        grads = {str(j): [float(v) for v in gcpu[j]] for j in (2, 10)}
+        vs_oracle = None
+        gold = os.path.join(ROOT, "tests", "golden", "adjoint_case_gradient.json")
+        if model == "bgk" and steps == 2000 and ckpt == 100 and os.path.exists(gold):
+            with open(gold) as fh:
+                ref = json.load(fh)
+            vs_oracle = {}
+            for nd in ref["nodes"]:
+                go = np.asarray(nd["grad"])
+                gg = gcpu[nd["index"]]
+                vs_oracle[str(nd["index"])] = [float(abs(gg[k] - go[k]) / max(abs(go[k]), 1e-300)) for k in range(3)]
         return {"workload": f"13 Smolyak nodes x 128x64x48 {coll}, log-law inflow, probe plane, "
                             f"{steps} steps, objective over the last {avg_len}, snapshots every {ckpt}",
                 "forward_s": round(t1 - t0, 4), "adjoint_s": round(t2 - t1, 4),
@@ -375,9 +478,79 @@ def adjoint_leg(variant, steps: int = 2000, avg_len: int = 500, ckpt: int = 100,
                 "adjoint_step_us": round(t_adj * 1e6, 1), "forward_step_us": round(t_fwd * 1e6, 1),
                 "kernel_ratio": round(t_adj / t_fwd, 3),
                 "lambda_buffers": "one, in place" if run.inplace else "two",
-                "grad_finite": bool(torch.isfinite(g).all())}
+                "grad_finite": bool(torch.isfinite(g).all()),
+                "grad_nodes": grads,
+                "grad_rel_err_vs_stored_oracle": vs_oracle}
     finally:
         ens.close()
+
+
+def small_block_leg():
+    """The small SC-LBM case in full: 5 Gauss-Legendre nodes of the 32x16x16
+    BGK block case, 1000 steps, final fields and FP64 moments; the stepping
+    of the 5 nodes in one plan (graph replay) against one plan per node (one
+    launch per node per step).  3 MB of populations: cache-resident, so no
+    roofline figure."""
+    import torch
+    from paper_2508_18202_amd import inputs, sc
+    from paper_2508_18202_amd import lbmsc as L
+    w = inputs.small_block()
+    solid = inputs.solid_mask(w)
+    fluid = int((solid == 0).sum())
+    x, a, th = sc.collocation(w)
+    cg = sc.make_geometry(w, solid)
+
+    def sc_pass():
+        x, a, th = sc.collocation(w)
+        ens = sc.Ensemble([cg], [th], use_graph=True)
+        try:
+            ens.advance(w.steps)
+            q = torch.stack([ens.fields(j) for j in range(len(ens))])
+            mean, var = sc.moments(q, a)
+            if ens.health() >= 0:
+                raise RuntimeError("small block leg went unstable")
+            return mean
+        finally:
+            ens.close()
+
+    sc_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sc_pass()
+    torch.cuda.synchronize()
+    t_pass = time.perf_counter() - t0
+    ens = sc.Ensemble([cg], [th], use_graph=True)
+    try:
+        ens.advance(w.steps)
+        ens.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ens.advance(w.steps)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        plans = [L.lbm_plan_create([inst], use_graph=True) for inst in ens.instances]
+        stream = sc.stream_handle()
+        for p_ in plans:
+            L.lbm_collide_stream(p_, 2, stream)
+            L.lbm_plan_set_step(p_, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p_ in plans:
+            L.lbm_collide_stream(p_, w.steps, stream)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        for p_ in plans:
+            L.lbm_plan_destroy(p_)
+    finally:
+        ens.close()
+    n = len(th)
+    return {"workload": "5 Gauss-Legendre nodes x 32x16x16 D3Q19 BGK tau 0.6, one 6x6x8 block, uniform inflow "
+                        "0.05 (1 + 0.1 xi), 1000 steps, final fields and FP64 moments",
+            "sc_pass_ms": round(t_pass * 1e3, 2),
+            "sc_pass_mlups": round(n * fluid * w.steps / t_pass / 1e6, 1),
+            "batched_mlups": round(n * fluid * w.steps / tb / 1e6, 1),
+            "one_at_a_time_mlups": round(n * fluid * w.steps / ts / 1e6, 1),
+            "speedup": round(ts / tb, 3)}
 
 
 def uneven_leg(variant, steps: int = 60):
@@ -437,7 +610,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2508_18202_amd import inputs, sc
@@ -465,7 +637,9 @@ def main():
         ens.close()
         del ens, cg
 
-    def sc_pass(timing):
+    checks = {}
+
+    def sc_pass(timing, check=False):
         x, a, th = sc.collocation(w)                       # collocation rule + node parameters
         cg = sc.make_geometry(w, solid)
         ens = sc.Ensemble([cg], [th], avg_begin=w.avg_start, avg_end=w.steps,
@@ -481,11 +655,22 @@ def main():
             q = torch.empty(len(ens), cg.ncells, 4, dtype=torch.float32, device="cuda")
             for j in range(len(ens)):
                 ens.averages_into(j, q[j])
-            mean, var = sc.moments(q, a)
+            mean, var, nneg = sc.moments(q, a, count_negative=True)
             bad = ens.health()
             if bad >= 0:
                 raise RuntimeError(f"node {bad} went unstable")
             timing.append((e0, e1))
+            if check:
+                # invariants of the full-length run: finite fields and moments,
+                # the mean density deviation of every node (sum of f - w over the
+                # fluid cells, solid slots being zero), negative Smolyak variances
+                drift = [float(ens.populations(j).sum(dtype=torch.float64)) / n_fluid for j in range(len(ens))]
+                checks.update({
+                    "fields_finite": bool(torch.isfinite(q).all()),
+                    "moments_finite": bool(torch.isfinite(mean).all() and torch.isfinite(var).all()),
+                    "mean_density_deviation_max": max(abs(d) for d in drift),
+                    "negative_variance_count": int(nneg),
+                    "negative_variance_fraction": round(int(nneg) / (4 * n_fluid), 6)})
             return mean, var, len(ens)
         finally:
             ens.close()
@@ -495,8 +680,8 @@ def main():
     torch.cuda.synchronize()
     timing = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        mean, var, n_inst = sc_pass(timing)
+    for k in range(args.steps):
+        mean, var, n_inst = sc_pass(timing, check=(k == args.steps - 1))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -554,24 +739,34 @@ def main():
                              "frac": round(achieved / copy_gbs, 4)},
         },
         "kernel_mlups": round(n_inst * n_fluid / avg_launch_s / 1e6, 1),
+        "invariants": checks,
     }
+
+    def leg(name, fn, *a, **kw):
+        t0 = time.perf_counter()
+        r = fn(*a, **kw)
+        r["wall_s"] = round(time.perf_counter() - t0, 1)
+        out[name] = r
+    leg("small_block", small_block_leg)
     if not args.no_rr3:
-        out["regularised_collision"] = rr3_leg(variant)
-        out["series_inflow"] = series_leg(variant)
-        out["gauss_hermite_gpc"] = gauss_hermite_leg(variant)
+        leg("regularised_collision", rr3_leg, variant)
+        leg("series_inflow", series_leg, variant)
+        leg("gauss_hermite_gpc", gauss_hermite_leg, variant)
     if not args.no_cylinder:
-        out["cylinder"] = cylinder_leg(None if not args.block else variant)
+        leg("cylinder", cylinder_leg, None if not args.block else variant)
     if not args.no_adjoint:
         n_adj = args.adjoint_steps
         if n_adj < 200 or n_adj % 100:
             raise SystemExit("--adjoint-steps must be a multiple of 100, at least 200")
-        out["adjoint_vs_forward"] = adjoint_leg(variant, steps=n_adj, avg_len=n_adj // 4)
-        out["adjoint_vs_forward_regularised"] = adjoint_leg(variant, steps=n_adj, avg_len=n_adj // 4, model="rr3")
+        leg("adjoint_vs_forward", adjoint_leg, variant, steps=n_adj, avg_len=n_adj // 4)
+        leg("adjoint_vs_forward_smagorinsky", adjoint_leg, variant, steps=n_adj, avg_len=n_adj // 4,
+            model="smagorinsky")
+        leg("adjoint_vs_forward_regularised", adjoint_leg, variant, steps=n_adj, avg_len=n_adj // 4, model="rr3")
     if not args.no_uneven:
-        out["batched_vs_one_at_a_time"] = uneven_leg(variant)
+        leg("batched_vs_one_at_a_time", uneven_leg, variant)
     if not args.no_cpu:
         x, a, th = sc.collocation(w)
-        out["cpu_baseline"] = cpu_baseline(w, solid, th[0], args.cpu_seconds)
+        leg("cpu_baseline", cpu_baseline, w, solid, th[0], args.cpu_seconds)
     if args.profile_calib:
         n = 1 << 28
         src = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -281,9 +281,11 @@ int lbm_sc_moments(const float *q_dev, const double *w_host, int32_t n_nodes, in
  * lbm_gpc_basis (host): the P multi-indices of total degree <= order in dim
  *   variables (graded: degree 0, 1, ...; within a degree the first
  *   variable's power descending) into alpha_out[P][dim], and
- *   phi_out[j][p] = Phi_alpha_p(nodes[j]) for the n_nodes nodes [n][dim].
- *   P is returned through *n_basis; with phi_out == NULL only the count.
- *   cap = capacity of phi_out in rows of P values.
+ *   phi_out[j][p] = Phi_alpha_p(nodes[j]) for the n_nodes nodes [n][dim],
+ *   or, with the collocation weights given (weights_host[n], may be NULL),
+ *   the weighted basis a_j Phi_alpha_p(nodes[j]) that lbm_gpc_coefficients
+ *   takes.  P is returned through *n_basis; with phi_out == NULL only the
+ *   count.  cap = capacity of phi_out in rows of P values.
  * lbm_gpc_coefficients (device, FP64): coef[p][e] = sum_j wphi[j][p] q[j][e]
  *   for the node-major FP32 input q_dev[n_nodes][n_elems] and the weighted
  *   basis wphi_dev[n_nodes][n_basis] = a_j Phi_p(Z^(j)) (device, caller
@@ -292,8 +294,8 @@ int lbm_sc_moments(const float *q_dev, const double *w_host, int32_t n_nodes, in
  *   var_dev[e] = sum_{p >= 1} coef[p][e]^2 and the 95 % band
  *   band_dev[0][e] = coef[0][e] - 1.96 sqrt(var), band_dev[1][e] = coef[0][e] + 1.96 sqrt(var).
  *   Rejected: n_nodes < 1, n_basis < 1 or > 64, n_elems < 0. */
-int lbm_gpc_basis(const double *nodes_host, int32_t n_nodes, int32_t dim, int32_t order,
-                  double *phi_out, int32_t *alpha_out, int32_t cap, int32_t *n_basis);
+int lbm_gpc_basis(const double *nodes_host, const double *weights_host, int32_t n_nodes, int32_t dim,
+                  int32_t order, double *phi_out, int32_t *alpha_out, int32_t cap, int32_t *n_basis);
 int lbm_gpc_coefficients(const float *q_dev, const double *wphi_dev, int32_t n_nodes, int32_t n_basis,
                          int64_t n_elems, double *coef_dev, double *var_dev, double *band_dev,
                          hipStream_t stream);

@@ -464,8 +464,8 @@ int lbm_quadrature(int32_t kind, int32_t level, int32_t dim, double *nodes_host,
     return LBM_OK;
 }
 
-int lbm_gpc_basis(const double *nodes_host, int32_t n_nodes, int32_t dim, int32_t order, double *phi_out,
-                  int32_t *alpha_out, int32_t cap, int32_t *n_basis)
+int lbm_gpc_basis(const double *nodes_host, const double *weights_host, int32_t n_nodes, int32_t dim,
+                  int32_t order, double *phi_out, int32_t *alpha_out, int32_t cap, int32_t *n_basis)
 {
     if (dim < 1 || dim > 8 || order < 0 || order > 16 || n_nodes < 0)
         return fail(LBM_E_INVALID, "gPC basis: need 1 <= dim <= 8, 0 <= order <= 16, n_nodes >= 0");
@@ -478,6 +478,10 @@ int lbm_gpc_basis(const double *nodes_host, int32_t n_nodes, int32_t dim, int32_
     if (cap < n_nodes) return fail(LBM_E_INVALID, "gPC basis: capacity %d < %d nodes", cap, n_nodes);
     std::vector<double> phi;
     gpc_basis(nodes_host, n_nodes, dim, alpha, phi);
+    // projection weights of the coefficients c_p = sum_j a_j Q_j Phi_p(Z^(j))
+    if (weights_host)
+        for (int32_t j = 0; j < n_nodes; ++j)
+            for (int32_t k = 0; k < P; ++k) phi[(size_t)j * P + k] *= weights_host[j];
     std::memcpy(phi_out, phi.data(), sizeof(double) * phi.size());
     for (size_t k = 0; k < alpha.size(); ++k) alpha_out[k] = alpha[k];
     return LBM_OK;

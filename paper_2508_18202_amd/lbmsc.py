@@ -90,7 +90,7 @@ _SIGS = [
     ("lbm_read_populations", ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
     ("lbm_qoi_average", ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     ("lbm_sc_moments", ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P]),
-    ("lbm_gpc_basis", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int32,
+    ("lbm_gpc_basis", ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int32,
                                      _P]),
     ("lbm_gpc_coefficients", ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P, _P, _P,
                                             _P]),
@@ -158,16 +158,20 @@ def lbm_quadrature(kind, level: int, dim: int):
     return x, w
 
 
-def lbm_gpc_basis(nodes: np.ndarray, order: int):
-    """(phi [n, P], alpha [P, dim]) of the orthonormal Hermite chaos basis."""
+def lbm_gpc_basis(nodes: np.ndarray, order: int, weights: Optional[np.ndarray] = None):
+    """(phi [n, P], alpha [P, dim]) of the orthonormal Hermite chaos basis;
+    with weights, phi holds the weighted basis a_j Phi_p(Z^(j))."""
     x = np.ascontiguousarray(nodes, dtype=np.float64)
     n, dim = x.shape
+    wt = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+    if wt is not None and wt.shape != (n,):
+        raise ValueError("one weight per node")
     P = ctypes.c_int32(0)
-    _check(lib().lbm_gpc_basis(None, n, dim, order, None, None, 0, ctypes.byref(P)))
+    _check(lib().lbm_gpc_basis(None, None, n, dim, order, None, None, 0, ctypes.byref(P)))
     phi = np.zeros((n, P.value))
     alpha = np.zeros((P.value, dim), dtype=np.int32)
-    _check(lib().lbm_gpc_basis(x.ctypes.data, n, dim, order, phi.ctypes.data, alpha.ctypes.data, n,
-                               ctypes.byref(P)))
+    _check(lib().lbm_gpc_basis(x.ctypes.data, wt.ctypes.data if wt is not None else None, n, dim, order,
+                               phi.ctypes.data, alpha.ctypes.data, n, ctypes.byref(P)))
     return phi, alpha
 
 

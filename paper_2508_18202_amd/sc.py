@@ -205,11 +205,11 @@ def gpc(q: torch.Tensor, nodes: np.ndarray, weights: np.ndarray, order: int):
     nodes: coefficients [P, ...], multi-indices [P, d], mean (coef 0),
     variance (sum of the squared higher coefficients) and the 95 % band
     mean -+ 1.96 std, all FP64 from one kernel."""
-    phi, alpha = L.lbm_gpc_basis(nodes, order)
-    wphi = torch.from_numpy(phi * np.asarray(weights, dtype=np.float64)[:, None]).to(q.device).contiguous()
+    wphi_h, alpha = L.lbm_gpc_basis(nodes, order, weights)
+    wphi = torch.from_numpy(wphi_h).to(q.device).contiguous()
     q = q.contiguous()
     n = q[0].numel()
-    P = phi.shape[1]
+    P = wphi_h.shape[1]
     coef = torch.empty((P,) + tuple(q.shape[1:]), dtype=torch.float64, device=q.device)
     var = torch.empty(tuple(q.shape[1:]), dtype=torch.float64, device=q.device)
     band = torch.empty((2,) + tuple(q.shape[1:]), dtype=torch.float64, device=q.device)

@@ -84,6 +84,11 @@ def test_gpc_basis_matches_oracle(dim, order):
     phio, alphao = orc.gpc_basis(nodes, order)
     assert np.array_equal(alpha, alphao)
     assert np.abs(phi - phio).max() < 1e-12 * max(1.0, np.abs(phio).max())
+    # the weighted basis a_j Phi_p(Z^(j)) of the projection, with the rule's weights
+    _, wts = orc.tensor_gauss_hermite(5, dim)
+    wphi, alpha_w = L.lbm_gpc_basis(nodes, order, wts)
+    assert np.array_equal(alpha_w, alphao)
+    assert np.abs(wphi - wts[:, None] * phio).max() < 1e-12 * max(1.0, np.abs(phio).max())
 
 
 def test_gpc_rejections():
