@@ -23,7 +23,8 @@
  *     HIP device; _host pointers are host memory.  The caller allocates and
  *     frees all device buffers.  The library allocates device memory only
  *     inside an lbm_plan (instance and tile tables, health words, captured
- *     graphs) and frees it in lbm_plan_destroy.
+ *     graphs) and frees it in lbm_plan_destroy; besides, it holds one static
+ *     8 MiB scratch array per device for lbm_adjoint_step_inplace_noalloc.
  *   - Calls taking a hipStream_t only enqueue work on that stream (they may
  *     copy small host tables synchronously first); device faults surface on a
  *     later call or on lbm_sync / lbm_check_health.
@@ -342,6 +343,24 @@ int lbm_adjoint_step(lbm_plan *plan, int64_t step, float *const *lam_in_host,
 int lbm_adjoint_step_inplace(lbm_plan *plan, int64_t step, float *const *lam_host, float *const *rec_host,
                              int32_t record_kind, int32_t n_slots, const double *const *pw_host,
                              double *dJdtheta_dev, hipStream_t stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * step as lbm_adjoint_step_inplace, same arguments and results, but it calls
+ * no hipMalloc, hipFree or other allocating routine.  Its scratch (the three
+ * tables of buffer pointers, copied from the host arrays with stream-ordered
+ * copies, and one FP64 gradient partial triple per tile) lives in a
+ * library-owned device array of 8 MiB per device, held until the process
+ * ends: 3 * align256(8 n_inst) + 24 n_tiles bytes must fit (about 340 000
+ * tiles, e.g. 44 M cells at 128 cells per tile), otherwise LBM_E_INVALID.
+ * Every call on one device shares that array and leaves its contents there;
+ * every partial is rewritten by each call, so nothing needs clearing.  Calls
+ * that may overlap on one device (several streams, several host threads, or
+ * several plans without ordering between them) race on the array: the
+ * caller orders them, e.g. on one stream. */
+int lbm_adjoint_step_inplace_noalloc(lbm_plan *plan, int64_t step, float *const *lam_host,
+                                     float *const *rec_host, int32_t record_kind, int32_t n_slots,
+                                     const double *const *pw_host, double *dJdtheta_dev,
+                                     hipStream_t stream);
 /* lam^N = dj_N/df^N from the plan's current (even) state N; lam_out as above. */
 int lbm_adjoint_init(lbm_plan *plan, float *const *lam_out_host, const double *const *pw_host,
                      hipStream_t stream);

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -138,6 +139,37 @@ int check_device()
     HIPCHK(hipGetDeviceProperties(&prop, dev));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(LBM_E_UNSUPPORTED, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+    return LBM_OK;
+}
+
+// Device scratch of lbm_adjoint_step_inplace_noalloc: the instance tables
+// of buffer pointers and the per-tile gradient partials of one adjoint step.
+// One copy per device, resident until the process ends.  Host code never
+// uses the array's name as an address: the device address of each device's
+// copy is taken once with hipGetSymbolAddress (scratch_ptr).
+constexpr size_t SCRATCH_BYTES = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of the current device's scratch array (looked up on the
+// first call on that device, with the device current).
+int scratch_ptr(unsigned char **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(LBM_E_UNSUPPORTED, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(LBM_E_HIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev, hipGetErrorString(e));
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = (unsigned char *)g_scratch_dev[dev];
     return LBM_OK;
 }
 
@@ -854,7 +886,7 @@ namespace {
 // mode 0: two buffers (natural layout); mode 1 / 2: one buffer in place
 int adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float *const *lam_out_host,
                  float *const *rec_host, int32_t kind, int32_t n_slots, const double *const *pw_host,
-                 double *dJdtheta_dev, int mode, hipStream_t s)
+                 double *dJdtheta_dev, int mode, bool noalloc, hipStream_t s)
 {
     int r = check_plan(p);
     if (r) return r;
@@ -867,11 +899,33 @@ int adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float *co
         if (!lam_in_host[i] || !lam_out_host[i] || !rec_host[i] || (mode == 0 && lam_in_host[i] == lam_out_host[i]))
             return fail(LBM_E_INVALID, "instance %d: missing or aliased adjoint buffers", i);
     AdjArgs a{};
-    r = table_of(p, (float *const *)lam_in_host, (float ***)&a.lam_in);
-    if (!r) r = table_of(p, (float *const *)lam_out_host, (float ***)&a.lam_out);
-    if (!r) r = table_of(p, (float *const *)rec_host, (float ***)&a.rec);
-    if (!r) r = table_of(p, (const double *const *)pw_host, (const double ***)&a.pw);
-    if (r) return r;
+    double *part = nullptr;
+    if (noalloc) {
+        // tables and partials in the device scratch array: [lam][rec][pw][partials]
+        const size_t tab = (size_t)align256(8 * (int64_t)p->n_inst);
+        const size_t need = 3 * tab + sizeof(double) * 3 * (size_t)p->n_tiles;
+        if (need > SCRATCH_BYTES)
+            return fail(LBM_E_INVALID,
+                        "the allocation-free adjoint step needs %zu bytes of scratch for %d instances and %d tiles; "
+                        "the limit is %zu",
+                        need, p->n_inst, p->n_tiles, SCRATCH_BYTES);
+        unsigned char *sp = nullptr;
+        r = scratch_ptr(&sp);
+        if (r) return r;
+        HIPCHK(hipMemcpyAsync(sp, lam_out_host, 8 * (size_t)p->n_inst, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(sp + tab, rec_host, 8 * (size_t)p->n_inst, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(sp + 2 * tab, pw_host, 8 * (size_t)p->n_inst, hipMemcpyHostToDevice, s));
+        a.lam_in = a.lam_out = (float *const *)sp;
+        a.rec = (float *const *)(sp + tab);
+        a.pw = (const double *const *)(sp + 2 * tab);
+        part = (double *)(sp + 3 * tab);
+    } else {
+        r = table_of(p, (float *const *)lam_in_host, (float ***)&a.lam_in);
+        if (!r) r = table_of(p, (float *const *)lam_out_host, (float ***)&a.lam_out);
+        if (!r) r = table_of(p, (float *const *)rec_host, (float ***)&a.rec);
+        if (!r) r = table_of(p, (const double *const *)pw_host, (const double ***)&a.pw);
+        if (r) return r;
+    }
     a.step = step;
     a.model = p->model;
     a.record = kind;
@@ -879,14 +933,18 @@ int adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float *co
     a.in_window = (p->avg_begin < step && step <= p->avg_end) ? 1 : 0;
     a.inv_count = p->avg_end > p->avg_begin ? 1.0 / (double)(p->avg_end - p->avg_begin) : 0.0;
     a.grad = dJdtheta_dev;
-    if (p->gpart_tiles < p->n_tiles) {
-        if (p->gpart_d) HIPCHK(hipFree(p->gpart_d));
-        p->gpart_d = nullptr;
-        p->gpart_tiles = 0;
-        HIPCHK(hipMalloc(&p->gpart_d, sizeof(double) * 3 * (size_t)p->n_tiles));
-        p->gpart_tiles = p->n_tiles;
+    if (!noalloc) {
+        if (p->gpart_tiles < p->n_tiles) {
+            if (p->gpart_d) HIPCHK(hipFree(p->gpart_d));
+            p->gpart_d = nullptr;
+            p->gpart_tiles = 0;
+            HIPCHK(hipMalloc(&p->gpart_d, sizeof(double) * 3 * (size_t)p->n_tiles));
+            p->gpart_tiles = p->n_tiles;
+        }
+        part = p->gpart_d;
     }
-    a.part = p->gpart_d;
+    // every tile writes its partial, so the buffer needs no clearing
+    a.part = part;
     a.tinfo = p->tinfo_d;
     // the adjoint keeps more live state per cell than a step: it runs one
     // cell per thread over the same tiles (whole tile per workgroup, up to
@@ -895,7 +953,7 @@ int adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float *co
     va.bs = std::min(p->v.tile(), 512);
     va.cpt = p->v.tile() / va.bs;
     if (launch_adjoint(va, p->geo_d, p->tiles_d, p->n_tiles, a, mode, s) ||
-        launch_grad_reduce(p->v.tile(), p->geo_h.data(), p->n_inst, p->geo_d, p->gpart_d, dJdtheta_dev, s))
+        launch_grad_reduce(p->v.tile(), p->geo_h.data(), p->n_inst, p->geo_d, part, dJdtheta_dev, s))
         return fail(LBM_E_HIP, "adjoint launch failed: %s", hipGetErrorString(hipGetLastError()));
     return LBM_OK;
 }
@@ -906,7 +964,8 @@ int lbm_adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float
                      float *const *rec_host, int32_t kind, int32_t n_slots, const double *const *pw_host,
                      double *dJdtheta_dev, hipStream_t s)
 {
-    return adjoint_step(p, step, lam_in_host, lam_out_host, rec_host, kind, n_slots, pw_host, dJdtheta_dev, 0, s);
+    return adjoint_step(p, step, lam_in_host, lam_out_host, rec_host, kind, n_slots, pw_host, dJdtheta_dev, 0, false,
+                        s);
 }
 
 int lbm_adjoint_step_inplace(lbm_plan *p, int64_t step, float *const *lam_host, float *const *rec_host,
@@ -914,7 +973,15 @@ int lbm_adjoint_step_inplace(lbm_plan *p, int64_t step, float *const *lam_host, 
                              hipStream_t s)
 {
     return adjoint_step(p, step, lam_host, lam_host, rec_host, kind, n_slots, pw_host, dJdtheta_dev,
-                        (step & 1) ? 1 : 2, s);
+                        (step & 1) ? 1 : 2, false, s);
+}
+
+int lbm_adjoint_step_inplace_noalloc(lbm_plan *p, int64_t step, float *const *lam_host, float *const *rec_host,
+                                     int32_t kind, int32_t n_slots, const double *const *pw_host,
+                                     double *dJdtheta_dev, hipStream_t s)
+{
+    return adjoint_step(p, step, lam_host, lam_host, rec_host, kind, n_slots, pw_host, dJdtheta_dev,
+                        (step & 1) ? 1 : 2, true, s);
 }
 
 int lbm_adjoint_init(lbm_plan *p, float *const *lam_out_host, const double *const *pw_host, hipStream_t s)

@@ -98,6 +98,8 @@ _SIGS = [
                                         ctypes.c_int32, _P, _P, _P]),
     ("lbm_adjoint_step_inplace", ctypes.c_int, [_P, ctypes.c_int64, _P, _P, ctypes.c_int32, ctypes.c_int32,
                                                 _P, _P, _P]),
+    ("lbm_adjoint_step_inplace_noalloc", ctypes.c_int, [_P, ctypes.c_int64, _P, _P, ctypes.c_int32,
+                                                        ctypes.c_int32, _P, _P, _P]),
     ("lbm_adjoint_init", ctypes.c_int, [_P, _P, _P, _P]),
 ]
 
@@ -308,6 +310,12 @@ def lbm_adjoint_step_inplace(plan, step: int, lam: Sequence[int], rec: Sequence[
                              pw: Sequence[Optional[int]], grad_dev: int, stream: int):
     _check(lib().lbm_adjoint_step_inplace(plan, step, _ptr_array(lam), _ptr_array(rec), kind, n_slots,
                                           _ptr_array(pw), grad_dev, stream))
+
+
+def lbm_adjoint_step_inplace_noalloc(plan, step: int, lam: Sequence[int], rec: Sequence[int], kind: int,
+                                     n_slots: int, pw: Sequence[Optional[int]], grad_dev: int, stream: int):
+    _check(lib().lbm_adjoint_step_inplace_noalloc(plan, step, _ptr_array(lam), _ptr_array(rec), kind, n_slots,
+                                                  _ptr_array(pw), grad_dev, stream))
 
 
 def lbm_adjoint_init(plan, lam_out: Sequence[int], pw: Sequence[Optional[int]], stream: int):
