@@ -60,6 +60,11 @@ def parse():
     ap.add_argument("--no-cylinder", action="store_true", help="skip the paper-size cylinder leg")
     ap.add_argument("--cpu-seconds", type=float, default=16.0,
                     help="time budget of the urban LES samples of the CPU baseline")
+    ap.add_argument("--assimilation-iters", type=int, default=0,
+                    help="also run the data-assimilation configuration at its size for this many "
+                         "gradient-descent iterations (about 100 s each; 0 = skip)")
+    ap.add_argument("--only-assimilation", action="store_true",
+                    help="skip the headline pass and every other leg (with --assimilation-iters)")
     ap.add_argument("--profile-calib", action="store_true",
                     help="also run a plain copy of known size (HBM counter calibration)")
     return ap.parse_args()
@@ -601,6 +606,65 @@ def uneven_leg(variant, steps: int = 60):
         ens.close()
 
 
+def assimilation_leg(iters: int):
+    """The data-assimilation configuration at its size: 13 Smolyak nodes of
+    the 512x256x128 Smagorinsky box (10x6 buildings, 16.8 M cells each), 64
+    probes, 2000 steps per forward run with the objective over the last 500,
+    observations from the hidden truth with 5 % noise, then `iters`
+    gradient-descent iterations (Armijo backtracking) through the
+    checkpointed adjoint, one node per reverse sweep (group_size 1: snapshots
+    every 100 steps and 100 recorded population states of one node)."""
+    import torch
+    from paper_2508_18202_amd import inputs
+    from paper_2508_18202_amd.assimilation import Assimilation
+    w = inputs.assimilation_case()
+    t0 = time.perf_counter()
+    da = Assimilation(w, w.steps, w.steps - w.avg_start, ckpt=100, group_size=1)
+    t_setup = time.perf_counter() - t0
+    try:
+        fwd, bwd = [], []
+        run_f, run_b = da.runner.forward, da.runner.backward
+
+        def timed_forward():
+            t = time.perf_counter()
+            r = run_f()
+            torch.cuda.synchronize()
+            fwd.append(time.perf_counter() - t)
+            return r
+
+        def timed_backward(pw):
+            t = time.perf_counter()
+            r = run_b(pw)
+            torch.cuda.synchronize()
+            bwd.append(time.perf_counter() - t)
+            return r
+
+        da.runner.forward, da.runner.backward = timed_forward, timed_backward
+        n_probes = len(da.ens.cases[0].probes)
+        t0 = time.perf_counter()
+        da.observe(inputs.da_truth(), inputs.da_noise(2 * n_probes))
+        t_obs = time.perf_counter() - t0
+        torch.cuda.reset_peak_memory_stats()
+        t0 = time.perf_counter()
+        hist = da.run(inputs.da_start(), iters)
+        t_run = time.perf_counter() - t0
+        peak = torch.cuda.max_memory_allocated()
+        free, total = torch.cuda.mem_get_info()
+        fluid = int((inputs.solid_mask(w) == 0).sum())
+        return {"workload": "13 Smolyak nodes x 512x256x128 D3Q19 Smagorinsky Cs=0.1, 10x6 buildings, log-law inflow, "
+                            "64 probes, 2000 steps per forward run (objective over the last 500), snapshots every 100, "
+                            "one node per reverse sweep",
+                "iterations": len(hist), "setup_s": round(t_setup, 1), "observe_s": round(t_obs, 1),
+                "run_s": round(t_run, 1), "s_per_iteration": round(t_run / max(1, len(hist)), 1),
+                "forward_runs_s": [round(v, 2) for v in fwd], "backward_runs_s": [round(v, 2) for v in bwd],
+                "forward_mlups": round(13 * fluid * w.steps / min(fwd) / 1e6, 1) if fwd else None,
+                "history": hist,
+                "peak_torch_gib": round(peak / 2 ** 30, 1),
+                "device_used_gib": round((total - free) / 2 ** 30, 1)}
+    finally:
+        da.close()
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -616,6 +680,9 @@ def main():
     from paper_2508_18202_amd import lbmsc as L
 
     torch.cuda.set_device(0)
+    if args.only_assimilation:
+        print(json.dumps({"assimilation": assimilation_leg(max(1, args.assimilation_iters))}), flush=True)
+        return
     lbm_steps = args.lbm_steps
     w = inputs.urban_les(steps=lbm_steps, avg_len=min(args.avg_len, lbm_steps))
     if args.model != w.model:        # experiments only: the workload is Smagorinsky
@@ -764,6 +831,8 @@ def main():
         leg("adjoint_vs_forward_regularised", adjoint_leg, variant, steps=n_adj, avg_len=n_adj // 4, model="rr3")
     if not args.no_uneven:
         leg("batched_vs_one_at_a_time", uneven_leg, variant)
+    if args.assimilation_iters > 0:
+        leg("assimilation", assimilation_leg, args.assimilation_iters)
     if not args.no_cpu:
         x, a, th = sc.collocation(w)
         leg("cpu_baseline", cpu_baseline, w, solid, th[0], args.cpu_seconds)

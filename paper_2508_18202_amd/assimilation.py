@@ -18,6 +18,7 @@ parameter map; steps use gradient descent with Armijo backtracking.
 from __future__ import annotations
 
 import math
+import time
 from typing import Dict, List, Optional, Tuple
 
 import numpy as np
@@ -88,6 +89,7 @@ class Assimilation:
         hist = []
         step = step0
         for it in range(iters):
+            t0 = time.perf_counter()
             p = params.clone().requires_grad_(True)
             L = self.loss(p)
             (g,) = torch.autograd.grad(L, p)
@@ -97,9 +99,11 @@ class Assimilation:
             if gn2 == 0.0:
                 # a stationary point (with exact observations, the truth)
                 hist.append({"iter": it, "mu": float(params[0]), "s": float(params[1]), "loss": lval,
-                             "grad": [0.0, 0.0], "step": step, "accepted": False})
+                             "grad": [0.0, 0.0], "step": step, "accepted": False, "trials": 0,
+                             "wall_s": round(time.perf_counter() - t0, 2)})
                 break
             accepted = False
+            trials = 0
             for _ in range(max_backtrack):
                 trial = params - step * g
                 if float(trial[1]) <= 0.0:
@@ -107,6 +111,7 @@ class Assimilation:
                     continue
                 with torch.no_grad():
                     lt = float(self.loss(trial))
+                trials += 1
                 if lt <= lval - 1e-4 * step * gn2:
                     params = trial
                     accepted = True
@@ -114,5 +119,6 @@ class Assimilation:
                     break
                 step *= 0.5
             hist.append({"iter": it, "mu": float(params[0]), "s": float(params[1]), "loss": lval,
-                         "grad": [float(v) for v in g], "step": step, "accepted": accepted})
+                         "grad": [float(v) for v in g], "step": step, "accepted": accepted, "trials": trials,
+                         "wall_s": round(time.perf_counter() - t0, 2)})
         return hist

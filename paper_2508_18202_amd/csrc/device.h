@@ -242,6 +242,75 @@ __device__ __forceinline__ void scatter_all(const Geo &G, const Shape &S, const 
         ...);
 }
 
+// Wavefronts of rule class 1 hold boundary lanes only in the first and last
+// x column, with the -x face an inlet or a wall and the +x face an outlet or
+// a wall (periodic x faces, y/z faces and solid neighbours are classes 2 and
+// 3).  Their links are the plain stencil except for the five directions that
+// cross an x face, which these forms patch per lane:
+//   gather, c_x = +1 at x = 0:      own slot I (bounce-back), plus the
+//                                   moving-wall momentum at an inlet;
+//   gather, c_x = -1 at x = nx-1:   outlet: slot opp(I) of (nx-1, y - c_y,
+//                                   z - c_z); wall: own slot I;
+//   scatter, c_x = -1 at x = 0:     own slot opp(K) (plus the moving-wall
+//                                   momentum at an inlet);
+//   scatter, c_x = +1 at x = nx-1:  outlet: no destination; wall: own slot
+//                                   opp(K);
+//   scatter, c_x = -1 at x = nx-1:  outlet: also slot K of (nx-1, y + c_y,
+//                                   z + c_z), the zero-gradient link of that
+//                                   cell.
+// Indices are clamped into the instance (lanes of solid cells gather before
+// their kind is known; their values are dropped).
+template <bool NT = false, int... Is>
+__device__ __forceinline__ void gather_x(const Geo &G, const Shape &S, bool xlo, bool xhi, uint32_t c, float U,
+                                         const InflowT &T, float g[Q], std::integer_sequence<int, Is...>)
+{
+    const GLOBAL_AS float *__restrict__ f = gp(G.f);
+    const uint32_t qs = (uint32_t)G.qs;
+    const uint32_t last = (uint32_t)G.ncells - 1u;
+    const bool inl = S.face[0] == FACE_INLET, out = S.face[1] == FACE_OUTLET;
+    (
+        [&] {
+            constexpr int I = Is;
+            const uint32_t pn = umin_u32((uint32_t)((int32_t)c - off_of(G, I)), last);
+            if constexpr (cx(I) == 1) {
+                const float v = ldg<NT>(f, xlo ? (uint32_t)I * qs + c : (uint32_t)opp(I) * qs + pn);
+                g[I] = (xlo && inl) ? v + inlet_term(I, U, T) : v;
+            } else if constexpr (cx(I) == -1) {
+                const uint32_t po = umin_u32(pn - 1u, last);
+                g[I] = ldg<NT>(f, !xhi ? (uint32_t)opp(I) * qs + pn
+                                       : (out ? (uint32_t)opp(I) * qs + po : (uint32_t)I * qs + c));
+            } else {
+                g[I] = ldg<NT>(f, (uint32_t)opp(I) * qs + pn);
+            }
+        }(),
+        ...);
+}
+
+template <bool NT = false, int... Ks>
+__device__ __forceinline__ void scatter_x(const Geo &G, const Shape &S, bool xlo, bool xhi, uint32_t c, float U,
+                                          const InflowT &T, const float g[Q], std::integer_sequence<int, Ks...>)
+{
+    GLOBAL_AS float *__restrict__ f = gp(G.f);
+    const uint32_t qs = (uint32_t)G.qs;
+    const bool inl = S.face[0] == FACE_INLET, out = S.face[1] == FACE_OUTLET;
+    (
+        [&] {
+            constexpr int K = Ks;
+            const uint32_t pn = (uint32_t)((int32_t)c + off_of(G, K));
+            if constexpr (cx(K) == -1) {
+                const float v = (xlo && inl) ? g[K] + inlet_term(opp(K), U, T) : g[K];
+                stg<NT>(f, xlo ? (uint32_t)opp(K) * qs + c : (uint32_t)K * qs + pn, v);
+                if (xhi && out)
+                    stg<NT>(f, (uint32_t)K * qs + (uint32_t)((int32_t)c + cy(K) * G.offy + cz(K) * G.offz), g[K]);
+            } else if constexpr (cx(K) == 1) {
+                if (!(xhi && out)) stg<NT>(f, xhi ? (uint32_t)opp(K) * qs + c : (uint32_t)K * qs + pn, g[K]);
+            } else {
+                stg<NT>(f, (uint32_t)K * qs + pn, g[K]);
+            }
+        }(),
+        ...);
+}
+
 using Dirs = std::make_integer_sequence<int, Q>;
 
 // Populations f^n(x) of a fluid cell in the current storage state.
@@ -564,8 +633,7 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
             if (inl) U[j] = inflow_speed(G, z);
             if (active) {
                 const InflowT T = flow_wave[j] ? inflow_at(G, a.step - 1) : InflowT{0.f, 0.f, 0.f, 0.f};
-                const Preds px{pr[j].xlo, pr[j].xhi, false, false, false, false, false};
-                gather_all<NT, true>(G, S, px, 0u, c[j], U[j], T, g[j], Dirs{});
+                gather_x<NT>(G, S, pr[j].xlo, pr[j].xhi, c[j], U[j], T, g[j], Dirs{});
             }
         }
         fl[j] = active ? gp(G.flags)[c[j]] : (uint8_t)FL_SOLID;
@@ -659,8 +727,7 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
             const Preds ps{pr[j].xlo, pr[j].xhi, false, false, false, false, pr[j].mantle};
             scatter_all<NT>(G, S, ps, sm[j], c[j], U[j], T, g[j], Dirs{});
         } else {
-            const Preds px{pr[j].xlo, pr[j].xhi, false, false, false, false, false};
-            scatter_all<NT>(G, S, px, 0u, c[j], U[j], T, g[j], Dirs{});
+            scatter_x<NT>(G, S, pr[j].xlo, pr[j].xhi, c[j], U[j], T, g[j], Dirs{});
         }
     }
 }
@@ -709,15 +776,86 @@ __device__ __forceinline__ void inflow_grad(const Geo &G, int z, const InflowT &
     g2 += (double)a2 * cd;
 }
 
+// Weighted moments of a field v over the velocity set, from the sums and
+// differences of opposite pairs: m0 = sum w v, m1_a = sum w c_a v, the
+// second-order tensor m2 = sum w c c v (xx, yy, zz, xy, xz, yz) and h3_j =
+// sum w P_j(c) v for the six third-order polynomials P_j above.
+struct WMoments {
+    float m0, m1[3], m2[6], h3[6];
+};
+
+__device__ __forceinline__ WMoments weighted_moments(const float v[Q])
+{
+    WMoments M;
+    M.m0 = wgt(0) * v[0];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) M.m1[a] = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) M.m2[a] = M.h3[a] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int i = 2 * k + 1;
+        const float ws = wgt(i) * (v[i] + v[i + 1]);
+        const float wd = wgt(i) * (v[i] - v[i + 1]);
+        M.m0 += ws;
+        if (cx(i)) { M.m1[0] += cx(i) * wd; M.m2[0] += ws; }
+        if (cy(i)) { M.m1[1] += cy(i) * wd; M.m2[1] += ws; }
+        if (cz(i)) { M.m1[2] += cz(i) * wd; M.m2[2] += ws; }
+        if (cx(i) && cy(i)) M.m2[3] += cx(i) * cy(i) * ws;
+        if (cx(i) && cz(i)) M.m2[4] += cx(i) * cz(i) * ws;
+        if (cy(i) && cz(i)) M.m2[5] += cy(i) * cz(i) * ws;
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            if (herm3(j, i) != 0.0f) M.h3[j] += herm3(j, i) * wd;
+    }
+    return M;
+}
+
+// out_k = scale base_k + alpha + beta . c_k + c_k^T Gam c_k + sum_j gam_j P_j(c_k)
+// for every direction k (Gam symmetric: xx, yy, zz, xy, xz, yz), evaluated
+// per opposite pair as its even part plus or minus its odd part.
+template <bool THIRD, bool BASE>
+__device__ __forceinline__ void eval_poly(float out[Q], const float base[Q], float scale, float alpha,
+                                          const float beta[3], const float Gam[6], const float gam[6])
+{
+    out[0] = BASE ? scale * base[0] + alpha : alpha;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int i = 2 * k + 1;
+        float E = alpha, O = 0.0f;
+        if (cx(i)) { E += Gam[0]; O += cx(i) * beta[0]; }
+        if (cy(i)) { E += Gam[1]; O += cy(i) * beta[1]; }
+        if (cz(i)) { E += Gam[2]; O += cz(i) * beta[2]; }
+        if (cx(i) && cy(i)) E += (float)(2 * cx(i) * cy(i)) * Gam[3];
+        if (cx(i) && cz(i)) E += (float)(2 * cx(i) * cz(i)) * Gam[4];
+        if (cy(i) && cz(i)) E += (float)(2 * cy(i) * cz(i)) * Gam[5];
+        if constexpr (THIRD) {
+#pragma unroll
+            for (int j = 0; j < 6; ++j)
+                if (herm3(j, i) != 0.0f) O += herm3(j, i) * gam[j];
+        }
+        out[i] = BASE ? scale * base[i] + (E + O) : E + O;
+        out[i + 1] = BASE ? scale * base[i + 1] + (E - O) : E - O;
+    }
+}
+
 // lambda = J^T mu of the regularised collision f* = f_eq3 + (1 - om) R f1,
-// f1 = f - f_eq3, R the regularisation (second-order stress and third-order
-// projections): with nu = R^T mu and x = mu - (1 - om) nu,
+// f1 = f - f_eq3, with R the regularisation (the second-order stress and
+// third-order Hermite projections), written in moments.  With nu = R^T mu and
+// x = mu - (1 - om) nu,
 //   lambda_k = s_rho(x) + (c_k - u).t(x) + (1 - om) nu_k + (mu.R f1 / tau^2) dtau/df_k,
-// where s_rho + (c - u).t is the transposed derivative of f_eq3 (orders 0..3)
-// and every sum is a Hermite moment.  srcw: objective weight of u_x (the
-// source srcw (c_kx - u_x) / rho is added).
-__device__ __forceinline__ void adjoint_rr3(const Geo &G, const float g[Q], const float mu[Q], float srcw,
-                                            float lam[Q])
+// s_rho + (c - u).t being the transposed derivative of f_eq3 (orders 0..3),
+// which needs only the weighted moments of x.  nu_k = 4.5 c_k^T M' c_k +
+// sum_j b_j P_j(c_k) / N_j with M = sum w mu c c, M' = M - (sum w mu) I / 3 and
+// b_j = sum w mu P_j(c); the D3Q19 lattice moments (sum w = 1,
+// sum w c_a c_b = delta / 3, sum w c_a c_b c_c c_d = (three deltas) / 9, odd
+// moments zero, sum w P_j P_j' = N_j delta_jj') give the moments of w nu in
+// closed form: order 0 1.5 tr M', order 1 zero, order 2
+// (tr M' I + 2 M') / 2, third order b_j.  lambda_k is then a cubic
+// polynomial in c_k with sixteen coefficients.  srcw: objective weight of
+// u_x (adds srcw (c_kx - u_x) / rho).
+__device__ __forceinline__ void adjoint_rr3_moments(const Geo &G, const float g[Q], const float mu[Q], float srcw,
+                                                    float lam[Q])
 {
     const PairSums ps = pair_sums(g);
     const Macro m = macro_of(g, ps);
@@ -726,9 +864,9 @@ __device__ __forceinline__ void adjoint_rr3(const Geo &G, const float g[Q], cons
     const float qn = stress_norm(P);
     const float R = sqrtf(G.tau0 * G.tau0 + G.kcs * qn / m.rho);
     const float tau = 0.5f * (G.tau0 + R);
-    const float keep = 1.0f - 1.0f / tau;
+    const float om = 1.0f / tau;
+    const float keep = 1.0f - om;
     const float ux = m.ux, uy = m.uy, uz = m.uz, rho = m.rho;
-    // Maxwellian coefficients of the six third-order polynomials and their u-gradients
     const float A3[6] = {ux * ux * uy + uy * uz * uz, ux * ux * uy - uy * uz * uz,
                          ux * uz * uz + ux * uy * uy, ux * uz * uz - ux * uy * uy,
                          uy * uy * uz + ux * ux * uz, uy * uy * uz - ux * ux * uz};
@@ -738,104 +876,72 @@ __device__ __forceinline__ void adjoint_rr3(const Geo &G, const float g[Q], cons
                              {uz * uz - uy * uy, -2.f * ux * uy, 2.f * ux * uz},
                              {2.f * ux * uz, 2.f * uy * uz, uy * uy + ux * ux},
                              {-2.f * ux * uz, 2.f * uy * uz, uy * uy - ux * ux}};
-    // third-order projections a1 of f1 (odd: per opposite pair)
-    float a1[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    // third-order projections of f1: sum_i P_j(c_i) f_eq3_i = rho A3_j (the
+    // lower orders are orthogonal to P_j), and sum_i P_j(c_i) w_i = 0
+    float a1[6];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const int i = 2 * k + 1;
-        const float cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
-        float t = 0.0f;
+    for (int j = 0; j < 6; ++j) {
+        float s = 0.0f;
 #pragma unroll
-        for (int j = 0; j < 6; ++j)
-            if (herm3(j, i) != 0.0f) t += herm3(j, i) * herm3_inv_norm(j) * A3[j];
-        const float D = ps.d[k] - 2.0f * (3.0f * wgt(i) * rho * cu + wgt(i) * rho * t);
-#pragma unroll
-        for (int j = 0; j < 6; ++j)
-            if (herm3(j, i) != 0.0f) a1[j] += herm3(j, i) * D;
+        for (int k = 0; k < 9; ++k)
+            if (herm3(j, 2 * k + 1) != 0.0f) s += herm3(j, 2 * k + 1) * ps.d[k];
+        a1[j] = s - rho * A3[j];
     }
-    // moments of w mu: order 0, 2 (raw c_a c_b) and the third-order basis
-    float M0 = 0.f, Mxx = 0.f, Myy = 0.f, Mzz = 0.f, Mxy = 0.f, Mxz = 0.f, Myz = 0.f;
-    float b[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const WMoments W = weighted_moments(mu);
+    const float M0 = W.m0;
+    const float trp = W.m2[0] + W.m2[1] + W.m2[2] - M0;     // tr M'
+    const float Mp[6] = {W.m2[0] - M0 * (1.0f / 3.0f), W.m2[1] - M0 * (1.0f / 3.0f), W.m2[2] - M0 * (1.0f / 3.0f),
+                         W.m2[3], W.m2[4], W.m2[5]};
+    // mu . R f1
+    float sR = 4.5f * (Mp[0] * P[0] + Mp[1] * P[1] + Mp[2] * P[2] + 2.0f * (Mp[3] * P[3] + Mp[4] * P[4] + Mp[5] * P[5]));
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const float wm = wgt(i) * mu[i];
-        M0 += wm;
-        if (cx(i)) Mxx += wm;
-        if (cy(i)) Myy += wm;
-        if (cz(i)) Mzz += wm;
-        if (cx(i) && cy(i)) Mxy += cx(i) * cy(i) * wm;
-        if (cx(i) && cz(i)) Mxz += cx(i) * cz(i) * wm;
-        if (cy(i) && cz(i)) Myz += cy(i) * cz(i) * wm;
-#pragma unroll
-        for (int j = 0; j < 6; ++j)
-            if (herm3(j, i) != 0.0f) b[j] += herm3(j, i) * wm;
-    }
-    const float trP = P[0] + P[1] + P[2];
-    float sR = 4.5f * (Mxx * P[0] + Myy * P[1] + Mzz * P[2] + 2.0f * (Mxy * P[3] + Mxz * P[4] + Myz * P[5])) -
-               1.5f * M0 * trP;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) sR += herm3_inv_norm(j) * a1[j] * b[j];
-    // nu = R^T mu (recomputed where needed rather than held), x = mu - keep nu,
-    // and the moments of w x
-    auto nu_of = [&](int i) {
-        const float X_ = (float)cx(i), Y_ = (float)cy(i), Z_ = (float)cz(i);
-        const float cMc = X_ * X_ * Mxx + Y_ * Y_ * Myy + Z_ * Z_ * Mzz +
-                          2.0f * (X_ * Y_ * Mxy + X_ * Z_ * Mxz + Y_ * Z_ * Myz);
-        float n = 4.5f * cMc - 1.5f * (X_ * X_ + Y_ * Y_ + Z_ * Z_) * M0;
-#pragma unroll
-        for (int j = 0; j < 6; ++j)
-            if (herm3(j, i) != 0.0f) n += herm3(j, i) * herm3_inv_norm(j) * b[j];
-        return n;
-    };
-    float m0 = 0.f, m1x = 0.f, m1y = 0.f, m1z = 0.f;
-    float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
-    float X[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const float wx = wgt(i) * (mu[i] - keep * nu_of(i));
-        m0 += wx;
-        if (cx(i)) { m1x += cx(i) * wx; mxx += wx; }
-        if (cy(i)) { m1y += cy(i) * wx; myy += wx; }
-        if (cz(i)) { m1z += cz(i) * wx; mzz += wx; }
-        if (cx(i) && cy(i)) mxy += cx(i) * cy(i) * wx;
-        if (cx(i) && cz(i)) mxz += cx(i) * cz(i) * wx;
-        if (cy(i) && cz(i)) myz += cy(i) * cz(i) * wx;
-#pragma unroll
-        for (int j = 0; j < 6; ++j)
-            if (herm3(j, i) != 0.0f) X[j] += herm3(j, i) * wx;
-    }
+    for (int j = 0; j < 6; ++j) sR += herm3_inv_norm(j) * a1[j] * W.h3[j];
+    // weighted moments of x = mu - keep nu
+    const float m0 = M0 - keep * 1.5f * trp;
+    const float m1x = W.m1[0], m1y = W.m1[1], m1z = W.m1[2];
+    const float mxx = W.m2[0] - keep * (0.5f * trp + Mp[0]);
+    const float myy = W.m2[1] - keep * (0.5f * trp + Mp[1]);
+    const float mzz = W.m2[2] - keep * (0.5f * trp + Mp[2]);
+    const float mxy = W.m2[3] - keep * Mp[3];
+    const float mxz = W.m2[4] - keep * Mp[4];
+    const float myz = W.m2[5] - keep * Mp[5];
     const float usq = ux * ux + uy * uy + uz * uz;
     const float m2ux = mxx * ux + mxy * uy + mxz * uz;
     const float m2uy = mxy * ux + myy * uy + myz * uz;
     const float m2uz = mxz * ux + myz * uy + mzz * uz;
     float srho = m0 * (1.0f - 1.5f * usq) + 3.0f * (m1x * ux + m1y * uy + m1z * uz) +
                  4.5f * (ux * m2ux + uy * m2uy + uz * m2uz);
-    float tx = 3.0f * m1x + 9.0f * m2ux - 3.0f * ux * m0;
-    float ty = 3.0f * m1y + 9.0f * m2uy - 3.0f * uy * m0;
-    float tz = 3.0f * m1z + 9.0f * m2uz - 3.0f * uz * m0;
+    float t[3] = {3.0f * m1x + 9.0f * m2ux - 3.0f * ux * m0, 3.0f * m1y + 9.0f * m2uy - 3.0f * uy * m0,
+                  3.0f * m1z + 9.0f * m2uz - 3.0f * uz * m0};
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-        const float h = herm3_inv_norm(j) * X[j];
+        // third-order moments of w x: (1 - keep) b_j
+        const float h = herm3_inv_norm(j) * om * W.h3[j];
         srho += h * A3[j];
-        tx += h * dA3[j][0];
-        ty += h * dA3[j][1];
-        tz += h * dA3[j][2];
+        t[0] += h * dA3[j][0];
+        t[1] += h * dA3[j][1];
+        t[2] += h * dA3[j][2];
     }
-    // Smagorinsky tau_eff: + (mu.R f1 / tau^2) dtau/df_k
+    // Smagorinsky tau_eff: + (mu.R f1 / tau^2) dtau/df_k = sa (c_k - u)^T P (c_k - u) + sb
     float sa = 0.0f, sb = 0.0f;
     if (qn > 0.0f) {
         const float pre = sR / (tau * tau) * G.kcs / (4.0f * R);
         sa = pre / (rho * qn);
-        sb = -pre * qn / (rho * rho) - sa * trP * (1.0f / 3.0f);
+        sb = -pre * qn / (rho * rho) - sa * (P[0] + P[1] + P[2]) * (1.0f / 3.0f);
     }
     const float src = srcw / rho;
+    const float Pu[3] = {P[0] * ux + P[3] * uy + P[4] * uz, P[3] * ux + P[1] * uy + P[5] * uz,
+                         P[4] * ux + P[5] * uy + P[2] * uz};
+    const float alpha = srho - (ux * t[0] + uy * t[1] + uz * t[2]) + sb - src * ux +
+                        sa * (ux * Pu[0] + uy * Pu[1] + uz * Pu[2]);
+    const float beta[3] = {t[0] - 2.0f * sa * Pu[0] + src, t[1] - 2.0f * sa * Pu[1], t[2] - 2.0f * sa * Pu[2]};
+    const float k45 = 4.5f * keep;
+    const float Gam[6] = {k45 * Mp[0] + sa * P[0], k45 * Mp[1] + sa * P[1], k45 * Mp[2] + sa * P[2],
+                          k45 * Mp[3] + sa * P[3], k45 * Mp[4] + sa * P[4], k45 * Mp[5] + sa * P[5]};
+    float gam[6];
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
-        const float ex = cx(k) - ux, ey = cy(k) - uy, ez = cz(k) - uz;
-        const float quad = ex * (P[0] * ex + P[3] * ey + P[4] * ez) + ey * (P[3] * ex + P[1] * ey + P[5] * ez) +
-                           ez * (P[4] * ex + P[5] * ey + P[2] * ez);
-        lam[k] = srho + ex * tx + ey * ty + ez * tz + keep * nu_of(k) + sa * quad + sb + src * ex;
-    }
+    for (int j = 0; j < 6; ++j) gam[j] = keep * herm3_inv_norm(j) * W.h3[j];
+    eval_poly<true, false>(lam, nullptr, 0.0f, alpha, beta, Gam, gam);
 }
 
 // mu_k = sum of lam^{n+1} over the destination links of direction k, and the
@@ -936,6 +1042,96 @@ __device__ __forceinline__ void adjoint_emit(const Geo &G, const Shape &S, const
     if (inl) inflow_grad(G, z, T, sx, sy, gr0, gr1, gr2);
 }
 
+// The transposed links of a class-1 wavefront (see gather_x / scatter_x):
+// mu_K sums lam^{n+1} over the destinations of the post-collision value K,
+// the plain one except at the x faces (x = 0, c_x = -1: own slot opp(K),
+// with the moving-wall gradient at an inlet; x = nx-1, c_x = +1: none at an
+// outlet, own slot opp(K) at a wall; x = nx-1, c_x = -1 at an outlet: plus
+// slot K of (nx-1, y + c_y, z + c_z)).
+template <int... Ks>
+__device__ __forceinline__ void adjoint_gather_x(const Geo &G, const Shape &S, bool xlo, bool xhi, uint32_t c, int z,
+                                                 const InflowT &T, const GLOBAL_AS float *__restrict__ lin,
+                                                 float mu[Q], double &gr0, double &gr1, double &gr2,
+                                                 std::integer_sequence<int, Ks...>)
+{
+    const uint32_t qs = (uint32_t)G.qs;
+    const uint32_t last = (uint32_t)G.ncells - 1u;
+    const bool inl = S.face[0] == FACE_INLET, out = S.face[1] == FACE_OUTLET;
+    double sx = 0.0, sy = 0.0;
+    (
+        [&] {
+            constexpr int K = Ks;
+            const uint32_t pn = umin_u32((uint32_t)((int32_t)c + off_of(G, K)), last);
+            if constexpr (cx(K) == -1) {
+                float v = ldg(lin, xlo ? (uint32_t)opp(K) * qs + c : (uint32_t)K * qs + pn);
+                if (xlo && inl) {
+                    constexpr int q = opp(K);
+                    const double f6 = 6.0 * (double)wgt(q) * (double)v;
+                    sx += (double)cx(q) * f6;
+                    sy += (double)cy(q) * f6;
+                }
+                if (xhi && out)
+                    v += ldg(lin, (uint32_t)K * qs +
+                                      umin_u32((uint32_t)((int32_t)c + cy(K) * G.offy + cz(K) * G.offz), last));
+                mu[K] = v;
+            } else if constexpr (cx(K) == 1) {
+                const float v = ldg(lin, xhi ? (uint32_t)opp(K) * qs + c : (uint32_t)K * qs + pn);
+                mu[K] = (xhi && out) ? 0.0f : v;
+            } else {
+                mu[K] = ldg(lin, (uint32_t)K * qs + pn);
+            }
+        }(),
+        ...);
+    if (xlo && inl) inflow_grad(G, z, T, sx, sy, gr0, gr1, gr2);
+}
+
+// In-place adjoint of the odd step in a class-1 wavefront (see
+// adjoint_emit): lam of the gathered population I goes to the slot the
+// forward step gathered it from, the plain one except at the x faces
+// (x = 0, c_x = +1: own slot I, with the moving-wall gradient at an inlet;
+// x = nx-1, c_x = -1: own slot I at a wall; at an outlet the slot is the one
+// the upstream neighbour, one lane down, gathers from too: the value goes to
+// that lane, which adds it before it stores, and the outflow column's extra
+// destination, slot I of (nx-1, y + c_y, z + c_z), is zeroed).
+template <class F, int... Is>
+__device__ __forceinline__ void adjoint_emit_x(const Geo &G, const Shape &S, bool xlo, bool xhi, bool owner,
+                                               bool wave_out, uint32_t c, int z, const InflowT &T,
+                                               GLOBAL_AS float *lam, F lk_of, double &gr0, double &gr1, double &gr2,
+                                               std::integer_sequence<int, Is...>)
+{
+    const uint32_t qs = (uint32_t)G.qs;
+    const bool inl = S.face[0] == FACE_INLET, out = S.face[1] == FACE_OUTLET;
+    double sx = 0.0, sy = 0.0;
+    (
+        [&] {
+            constexpr int I = Is;
+            float v = lk_of(I);
+            const uint32_t pn = (uint32_t)opp(I) * qs + (uint32_t)((int32_t)c - off_of(G, I));
+            if constexpr (cx(I) == 1) {
+                stg(lam, xlo ? (uint32_t)I * qs + c : pn, v);
+                if (xlo && inl) {
+                    const double f6 = 6.0 * (double)wgt(I) * (double)v;
+                    sx += (double)cx(I) * f6;
+                    sy += (double)cy(I) * f6;
+                }
+            } else if constexpr (cx(I) == -1) {
+                const bool shared = xhi && out;
+                if (wave_out) {
+                    const float recv = __shfl_down(shared ? v : 0.0f, 1, 64);
+                    if (owner) v += recv;
+                }
+                if (!shared)
+                    stg(lam, xhi ? (uint32_t)I * qs + c : pn, v);
+                else
+                    stg(lam, (uint32_t)I * qs + (uint32_t)((int32_t)c + cy(I) * G.offy + cz(I) * G.offz), 0.0f);
+            } else {
+                stg(lam, pn, v);
+            }
+        }(),
+        ...);
+    if (xlo && inl) inflow_grad(G, z, T, sx, sy, gr0, gr1, gr2);
+}
+
 // One adjoint step of every instance, with the tiling of the step kernels:
 // a workgroup of BS threads owns BS * CPT consecutive cells of one instance.
 // Gather: per wavefront class the plain shifted pattern, the transposed x
@@ -1007,12 +1203,11 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
         } else if (cls[j] == 1) {
             int x, y, z;
             coords(G, c[j], x, y, z);
-            const Preds px{x == 0, x == S.nx - 1, false, false, false, false, false};
-            const bool inl = act[j] && px.xlo && S.face[0] == FACE_INLET;
+            const bool inl = act[j] && x == 0 && S.face[0] == FACE_INLET;
             const InflowT Tx = __any(inl) ? inflow_at(G, a.step) : InflowT{0.f, 0.f, 0.f, 0.f};
             if (act[j])
-                adjoint_gather<true>(G, S, px, 0u, c[j], z, Tx, MODE == 0 ? lin : lbuf, mu[j], sg[j][0], sg[j][1],
-                                     sg[j][2], Dirs{});
+                adjoint_gather_x(G, S, x == 0, x == S.nx - 1, c[j], z, Tx, MODE == 0 ? lin : lbuf, mu[j], sg[j][0],
+                                 sg[j][1], sg[j][2], Dirs{});
         }
         fl[j] = act[j] ? gp(G.flags)[c[j]] : (uint8_t)FL_SOLID;
         smv[j] = (cls[j] >= 2 && act[j]) ? gp(G.smask)[c[j]] : 0u;
@@ -1095,10 +1290,14 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
                 const int p = probe_index(G, (int32_t)c[j]);
                 if (p >= 0) srcw = (float)(a.pw[ii][p] * a.inv_count);
             }
-            adjoint_rr3(G, gs[j], mu[j], srcw, lam);
+            adjoint_rr3_moments(G, gs[j], mu[j], srcw, lam);
             if constexpr (MODE == 1) {
-                adjoint_emit(G, S, pg[j], smv[j], c[j], zg[j], Tg, lbuf, cls[j] == 0, wout[j], outflow[j], owner[j],
-                             [&](int k) { return lam[k]; }, gr0, gr1, gr2, Dirs{});
+                if (cls[j] == 1)
+                    adjoint_emit_x(G, S, pg[j].xlo, pg[j].xhi, owner[j], wout[j], c[j], zg[j], Tg, lbuf,
+                                   [&](int k) { return lam[k]; }, gr0, gr1, gr2, Dirs{});
+                else
+                    adjoint_emit(G, S, pg[j], smv[j], c[j], zg[j], Tg, lbuf, cls[j] == 0, wout[j], outflow[j],
+                                 owner[j], [&](int k) { return lam[k]; }, gr0, gr1, gr2, Dirs{});
             } else {
 #pragma unroll
                 for (int k = 0; k < Q; ++k) stg((MODE == 0 ? lout : lbuf) + (size_t)k * qs, c[j], lam[k]);
@@ -1132,20 +1331,11 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
             }
             om = 1.0f / tau;
         }
-        // BGK part: (1 - om) mu_k + om [s_rho + (c_k - u) . t]
-        float m0 = 0.f, m1x = 0.f, m1y = 0.f, m1z = 0.f;
-        float mxx = 0.f, myy = 0.f, mzz = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const float wm = wgt(i) * mu[j][i];
-            m0 += wm;
-            if (cx(i)) { m1x += cx(i) * wm; mxx += wm; }
-            if (cy(i)) { m1y += cy(i) * wm; myy += wm; }
-            if (cz(i)) { m1z += cz(i) * wm; mzz += wm; }
-            if (cx(i) && cy(i)) mxy += cx(i) * cy(i) * wm;
-            if (cx(i) && cz(i)) mxz += cx(i) * cz(i) * wm;
-            if (cy(i) && cz(i)) myz += cy(i) * cz(i) * wm;
-        }
+        // BGK part: (1 - om) mu_k + om [s_rho + (c_k - u) . t], from the
+        // weighted moments of mu
+        const WMoments W = weighted_moments(mu[j]);
+        const float m0 = W.m0, m1x = W.m1[0], m1y = W.m1[1], m1z = W.m1[2];
+        const float mxx = W.m2[0], myy = W.m2[1], mzz = W.m2[2], mxy = W.m2[3], mxz = W.m2[4], myz = W.m2[5];
         const float usq = ux * ux + uy * uy + uz * uz;
         const float m2ux = mxx * ux + mxy * uy + mxz * uz;
         const float m2uy = mxy * ux + myy * uy + myz * uz;
@@ -1155,7 +1345,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
         const float tx = 3.0f * m1x + 9.0f * m2ux - 3.0f * ux * m0;
         const float ty = 3.0f * m1y + 9.0f * m2uy - 3.0f * uy * m0;
         const float tz = 3.0f * m1z + 9.0f * m2uz - 3.0f * uz * m0;
-        // Smagorinsky: + (A / tau^2) dtau/df_k
+        // Smagorinsky: + (A / tau^2) dtau/df_k = sa (c_k - u)^T P (c_k - u) + sb
         float sa = 0.0f, sb = 0.0f;
         if (MODEL == 1 && qn > 0.0f) {
             const float R = sqrtf(G.tau0 * G.tau0 + G.kcs * qn / rho);
@@ -1169,20 +1359,23 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
             const int p = probe_index(G, (int32_t)c[j]);
             if (p >= 0) src = (float)(a.pw[ii][p] * a.inv_count) / rho;
         }
-        auto lk_of = [&](int k) {
-            const float ex = cx(k) - ux, ey = cy(k) - uy, ez = cz(k) - uz;
-            float lk = (1.0f - om) * mu[j][k] + om * (srho + ex * tx + ey * ty + ez * tz);
-            if (MODEL == 1) {
-                const float quad = ex * (P[0] * ex + P[3] * ey + P[4] * ez) +
-                                   ey * (P[3] * ex + P[1] * ey + P[5] * ez) +
-                                   ez * (P[4] * ex + P[5] * ey + P[2] * ez);
-                lk += sa * quad + sb;
-            }
-            return lk + src * ex;
-        };
+        // lambda_k = (1 - om) mu_k + alpha + beta . c_k + c_k^T (sa P) c_k
+        const float Pu[3] = {P[0] * ux + P[3] * uy + P[4] * uz, P[3] * ux + P[1] * uy + P[5] * uz,
+                             P[4] * ux + P[5] * uy + P[2] * uz};
+        const float alpha = om * (srho - (ux * tx + uy * ty + uz * tz)) + sb - src * ux +
+                            sa * (ux * Pu[0] + uy * Pu[1] + uz * Pu[2]);
+        const float beta[3] = {om * tx - 2.0f * sa * Pu[0] + src, om * ty - 2.0f * sa * Pu[1],
+                               om * tz - 2.0f * sa * Pu[2]};
+        const float Gam[6] = {sa * P[0], sa * P[1], sa * P[2], sa * P[3], sa * P[4], sa * P[5]};
+        eval_poly<false, true>(mu[j], mu[j], 1.0f - om, alpha, beta, Gam, nullptr);
+        auto lk_of = [&](int k) { return mu[j][k]; };
         if constexpr (MODE == 1) {
-            adjoint_emit(G, S, pg[j], smv[j], c[j], zg[j], Tg, lbuf, cls[j] == 0, wout[j], outflow[j], owner[j],
-                         lk_of, gr0, gr1, gr2, Dirs{});
+            if (cls[j] == 1)
+                adjoint_emit_x(G, S, pg[j].xlo, pg[j].xhi, owner[j], wout[j], c[j], zg[j], Tg, lbuf, lk_of, gr0, gr1,
+                               gr2, Dirs{});
+            else
+                adjoint_emit(G, S, pg[j], smv[j], c[j], zg[j], Tg, lbuf, cls[j] == 0, wout[j], outflow[j], owner[j],
+                             lk_of, gr0, gr1, gr2, Dirs{});
         } else {
 #pragma unroll
             for (int k = 0; k < Q; ++k) stg((MODE == 0 ? lout : lbuf) + (size_t)k * qs, c[j], lk_of(k));

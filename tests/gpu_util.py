@@ -20,6 +20,17 @@ def per_channel_rel(gpu_c4, ora_4c, fluid):
     return [rel_l2(g[k], ora_4c[k], fluid) for k in range(4)]
 
 
+def per_channel_maxrel(gpu_c4, ora_4c, fluid):
+    """Element-wise maximum error of each channel relative to the channel's
+    largest oracle value (a localised error cannot hide in the L2 norm)."""
+    g = np.asarray(gpu_c4, np.float64).T
+    out = []
+    for k in range(4):
+        a, b = g[k][fluid], np.asarray(ora_4c[k], np.float64)[fluid]
+        out.append(float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)))
+    return out
+
+
 def oracle_case(w, solid, theta, **over):
     kw = dict(model=w.model, tau0=w.tau0, cs=w.cs, inflow=w.inflow, theta=theta, ramp=w.ramp,
               series=w.series, hour_steps=w.hour_steps, blend_steps=w.blend_steps, ref_height=w.ref_height)

@@ -18,7 +18,7 @@ from oracle import oracle as orc
 from paper_2508_18202_amd import inputs
 from paper_2508_18202_amd import lbmsc as L
 from paper_2508_18202_amd import sc
-from gpu_util import oracle_case, per_channel_rel, rel_l2
+from gpu_util import oracle_case, per_channel_maxrel, per_channel_rel, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -219,8 +219,10 @@ def test_full_size_cylinder_first_steps():
             res = orc.run(case, 12)
             u = ens.fields(k).cpu().numpy()
             errs = per_channel_rel(u, res["final"], fluid)
-            assert max(errs[:2] + errs[3:]) < FIELD_TOL, (j, errs)
-            assert errs[2] < 10 * FIELD_TOL, (j, errs)     # u_z is small this early
+            mx = per_channel_maxrel(u, res["final"], fluid)
+            _say(f"full-size cylinder node {j}: rel L2 {['%.2e' % e for e in errs]}, max {['%.2e' % e for e in mx]}")
+            assert max(errs) < FIELD_TOL, (j, errs)
+            assert max(mx) < 1e-4, (j, mx)
         assert ens.health() == -1
     finally:
         ens.close()

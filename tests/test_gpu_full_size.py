@@ -1,10 +1,14 @@
-"""GPU parity at the full sizes of the batched-uneven and data-assimilation
-workloads, on sampled instances the FP64 oracle can step one by one.
+"""GPU parity at the full sizes of the bench's workloads, on sampled
+instances the FP64 oracle can step one by one.
 
-Both start from rest with the full inflow from step 0 (no ramp), so that the
-first steps already carry the boundary rules; the fields of the sampled
-instances are compared per velocity channel (relative L2 over fluid cells
-<= 1e-5; u_z, still small this early, <= 1e-4).
+The fields of the sampled instances are compared per channel (u_x, u_y, u_z,
+|u|): relative L2 over fluid cells <= 1e-5, and the element-wise maximum
+error <= 1e-4 of the channel's largest value.  Runs start from rest either
+with the full inflow from step 0 (so that the first steps already carry every
+boundary rule) or with the workload's own 1000-step ramp; a ramped start is
+compared from 60 (assimilation box) or 200 steps on, since before that u_y is
+only a few 1e-5 of the inflow speed and its FP32 rounding exceeds 1e-5 of its
+norm.
 """
 import sys
 
@@ -15,10 +19,11 @@ torch = pytest.importorskip("torch")
 
 from oracle import oracle as orc
 from paper_2508_18202_amd import inputs, sc
-from gpu_util import oracle_case, per_channel_rel
+from gpu_util import oracle_case, per_channel_maxrel, per_channel_rel
 
 pytestmark = pytest.mark.gpu
 FIELD_TOL = 1e-5
+MAX_TOL = 1e-4
 
 
 def _say(msg):
@@ -38,9 +43,12 @@ def _check(ens, i, w0, solid, theta, steps, label):
     _say(f"{label}: oracle instance {i}")
     res = orc.run(oracle_case(w0, solid, theta), steps)
     u = ens.fields(i).cpu().numpy()
-    errs = per_channel_rel(u, res["final"], solid.reshape(-1) == 0)
-    assert max(errs[:2] + errs[3:]) < FIELD_TOL, (label, i, errs)
-    assert errs[2] < 10 * FIELD_TOL, (label, i, errs)
+    fluid = solid.reshape(-1) == 0
+    errs = per_channel_rel(u, res["final"], fluid)
+    mx = per_channel_maxrel(u, res["final"], fluid)
+    _say(f"{label} instance {i}: rel L2 {['%.2e' % e for e in errs]}, max {['%.2e' % e for e in mx]}")
+    assert max(errs) < FIELD_TOL, (label, i, errs)
+    assert max(mx) < MAX_TOL, (label, i, mx)
 
 
 def test_full_size_uneven_batch_first_steps():
@@ -123,15 +131,15 @@ def test_full_size_regularised_urban_first_steps():
 
 def test_full_size_series_urban_through_an_hour_change():
     """The series-inflow leg of the bench in its launch configuration (13
-    nodes of 256x128x64, hourly series), with hours of 100 steps and blends
-    of 40 and no ramp, so that 160 steps run through the first change of the
+    nodes of 256x128x64, hourly series), with hours of 50 steps and blends
+    of 30 and no ramp, so that 100 steps run through the first change of the
     hourly wind; the first and last node against the oracle.  (After an
-    impulsive start the FP32 fields drift from the FP64 ones by about 4e-8
-    per step on u_y at this size, with or without the series, so the
-    horizon stays well under 250 steps.)"""
-    w = inputs.urban_series(hours=4, hour_steps=100, blend_steps=40)
+    impulsive start the FP32 fields drift from the FP64 ones almost linearly
+    in the step count, about 6e-8 per step on u_z with the series: 1.0e-5 of
+    its norm after 160 steps, so the horizon stays at 100.)"""
+    w = inputs.urban_series(hours=4, hour_steps=50, blend_steps=30)
     solid = inputs.solid_mask(w)
-    _full_size_nodes(inputs.scaled(w, w.nx, w.ny, w.nz, ramp=0), solid, (0, 12), 160, "series urban")
+    _full_size_nodes(inputs.scaled(w, w.nx, w.ny, w.nz, ramp=0), solid, (0, 12), 100, "series urban")
 
 
 def test_full_size_gauss_hermite_first_steps():
@@ -142,3 +150,43 @@ def test_full_size_gauss_hermite_first_steps():
                       ref_height=48.0)
     solid = inputs.solid_mask(w)
     _full_size_nodes(w, solid, (0, 60, 120), 24, "Gauss-Hermite urban")
+
+
+def test_full_size_assimilation_real_ramp():
+    """The data-assimilation scale with its own 1000-step inflow ramp: 60
+    steps of all 13 nodes, the fastest node against the oracle."""
+    steps = 60
+    w = inputs.assimilation_case()
+    solid = inputs.solid_mask(w)
+    x, a, th = sc.collocation(w)
+    cg = sc.make_geometry(w, solid)
+    ens = sc.Ensemble([cg], [th], use_graph=True, variant=(128, 1, 1, 1))
+    try:
+        _say("full-size assimilation, ramped: GPU 60 steps")
+        ens.advance(steps)
+        assert ens.health() == -1
+        xo, _ = orc.collocation(w)
+        _check(ens, 12, w, solid, orc.node_params(w, xo[12]), steps, "assimilation ramped node 12")
+    finally:
+        ens.close()
+
+
+def test_full_size_urban_real_ramp():
+    """The headline configuration as the bench runs it (13 nodes of the
+    256x128x64 urban box, graph replay, its 1000-step ramp): 200 steps, the
+    fastest and slowest nodes against the oracle."""
+    steps = 200
+    w = inputs.urban_les()
+    solid = inputs.solid_mask(w)
+    x, a, th = sc.collocation(w)
+    cg = sc.make_geometry(w, solid)
+    ens = sc.Ensemble([cg], [th], use_graph=True, variant=(128, 1, 1, 1))
+    try:
+        _say("full-size urban, ramped: GPU 200 steps")
+        ens.advance(steps)
+        assert ens.health() == -1
+        xo, _ = orc.collocation(w)
+        for j in (int(np.argmax(th[:, 0])), int(np.argmin(th[:, 0]))):
+            _check(ens, j, w, solid, orc.node_params(w, xo[j]), steps, f"urban ramped node {j}")
+    finally:
+        ens.close()
