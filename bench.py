@@ -38,6 +38,72 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_2508_18202_amd", *p) for p in
                 ("csrc", "d3q19.h"), ("build.py",))]
 
 
+def summarize_traffic(fetch_csv: str, write_csv: str, first: int, count: int) -> dict:
+    """HBM bytes per collide-and-stream launch of the headline workload from
+    two rocprofv3 --pmc runs of `bench.py ... --profile-calib` (FETCH_SIZE,
+    then WRITE_SIZE; KiB per dispatch; the runs' results.db or counter CSV
+    files): the step dispatches of the
+    Smagorinsky model in dispatch order are the time steps of the headline
+    pass (one dispatch per step), the medians over steps first ..
+    first+count-1 per parity are scaled by what each counter reads for the
+    1 GiB calibration copy at the end of the run."""
+    import csv
+    import re
+    import statistics
+
+    def load(path, counter):
+        rows = {}
+        if path.endswith(".db"):                  # rocprofv3's default (rocpd SQLite) output
+            import sqlite3
+            con = sqlite3.connect(path)
+            q = "select dispatch_id, kernel_name, value from counters_collection where counter_name = ?"
+            for d, name, v in con.execute(q, (counter,)):
+                rows[int(d)] = (name, float(v))
+            con.close()
+        else:                                     # --output-format csv
+            with open(path) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Counter_Name"] == counter:
+                        rows[int(r["Dispatch_Id"])] = (r["Kernel_Name"], float(r["Counter_Value"]))
+        return [rows[k] for k in sorted(rows)]
+
+    def steps_of(seq):
+        out = []
+        for name, v in seq:
+            m = re.search(r"k_step<(\d+), (\d+), (true|false), (\d+), (\d+)>", name)
+            if m and m.group(4) == "1":
+                out.append((int(m.group(5)), v, {"block": int(m.group(1)), "cells_per_thread": int(m.group(2))}))
+        return out
+
+    res = {}
+    for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        seq = load(path, counter)
+        copies = [v for name, v in seq if "copyBuffer" in name]
+        factor = (1 << 20) / copies[-1]           # the 1 GiB calibration copy, in KiB
+        all_steps = steps_of(seq)
+        if len(all_steps) < first + count:
+            raise SystemExit(f"{path}: {len(all_steps)} step dispatches, fewer than {first + count}")
+        st = all_steps[first:first + count]
+        res[key] = {par: statistics.median(v for p_, v, _ in st if p_ == par) * 1024 * factor for par in (0, 1)}
+        res[key + "_factor"] = round(factor, 3)
+        res[key + "_copy_kib"] = copies[-1]
+        res["launch"] = st[0][2]
+    hbm = 0.5 * (res["fetch"][0] + res["write"][0] + res["fetch"][1] + res["write"][1])
+    return {"kernel_sha": kernel_sha(), "hbm_bytes_per_launch": int(round(hbm)),
+            "fetch_factor": res["fetch_factor"], "write_factor": res["write_factor"],
+            "calibration_copy_kib": {"fetch": res["fetch_copy_kib"], "write": res["write_copy_kib"]},
+            "per_parity_bytes": {"even": [int(res["fetch"][0]), int(res["write"][0])],
+                                 "odd": [int(res["fetch"][1]), int(res["write"][1])]},
+            "steps": [first, first + count - 1], "launch_partial": res["launch"],
+            "summary": "collide_stream_urban_les_hbm_traffic.md"}
+
+
+def progress(msg: str):
+    """One line per finished pass, leg or run on stderr (the JSON line alone
+    goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +131,14 @@ def parse():
                          "gradient-descent iterations (about 100 s each; 0 = skip)")
     ap.add_argument("--only-assimilation", action="store_true",
                     help="skip the headline pass and every other leg (with --assimilation-iters)")
+    ap.add_argument("--no-small", action="store_true", help="skip the small block-case leg")
+    ap.add_argument("--ramp", type=int, default=None,
+                    help="inflow ramp length of the headline pass (profiling runs; default: the workload's 1000)")
+    ap.add_argument("--box", type=int, nargs=3, metavar=("NX", "NY", "NZ"), help=argparse.SUPPRESS)
+    ap.add_argument("--faces", nargs=6, help=argparse.SUPPRESS)
+    ap.add_argument("--no-buildings", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic summary of two rocprofv3 counter runs and exit (no GPU)")
     ap.add_argument("--profile-calib", action="store_true",
                     help="also run a plain copy of known size (HBM counter calibration)")
     return ap.parse_args()
@@ -630,6 +704,7 @@ def assimilation_leg(iters: int):
             r = run_f()
             torch.cuda.synchronize()
             fwd.append(time.perf_counter() - t)
+            progress(f"assimilation forward run {len(fwd)}: {fwd[-1]:.1f} s")
             return r
 
         def timed_backward(pw):
@@ -637,6 +712,7 @@ def assimilation_leg(iters: int):
             r = run_b(pw)
             torch.cuda.synchronize()
             bwd.append(time.perf_counter() - t)
+            progress(f"assimilation reverse sweep {len(bwd)}: {bwd[-1]:.1f} s")
             return r
 
         da.runner.forward, da.runner.backward = timed_forward, timed_backward
@@ -667,6 +743,22 @@ def assimilation_leg(iters: int):
 
 def main():
     args = parse()
+    if args.summarize_traffic:
+        # the plain stretch of the headline pass the counter runs took,
+        # from the same flags: steps after the ramp, before the QoI window
+        ramp = 1000 if args.ramp is None else args.ramp
+        first = ramp + 16
+        count = (args.lbm_steps - min(args.avg_len, args.lbm_steps)) - 16 - first
+        t = summarize_traffic(*args.summarize_traffic, first=first, count=count - count % 2)
+        t["algorithmic_bytes_per_launch"] = BYTES_PER_CELL_UPDATE * 13 * 1942272
+        # the launch shape the counter runs were given
+        t["launch"] = {"block": args.block, "cells_per_thread": args.cells_per_thread,
+                       "nontemporal": args.nontemporal, "xcd_order": args.xcd_order}
+        assert (t["launch"]["block"], t["launch"]["cells_per_thread"]) == \
+            (t["launch_partial"]["block"], t["launch_partial"]["cells_per_thread"]), "launch shape mismatch"
+        del t["launch_partial"]
+        print(json.dumps(t, indent=1))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path "
@@ -687,7 +779,14 @@ def main():
     w = inputs.urban_les(steps=lbm_steps, avg_len=min(args.avg_len, lbm_steps))
     if args.model != w.model:        # experiments only: the workload is Smagorinsky
         w = inputs.scaled(w, w.nx, w.ny, w.nz, model=args.model, tau0=0.6, cs=0.0)
-    solid = inputs.solid_mask(w)
+    if args.ramp is not None:        # profiling runs: a short ramp before the plain stretch
+        w = inputs.scaled(w, w.nx, w.ny, w.nz, ramp=args.ramp)
+    # experiments only (traffic studies): another box, other faces, no buildings
+    if args.box:
+        w = inputs.scaled(w, *args.box)
+    if args.faces:
+        w = inputs.scaled(w, w.nx, w.ny, w.nz, faces=tuple(args.faces))
+    solid = np.zeros((w.nz, w.ny, w.nx), np.uint8) if args.no_buildings else inputs.solid_mask(w)
     n_fluid = int((solid == 0).sum())
     ramp = min(w.ramp, w.avg_start)
     plain = max(0, w.avg_start - ramp)
@@ -742,13 +841,15 @@ def main():
         finally:
             ens.close()
 
-    for _ in range(args.warmup):
+    for k in range(args.warmup):
         sc_pass([])
+        progress(f"warm-up pass {k + 1}/{args.warmup}")
     torch.cuda.synchronize()
     timing = []
     t0 = time.perf_counter()
     for k in range(args.steps):
         mean, var, n_inst = sc_pass(timing, check=(k == args.steps - 1))
+        progress(f"timed pass {k + 1}/{args.steps}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -814,7 +915,9 @@ def main():
         r = fn(*a, **kw)
         r["wall_s"] = round(time.perf_counter() - t0, 1)
         out[name] = r
-    leg("small_block", small_block_leg)
+        progress(f"{name}: {r['wall_s']} s")
+    if not args.no_small:
+        leg("small_block", small_block_leg)
     if not args.no_rr3:
         leg("regularised_collision", rr3_leg, variant)
         leg("series_inflow", series_leg, variant)

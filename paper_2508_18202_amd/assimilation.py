@@ -13,7 +13,8 @@ perturbed by 5 % relative Gaussian noise.  The loss is
 
 with E, S from Eq. (quad_moments) over the nodes.  Its gradient chains the
 per-node probe adjoint (ProbeQoI) through the quadrature sums and the
-parameter map; steps use gradient descent with Armijo backtracking.
+parameter map; steps use gradient descent with Armijo backtracking, each
+first trial capped at the step where the loss's linearisation vanishes.
 """
 from __future__ import annotations
 
@@ -102,6 +103,10 @@ class Assimilation:
                              "grad": [0.0, 0.0], "step": step, "accepted": False, "trials": 0,
                              "wall_s": round(time.perf_counter() - t0, 2)})
                 break
+            # the loss is a sum of squares (never below zero): along -g its
+            # linearisation reaches zero at the step L / |g|^2, a step no
+            # trial exceeds, whatever the scale of the observations
+            step = min(step, lval / gn2)
             accepted = False
             trials = 0
             for _ in range(max_backtrack):

@@ -682,16 +682,16 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
         const Macro m = macro_of(g[j], ps);
         if (!(m.rho > 0.0f) || !isfinite(m.rho)) atomicOr(health + ii, 1);
         if (a.accumulate) accumulate_qoi(G, c[j], fl[j], m);
+        // records are read once, in reverse order, a whole segment later:
+        // streaming stores keep them from displacing the populations in the
+        // caches (the adjoint reads them with streaming loads)
         if (a.record == 1) {
-            GLOBAL_AS float *r = gp(a.rec[ii]) + 4 * ((size_t)a.rec_slot * (size_t)G.ncells + c[j]);
-            r[0] = m.rho;
-            r[1] = m.ux;
-            r[2] = m.uy;
-            r[3] = m.uz;
+            GLOBAL_AS f32x4 *r = (GLOBAL_AS f32x4 *)gp(a.rec[ii]) + ((size_t)a.rec_slot * (size_t)G.ncells + c[j]);
+            __builtin_nontemporal_store(f32x4{m.rho, m.ux, m.uy, m.uz}, r);
         } else if (a.record == 2) {
             GLOBAL_AS float *r = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)Q * G.qs;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) stg(r + (size_t)i * qs, c[j], g[j][i]);
+            for (int i = 0; i < Q; ++i) stg<true>(r + (size_t)i * qs, c[j], g[j][i]);
         }
         collide<MODEL>(G, g[j], m, ps);
     }
@@ -1212,7 +1212,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
         fl[j] = act[j] ? gp(G.flags)[c[j]] : (uint8_t)FL_SOLID;
         smv[j] = (cls[j] >= 2 && act[j]) ? gp(G.smask)[c[j]] : 0u;
         if (a.record == 1 && act[j])
-            st[j] = ((const GLOBAL_AS f32x4 *)gp(a.rec[ii]))[(size_t)a.rec_slot * (size_t)G.ncells + c[j]];
+            st[j] = __builtin_nontemporal_load((const GLOBAL_AS f32x4 *)gp(a.rec[ii]) + ((size_t)a.rec_slot * (size_t)G.ncells + c[j]));
     }
     bool flow2 = false;
 #pragma unroll
@@ -1245,7 +1245,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
         if (a.record != 1) {
             const GLOBAL_AS float *rp = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)Q * G.qs;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) gs[j][i] = ldg(rp + (size_t)i * qs, c[j]);
+            for (int i = 0; i < Q; ++i) gs[j][i] = ldg<true>(rp, (uint32_t)i * qs + c[j]);
         }
     }
     // MODE 1: the rules of each cell's stores (see adjoint_emit)

@@ -4,6 +4,11 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# pytest-xdist workers share the cores: keep the oracle's OpenMP team small
+# in each of them (set before the oracle library starts its runtime)
+if "PYTEST_XDIST_WORKER" in os.environ:
+    os.environ.setdefault("OMP_NUM_THREADS", "2")
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 

@@ -216,3 +216,23 @@ def test_full_size_adjoint_first_steps(model, nodes, inplace):
     for k in range(3):
         err = np.abs(g[sel, k] - go[:, k]).max() / np.abs(go[:, k]).max()
         assert err < GRAD_TOL, (model, k, err, g[sel, k], go[:, k])
+
+
+@pytest.mark.parametrize("model", ["bgk", "smagorinsky", "rr3"])
+def test_lambda_buffer_count_follows_the_layout(model):
+    """Two lambda buffers per instance by default, one with inplace=True, for
+    every collision model (the in-place layout exists to halve that memory)."""
+    w = inputs.scaled(inputs.adjoint_case(steps=20, avg_len=10), 24, 12, 10, model=model, cs=0.1)
+    solid = inputs.solid_mask(w)
+    probes = _plane_probes(w, solid)
+    cg = sc.make_geometry(w, solid, probes)
+    x, a, th = sc.collocation(w)
+    ens = sc.Ensemble([cg], [th[:2]], avg_begin=w.avg_start, avg_end=w.steps, fields=False, use_graph=False)
+    try:
+        for inplace, n_buf in ((None, 2), (False, 2), (True, 1)):
+            kw = {} if inplace is None else {"inplace": inplace}
+            run = CheckpointedAdjoint(ens, w.steps, 10, **kw)
+            assert [len(b) for b in run.lam] == ([2, 2] if n_buf == 2 else [2, 0]), (inplace, run.lam)
+            run.close()
+    finally:
+        ens.close()
