@@ -1304,15 +1304,14 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
             }
             continue;
         }
-        // state of step n
-        float rho, ux, uy, uz, om;
-        float A = 0.0f, P[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, qn = 0.0f, tau = G.tau0;
+        // state of step n (the relaxation rate as the forward step forms it)
+        float rho, ux, uy, uz;
+        float muf = 0.0f, P[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, qn = 0.0f, tau = G.tau0;
         if (a.record == 1) {
             rho = st[j].x;
             ux = st[j].y;
             uy = st[j].z;
             uz = st[j].w;
-            om = 1.0f / G.tau0;
         } else {
             const float *g = gs[j];
             const PairSums ps = pair_sums(g);
@@ -1325,12 +1324,11 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
                 neq_stress(ps, m, P);
                 qn = stress_norm(P);
                 tau = tau_of<1>(G, ps, m);
-                const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
 #pragma unroll
-                for (int i = 0; i < Q; ++i) A += mu[j][i] * (g[i] - geq(i, m, usq15));
+                for (int i = 0; i < Q; ++i) muf += mu[j][i] * g[i];
             }
-            om = 1.0f / tau;
         }
+        const float om = fast_rcp(tau);
         // BGK part: (1 - om) mu_k + om [s_rho + (c_k - u) . t], from the
         // weighted moments of mu
         const WMoments W = weighted_moments(mu[j]);
@@ -1346,12 +1344,17 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
         const float ty = 3.0f * m1y + 9.0f * m2uy - 3.0f * uy * m0;
         const float tz = 3.0f * m1z + 9.0f * m2uz - 3.0f * uz * m0;
         // Smagorinsky: + (A / tau^2) dtau/df_k = sa (c_k - u)^T P (c_k - u) + sb
+        // with A = mu . (f - f_eq) = mu . f - mu . f_eq, where (f - w and f_eq
+        // - w stored) mu . f_eq = rho s_rho - m0 comes from the same weighted
+        // moments, and R = 2 tau - tau0 the root of tau_eff
         float sa = 0.0f, sb = 0.0f;
         if (MODEL == 1 && qn > 0.0f) {
-            const float R = sqrtf(G.tau0 * G.tau0 + G.kcs * qn / rho);
-            const float pre = A / (tau * tau) * G.kcs / (4.0f * R);
-            sa = pre / (rho * qn);
-            sb = -pre * qn / (rho * rho) - sa * (P[0] + P[1] + P[2]) * (1.0f / 3.0f);
+            const float A = muf - (rho * srho - m0);
+            const float R = 2.0f * tau - G.tau0;
+            const float pre = A * G.kcs * fast_rcp(4.0f * tau * tau * R);
+            const float irho = fast_rcp(rho);
+            sa = pre * irho * fast_rcp(qn);
+            sb = -pre * qn * irho * irho - sa * (P[0] + P[1] + P[2]) * (1.0f / 3.0f);
         }
         // objective source at the probes: pw_p / count * (c_kx - u_x) / rho
         float src = 0.0f;
