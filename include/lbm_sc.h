@@ -246,8 +246,13 @@ int lbm_collide_stream(lbm_plan *plan, int32_t n_steps, hipStream_t stream);
 /* Same, and also record the state of every step n for the adjoint sweep
  * (recording runs do not add to the QoI sums):
  * record_kind 1 saves (rho, u) as [slot][ncells][4] floats (BGK adjoint),
- * record_kind 2 saves f - w as [slot][19][stride] floats (Smagorinsky and
- * regularised adjoints); slot = n % n_slots; rec_dev[i] is instance i's buffer. */
+ * record_kind 2 saves f - w as [slot][19][stride] floats (any model),
+ * record_kind 3 saves what the regularised adjoint needs, (rho, u_x, u_y,
+ * u_z, the non-equilibrium stress xx, yy, zz, xy, xz, yz, and the six
+ * third-order Hermite moments of f - w in the order of the regularised
+ * collision's basis), as [slot][16][stride] floats (regularised model only;
+ * LBM_E_INVALID otherwise); slot = n % n_slots; rec_dev[i] is instance i's
+ * buffer.  Records are written with non-temporal stores. */
 int lbm_collide_stream_record(lbm_plan *plan, int32_t n_steps, int32_t record_kind,
                               float *const *rec_dev_host, int32_t n_slots, hipStream_t stream);
 
@@ -312,8 +317,9 @@ int lbm_gpc_coefficients(const float *q_dev, const double *wphi_dev, int32_t n_n
  * (count = avg_end - avg_begin).  Buffers per instance (device pointers in
  * host arrays of length n_inst): lam_in (lam^{n+1}) and lam_out (lam^n),
  * [19][stride] floats; rec, the state recorded by
- * lbm_collide_stream_record for step n (kind 1 for BGK, 2 for the
- * Smagorinsky and regularised models, slot n % n_slots); pw, [n_probes] FP64 probe weights or NULL;
+ * lbm_collide_stream_record for step n (kind 1 or 2 for BGK, 2 for the
+ * Smagorinsky model, 2 or 3 for the regularised model; slot n % n_slots);
+ * pw, [n_probes] FP64 probe weights or NULL;
  * dJdtheta_dev, [n_inst][3] FP64 accumulated in place, in a fixed summation
  * order (per-tile partials in a plan-owned buffer, then one sum per
  * instance), so repeated sweeps give identical gradients.  lam^n of solid
@@ -321,8 +327,8 @@ int lbm_gpc_coefficients(const float *q_dev, const double *wphi_dev, int32_t n_n
  * is the chain rule through f_eq3, the regularisation projector and the
  * Smagorinsky tau_eff, in Hermite moments.  Rejected (LBM_E_INVALID): a
  * missing buffer, lam_in and lam_out the same buffer (the step reads
- * neighbours' lam^{n+1} while writing lam^n), a record kind other than 1 or
- * 2, kind 1 for a non-BGK plan, n_slots < 1 or a negative step. */
+ * neighbours' lam^{n+1} while writing lam^n), a record kind the plan's
+ * model does not take, n_slots < 1 or a negative step. */
 int lbm_adjoint_step(lbm_plan *plan, int64_t step, float *const *lam_in_host,
                      float *const *lam_out_host, float *const *rec_host, int32_t record_kind,
                      int32_t n_slots, const double *const *pw_host, double *dJdtheta_dev,

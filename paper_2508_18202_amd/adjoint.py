@@ -37,7 +37,7 @@ class CheckpointedAdjoint:
     """
 
     def __init__(self, ens: Ensemble, steps: int, ckpt: int = 100, group_size: Optional[int] = None,
-                 inplace: bool = False):
+                 inplace: bool = False, record_kind: Optional[int] = None):
         if steps % 2 or ckpt % 2:
             raise ValueError("run length and checkpoint spacing must be even")
         if ens.avg_end != steps:
@@ -56,7 +56,11 @@ class CheckpointedAdjoint:
         self.groups = [list(range(n))] if not group_size else \
             [list(range(k, min(n, k + group_size))) for k in range(0, n, group_size)]
         self.grouped = bool(group_size) and group_size < n
-        self.kind = L.RECORD_MACROS if self.model == L.BGK else L.RECORD_POPULATIONS
+        # what the recording re-runs save per cell and step: (rho, u) for BGK,
+        # the populations for Smagorinsky, the 16 state values of the
+        # regularised collision for it (record_kind overrides, e.g. 2)
+        default = {L.BGK: L.RECORD_MACROS, L.RR3: L.RECORD_RR3_STATE}.get(self.model, L.RECORD_POPULATIONS)
+        self.kind = default if record_kind is None else int(record_kind)
         self.marks = list(range(0, steps, ckpt))
         self.snaps: List[List[torch.Tensor]] = []
         gmax = max(len(g) for g in self.groups)
@@ -65,7 +69,8 @@ class CheckpointedAdjoint:
         self.lam = [[], []]
         for k in range(gmax):
             cgs = [ens.cases[ens.index[g[k]][0]] for g in self.groups if k < len(g)]
-            per_slot = max(4 * cg.ncells if self.kind == L.RECORD_MACROS else 19 * cg.qs for cg in cgs)
+            per_slot = max(4 * cg.ncells if self.kind == L.RECORD_MACROS else
+                           (L.RR3_STATE_VALUES if self.kind == L.RECORD_RR3_STATE else 19) * cg.qs for cg in cgs)
             lam_len = max(19 * cg.qs for cg in cgs)
             self.rec.append(torch.empty(ckpt * per_slot, dtype=torch.float32, device="cuda"))
             for b in range(1 if self.inplace else 2):

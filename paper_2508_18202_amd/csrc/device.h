@@ -454,6 +454,35 @@ __host__ __device__ constexpr float herm3(int k, int i)
 }
 __host__ __device__ constexpr float herm3_inv_norm(int k) { return (k & 1) ? 4.5f : 13.5f; }
 
+// What the regularised adjoint needs of the pre-collision state: rho, u,
+// the non-equilibrium stress P and the third-order Hermite moments
+// t3_j = sum_i P_j(c_i) (f_i - w_i) (16 values: record kind 3 stores them).
+struct Rr3State {
+    float rho, ux, uy, uz, P[6], t3[6];
+};
+
+__device__ __forceinline__ Rr3State rr3_state(const float g[Q])
+{
+    Rr3State r;
+    const PairSums ps = pair_sums(g);
+    const Macro m = macro_of(g, ps);
+    r.rho = m.rho;
+    r.ux = m.ux;
+    r.uy = m.uy;
+    r.uz = m.uz;
+    neq_stress(ps, m, r.P);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        float t = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            if (herm3(j, 2 * k + 1) != 0.0f) t += herm3(j, 2 * k + 1) * ps.d[k];
+        r.t3[j] = t;
+    }
+    return r;
+}
+
+
 // Regularised collision (Eq. deterministicLBE as printed), with the
 // Smagorinsky tau_eff:
 //   f* = f_eq3 + (1 - 1/tau) [w (H2 : Pi / (2 cs^4) + sum_k P_k a1_k / N_k)],
@@ -692,6 +721,15 @@ __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const 
             GLOBAL_AS float *r = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)Q * G.qs;
 #pragma unroll
             for (int i = 0; i < Q; ++i) stg<true>(r + (size_t)i * qs, c[j], g[j][i]);
+        } else if (MODEL == 2 && a.record == 3) {
+            // record kind 3: the regularised adjoint's 16 state values
+            const Rr3State st = rr3_state(g[j]);
+            const float v[RR3_REC] = {st.rho,   st.ux,   st.uy,   st.uz,   st.P[0],  st.P[1],
+                                      st.P[2],  st.P[3], st.P[4], st.P[5], st.t3[0], st.t3[1],
+                                      st.t3[2], st.t3[3], st.t3[4], st.t3[5]};
+            GLOBAL_AS float *r = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)RR3_REC * G.qs;
+#pragma unroll
+            for (int i = 0; i < RR3_REC; ++i) stg<true>(r + (size_t)i * qs, c[j], v[i]);
         }
         collide<MODEL>(G, g[j], m, ps);
     }
@@ -854,19 +892,16 @@ __device__ __forceinline__ void eval_poly(float out[Q], const float base[Q], flo
 // (tr M' I + 2 M') / 2, third order b_j.  lambda_k is then a cubic
 // polynomial in c_k with sixteen coefficients.  srcw: objective weight of
 // u_x (adds srcw (c_kx - u_x) / rho).
-__device__ __forceinline__ void adjoint_rr3_moments(const Geo &G, const float g[Q], const float mu[Q], float srcw,
+__device__ __forceinline__ void adjoint_rr3_moments(const Geo &G, const Rr3State &st, const float mu[Q], float srcw,
                                                     float lam[Q])
 {
-    const PairSums ps = pair_sums(g);
-    const Macro m = macro_of(g, ps);
-    float P[6];
-    neq_stress(ps, m, P);
+    const float *P = st.P;
     const float qn = stress_norm(P);
-    const float R = sqrtf(G.tau0 * G.tau0 + G.kcs * qn / m.rho);
+    const float R = sqrtf(G.tau0 * G.tau0 + G.kcs * qn / st.rho);
     const float tau = 0.5f * (G.tau0 + R);
     const float om = 1.0f / tau;
     const float keep = 1.0f - om;
-    const float ux = m.ux, uy = m.uy, uz = m.uz, rho = m.rho;
+    const float ux = st.ux, uy = st.uy, uz = st.uz, rho = st.rho;
     const float A3[6] = {ux * ux * uy + uy * uz * uz, ux * ux * uy - uy * uz * uz,
                          ux * uz * uz + ux * uy * uy, ux * uz * uz - ux * uy * uy,
                          uy * uy * uz + ux * ux * uz, uy * uy * uz - ux * ux * uz};
@@ -880,13 +915,7 @@ __device__ __forceinline__ void adjoint_rr3_moments(const Geo &G, const float g[
     // lower orders are orthogonal to P_j), and sum_i P_j(c_i) w_i = 0
     float a1[6];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        float s = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 9; ++k)
-            if (herm3(j, 2 * k + 1) != 0.0f) s += herm3(j, 2 * k + 1) * ps.d[k];
-        a1[j] = s - rho * A3[j];
-    }
+    for (int j = 0; j < 6; ++j) a1[j] = st.t3[j] - rho * A3[j];
     const WMoments W = weighted_moments(mu);
     const float M0 = W.m0;
     const float trp = W.m2[0] + W.m2[1] + W.m2[2] - M0;     // tr M'
@@ -1242,10 +1271,14 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
             const int z = inflow_lane(G, fl[j]) ? (int)fdiv(c[j], G.dxy) : 0;
             adjoint_gather(G, S, ps, smv[j], c[j], z, T, MODE == 0 ? lin : lbuf, mu[j], gr0, gr1, gr2, Dirs{});
         }
-        if (a.record != 1) {
+        if (a.record == 2) {
             const GLOBAL_AS float *rp = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)Q * G.qs;
 #pragma unroll
             for (int i = 0; i < Q; ++i) gs[j][i] = ldg<true>(rp, (uint32_t)i * qs + c[j]);
+        } else if (MODEL == 2 && a.record == 3) {
+            const GLOBAL_AS float *rp = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)RR3_REC * G.qs;
+#pragma unroll
+            for (int i = 0; i < RR3_REC; ++i) gs[j][i] = ldg<true>(rp, (uint32_t)i * qs + c[j]);
         }
     }
     // MODE 1: the rules of each cell's stores (see adjoint_emit)
@@ -1290,7 +1323,21 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
                 const int p = probe_index(G, (int32_t)c[j]);
                 if (p >= 0) srcw = (float)(a.pw[ii][p] * a.inv_count);
             }
-            adjoint_rr3_moments(G, gs[j], mu[j], srcw, lam);
+            Rr3State st;
+            if (a.record == 3) {
+                st.rho = gs[j][0];
+                st.ux = gs[j][1];
+                st.uy = gs[j][2];
+                st.uz = gs[j][3];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    st.P[k] = gs[j][4 + k];
+                    st.t3[k] = gs[j][10 + k];
+                }
+            } else {
+                st = rr3_state(gs[j]);
+            }
+            adjoint_rr3_moments(G, st, mu[j], srcw, lam);
             if constexpr (MODE == 1) {
                 if (cls[j] == 1)
                     adjoint_emit_x(G, S, pg[j].xlo, pg[j].xhi, owner[j], wout[j], c[j], zg[j], Tg, lbuf,

@@ -39,10 +39,14 @@ struct Geo {
 };
 
 // Launch arguments that change from step to step.
+// values per cell of a record of kind 3 (the regularised adjoint's state:
+// rho, u, the non-equilibrium stress, the six third-order Hermite moments)
+constexpr int RR3_REC = 16;
+
 struct StepArgs {
     int64_t step;              // time index n of the state being collided
     int32_t accumulate;        // add this state's QoIs to the window sums
-    int32_t record;            // 0 none, 1 (rho,u), 2 populations
+    int32_t record;            // 0 none, 1 (rho,u), 2 populations, 3 regularised state
     int32_t xcd_remap;         // tile order over the XCDs (set from the variant, see tile_of)
     float *const *rec;         // device array [n_inst] of record buffer bases
     int64_t rec_slot;          // slot index n % n_slots
@@ -104,7 +108,7 @@ int launch_moments(const float *q, const double *w, int32_t nq, int64_t n, doubl
 struct AdjArgs {
     int64_t step;
     int32_t model;
-    int32_t record;            // 1 (rho,u) or 2 populations
+    int32_t record;            // 1 (rho,u), 2 populations or 3 regularised state
     int32_t in_window;         // the objective has a term at this step
     double inv_count;          // 1 / (avg_end - avg_begin)
     float *const *lam_in;      // device arrays [n_inst]

@@ -819,7 +819,9 @@ int lbm_collide_stream_record(lbm_plan *p, int32_t n_steps, int32_t kind, float 
     int r = check_plan(p);
     if (r) return r;
     if (n_steps < 0 || n_slots < 1 || !rec_host) return fail(LBM_E_INVALID, "bad record arguments");
-    if (kind != 1 && kind != 2) return fail(LBM_E_INVALID, "record kind must be 1 (rho,u) or 2 (populations)");
+    if (kind < 1 || kind > 3)
+        return fail(LBM_E_INVALID, "record kind must be 1 (rho,u), 2 (populations) or 3 (regularised state)");
+    if (kind == 3 && p->model != LBM_RR3) return fail(LBM_E_INVALID, "record kind 3 is for the regularised model");
     for (int i = 0; i < p->n_inst; ++i)
         if (!rec_host[i]) return fail(LBM_E_INVALID, "instance %d: NULL record buffer", i);
     float **rec_d = nullptr;
@@ -892,9 +894,12 @@ int adjoint_step(lbm_plan *p, int64_t step, float *const *lam_in_host, float *co
     if (r) return r;
     if (!lam_in_host || !lam_out_host || !rec_host || !pw_host || !dJdtheta_dev || n_slots < 1 || step < 0)
         return fail(LBM_E_INVALID, "bad adjoint arguments");
-    if (kind != 1 && kind != 2) return fail(LBM_E_INVALID, "record kind must be 1 or 2");
-    if (p->model != LBM_BGK && kind != 2)
-        return fail(LBM_E_INVALID, "the Smagorinsky and regularised adjoints need recorded populations (kind 2)");
+    if (kind < 1 || kind > 3) return fail(LBM_E_INVALID, "record kind must be 1, 2 or 3");
+    if (p->model == LBM_SMAGORINSKY && kind != 2)
+        return fail(LBM_E_INVALID, "the Smagorinsky adjoint needs recorded populations (kind 2)");
+    if (p->model == LBM_RR3 && kind == 1)
+        return fail(LBM_E_INVALID, "the regularised adjoint needs recorded populations or its state (kind 2 or 3)");
+    if (p->model == LBM_BGK && kind == 3) return fail(LBM_E_INVALID, "record kind 3 is for the regularised model");
     for (int i = 0; i < p->n_inst; ++i)
         if (!lam_in_host[i] || !lam_out_host[i] || !rec_host[i] || (mode == 0 && lam_in_host[i] == lam_out_host[i]))
             return fail(LBM_E_INVALID, "instance %d: missing or aliased adjoint buffers", i);

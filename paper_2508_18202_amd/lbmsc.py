@@ -26,7 +26,8 @@ INFLOW_UNIFORM, INFLOW_LOGLAW, INFLOW_SERIES = 0, 1, 2
 INFLOWS = {"uniform": INFLOW_UNIFORM, "loglaw": INFLOW_LOGLAW, "series": INFLOW_SERIES}
 QUAD_GAUSS_LEGENDRE, QUAD_SMOLYAK_CC, QUAD_GAUSS_HERMITE = 0, 1, 2
 QUADS = {"gauss_legendre": QUAD_GAUSS_LEGENDRE, "smolyak_cc": QUAD_SMOLYAK_CC, "gauss_hermite": QUAD_GAUSS_HERMITE}
-RECORD_MACROS, RECORD_POPULATIONS = 1, 2
+RECORD_MACROS, RECORD_POPULATIONS, RECORD_RR3_STATE = 1, 2, 3
+RR3_STATE_VALUES = 16             # per cell in a record of kind 3
 
 
 class LbmError(RuntimeError):

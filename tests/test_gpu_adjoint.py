@@ -14,6 +14,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import oracle as orc
 from paper_2508_18202_amd import inputs, sc
+from paper_2508_18202_amd import lbmsc as L
 from paper_2508_18202_amd.adjoint import CheckpointedAdjoint, probe_qoi
 from gpu_util import oracle_case
 
@@ -234,5 +235,48 @@ def test_lambda_buffer_count_follows_the_layout(model):
             run = CheckpointedAdjoint(ens, w.steps, 10, **kw)
             assert [len(b) for b in run.lam] == ([2, 2] if n_buf == 2 else [2, 0]), (inplace, run.lam)
             run.close()
+    finally:
+        ens.close()
+
+
+@pytest.mark.parametrize("inplace", [False, True], ids=["two_buffers", "in_place"])
+def test_regularised_state_record_equals_population_record(inplace):
+    """The regularised adjoint from its 16 recorded state values (record kind
+    3, the default for the model) gives the same gradients, bit for bit, as
+    from the recorded populations (kind 2): the state is formed from the same
+    pre-collision values by the same arithmetic on both paths."""
+    w = inputs.scaled(inputs.urban_les(steps=60, avg_len=20), 48, 24, 20, model="rr3", ramp=20)
+    solid = inputs.solid_mask(w)
+    probes = _plane_probes(w, solid)
+    cg = sc.make_geometry(w, solid, probes)
+    x, a, th = sc.collocation(w)
+    pw = [torch.full((len(probes),), 1.0 / len(probes), dtype=torch.float64, device="cuda")] * 3
+    grads = {}
+    for kind in (L.RECORD_POPULATIONS, L.RECORD_RR3_STATE):
+        ens = sc.Ensemble([cg], [th[:3]], avg_begin=w.avg_start, avg_end=w.steps, use_graph=False)
+        try:
+            run = CheckpointedAdjoint(ens, w.steps, 20, inplace=inplace, record_kind=kind)
+            assert run.kind == kind
+            run.forward()
+            grads[kind] = run.backward(pw).cpu().numpy()
+            run.close()
+        finally:
+            ens.close()
+    assert np.abs(grads[L.RECORD_POPULATIONS]).max() > 0
+    assert np.array_equal(grads[L.RECORD_POPULATIONS], grads[L.RECORD_RR3_STATE])
+
+
+def test_record_kinds_rejected_for_other_models():
+    """Record kind 3 belongs to the regularised model: a Smagorinsky plan
+    refuses it for recording and for the adjoint step."""
+    w = inputs.scaled(inputs.urban_les(steps=20, avg_len=10), 24, 12, 10)
+    solid = inputs.solid_mask(w)
+    cg = sc.make_geometry(w, solid, _plane_probes(w, solid))
+    x, a, th = sc.collocation(w)
+    ens = sc.Ensemble([cg], [th[:1]], avg_begin=w.avg_start, avg_end=w.steps, use_graph=False)
+    try:
+        rec = torch.zeros(16 * cg.qs, dtype=torch.float32, device="cuda")
+        with pytest.raises(L.LbmError, match="kind 3"):
+            L.lbm_collide_stream_record(ens.plan, 1, L.RECORD_RR3_STATE, [rec.data_ptr()], 1, sc.stream_handle())
     finally:
         ens.close()
