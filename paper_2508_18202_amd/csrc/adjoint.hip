@@ -6,12 +6,28 @@ namespace lbmsc {
 
 namespace {
 
+// record kinds per model: BGK 1 or 2, Smagorinsky 2, regularised 2 or 3
+template <int BS, int CPT, int M, int MODE>
+void adjoint_r(const dim3 &grid, const dim3 &block, const Geo *geo, const int32_t *ti, int32_t nt, int32_t xr,
+               const AdjArgs &a, hipStream_t s)
+{
+    if constexpr (M == 0) {
+        if (a.record == 1) hipLaunchKernelGGL((k_adjoint<BS, CPT, M, MODE, 1>), grid, block, 0, s, geo, ti, nt, xr, a);
+        else hipLaunchKernelGGL((k_adjoint<BS, CPT, M, MODE, 2>), grid, block, 0, s, geo, ti, nt, xr, a);
+    } else if constexpr (M == 2) {
+        if (a.record == 3) hipLaunchKernelGGL((k_adjoint<BS, CPT, M, MODE, 3>), grid, block, 0, s, geo, ti, nt, xr, a);
+        else hipLaunchKernelGGL((k_adjoint<BS, CPT, M, MODE, 2>), grid, block, 0, s, geo, ti, nt, xr, a);
+    } else {
+        hipLaunchKernelGGL((k_adjoint<BS, CPT, M, MODE, 2>), grid, block, 0, s, geo, ti, nt, xr, a);
+    }
+}
+
 template <int BS, int MODE>
 void adjoint_m(const Variant &v, const Geo *geo, const int32_t *ti, int32_t nt, const AdjArgs &a, hipStream_t s)
 {
     const dim3 grid(grid_of(nt)), block(BS);
     const int32_t xr = v.xcd;
-#define LBM_ADJ(C, M) hipLaunchKernelGGL((k_adjoint<BS, C, M, MODE>), grid, block, 0, s, geo, ti, nt, xr, a)
+#define LBM_ADJ(C, M) adjoint_r<BS, C, M, MODE>(grid, block, geo, ti, nt, xr, a, s)
     // the adjoint runs a whole tile per workgroup: one cell per thread up
     // to 512 threads, then 2 or 4 cells per thread
     if constexpr (BS < 512) {

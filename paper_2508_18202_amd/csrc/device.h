@@ -1172,8 +1172,10 @@ __device__ __forceinline__ void adjoint_emit_x(const Geo &G, const Shape &S, boo
 // of the populations (the transposed in-place streaming): MODE 1 is the
 // adjoint of an odd step (lambda read at the slots the step scattered to,
 // written to the slots it gathered from), MODE 2 of an even step (own
-// slots, swapped back).
-template <int BS, int CPT, int MODEL, int MODE>
+// slots, swapped back).  REC: the record kind the sweep recorded (1 (rho, u),
+// 2 populations, 3 the regularised state), a template parameter so that each
+// instantiation carries one record path.
+template <int BS, int CPT, int MODEL, int MODE, int REC>
 __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
                                                 int32_t n_tiles, int32_t xcd_remap, AdjArgs a)
 {
@@ -1240,7 +1242,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
         }
         fl[j] = act[j] ? gp(G.flags)[c[j]] : (uint8_t)FL_SOLID;
         smv[j] = (cls[j] >= 2 && act[j]) ? gp(G.smask)[c[j]] : 0u;
-        if (a.record == 1 && act[j])
+        if (REC == 1 && act[j])
             st[j] = __builtin_nontemporal_load((const GLOBAL_AS f32x4 *)gp(a.rec[ii]) + ((size_t)a.rec_slot * (size_t)G.ncells + c[j]));
     }
     bool flow2 = false;
@@ -1271,11 +1273,11 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
             const int z = inflow_lane(G, fl[j]) ? (int)fdiv(c[j], G.dxy) : 0;
             adjoint_gather(G, S, ps, smv[j], c[j], z, T, MODE == 0 ? lin : lbuf, mu[j], gr0, gr1, gr2, Dirs{});
         }
-        if (a.record == 2) {
+        if (REC == 2) {
             const GLOBAL_AS float *rp = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)Q * G.qs;
 #pragma unroll
             for (int i = 0; i < Q; ++i) gs[j][i] = ldg<true>(rp, (uint32_t)i * qs + c[j]);
-        } else if (MODEL == 2 && a.record == 3) {
+        } else if (MODEL == 2 && REC == 3) {
             const GLOBAL_AS float *rp = gp(a.rec[ii]) + (size_t)a.rec_slot * (size_t)RR3_REC * G.qs;
 #pragma unroll
             for (int i = 0; i < RR3_REC; ++i) gs[j][i] = ldg<true>(rp, (uint32_t)i * qs + c[j]);
@@ -1324,7 +1326,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
                 if (p >= 0) srcw = (float)(a.pw[ii][p] * a.inv_count);
             }
             Rr3State st;
-            if (a.record == 3) {
+            if (REC == 3) {
                 st.rho = gs[j][0];
                 st.ux = gs[j][1];
                 st.uy = gs[j][2];
@@ -1354,7 +1356,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(const Geo *__restrict__ geo, con
         // state of step n (the relaxation rate as the forward step forms it)
         float rho, ux, uy, uz;
         float muf = 0.0f, P[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, qn = 0.0f, tau = G.tau0;
-        if (a.record == 1) {
+        if (REC == 1) {
             rho = st[j].x;
             ux = st[j].y;
             uy = st[j].z;
