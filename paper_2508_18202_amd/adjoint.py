@@ -37,7 +37,7 @@ class CheckpointedAdjoint:
     """
 
     def __init__(self, ens: Ensemble, steps: int, ckpt: int = 100, group_size: Optional[int] = None,
-                 inplace: bool = False, record_kind: Optional[int] = None):
+                 inplace: Optional[bool] = None, record_kind: Optional[int] = None):
         if steps % 2 or ckpt % 2:
             raise ValueError("run length and checkpoint spacing must be even")
         if ens.avg_end != steps:
@@ -46,12 +46,12 @@ class CheckpointedAdjoint:
         self.steps = steps
         self.ckpt = ckpt
         self.model = ens.instances[0].model
-        # two alternating lambda buffers per instance (lbm_adjoint_step) by
-        # default: measured as fast or faster than the in-place update for every
-        # model (sweep time on the 13 x 128x64x48 adjoint case: BGK equal,
-        # Smagorinsky 2 %, regularised 5 % faster); inplace=True keeps one
-        # buffer updated in place (lbm_adjoint_step_inplace), half the memory
-        self.inplace = bool(inplace)
+        # lambda layout by default the faster one measured on the 13 x
+        # 128x64x48 adjoint case (sweeps on one box): one buffer updated in
+        # place (lbm_adjoint_step_inplace, half the memory) for BGK, 2-3 %
+        # faster; two alternating buffers (lbm_adjoint_step) for the
+        # Smagorinsky and regularised models, 1-2 % and 5 % faster
+        self.inplace = (self.model == L.BGK) if inplace is None else bool(inplace)
         n = len(ens)
         self.groups = [list(range(n))] if not group_size else \
             [list(range(k, min(n, k + group_size))) for k in range(0, n, group_size)]
