@@ -10,14 +10,20 @@ Schedule for a run of N steps with snapshots every C steps:
   init      lam^N = dj_N/df^N                               (lbm_adjoint_init)
   segments  for each segment [s0, s1) from last to first:
               restore the snapshot of s0, re-run s0 -> s1 recording the state
-              of every step (rho, u for BGK; populations for Smagorinsky),
-              then lam^n from lam^{n+1} for n = s1-1 ... s0  (lbm_adjoint_step)
+              of every step (rho, u for BGK; populations for Smagorinsky; the
+              16 state values of the regularised collision), then lam^n from
+              lam^{n+1} for n = s1-1 ... s0  (lbm_adjoint_step)
 dJ/dtheta accumulates in FP64 inside the adjoint kernel.
 
 With ``group_size`` set, the forward pass advances the whole batch without
 snapshots, and the reverse sweep runs group by group (each group re-runs its
 own forward with snapshots on a plan of its own), so snapshot and record
 memory scale with the group, not the batch.
+
+Without groups the forward run records its last steps itself
+(lbm_collide_stream_record_qoi), as many whole segments as fit in a fraction
+of the free device memory (every step when they all fit: ``store_all``), and
+the sweep takes those segments without a re-run.
 """
 from __future__ import annotations
 
@@ -37,7 +43,9 @@ class CheckpointedAdjoint:
     """
 
     def __init__(self, ens: Ensemble, steps: int, ckpt: int = 100, group_size: Optional[int] = None,
-                 inplace: Optional[bool] = None, record_kind: Optional[int] = None):
+                 inplace: Optional[bool] = None, record_kind: Optional[int] = None,
+                 store_all: Optional[bool] = None, memory_fraction: float = 0.6,
+                 stored_steps: Optional[int] = None):
         if steps % 2 or ckpt % 2:
             raise ValueError("run length and checkpoint spacing must be even")
         if ens.avg_end != steps:
@@ -64,26 +72,62 @@ class CheckpointedAdjoint:
         self.marks = list(range(0, steps, ckpt))
         self.snaps: List[List[torch.Tensor]] = []
         gmax = max(len(g) for g in self.groups)
+
+        def per_slot_of(cg):
+            if self.kind == L.RECORD_MACROS:
+                return 4 * cg.ncells
+            return (L.RR3_STATE_VALUES if self.kind == L.RECORD_RR3_STATE else 19) * cg.qs
+
+        # stored tail: the forward run records its last `stored` steps (a
+        # multiple of ckpt), whose segments the sweep then takes without a
+        # re-run; the earlier segments keep their snapshots and are re-run
+        # with recording into the same slots (slot n % stored) once the tail
+        # is consumed.  By default as many steps as fit in memory_fraction of
+        # the free device memory (all of them for BGK's 16-byte records of the
+        # 13 x 128x64x48 adjoint case, 164 GB); store_all=True asks for every
+        # step, False for one segment; grouped sweeps store one segment.
+        per_step = 4 * sum(per_slot_of(ens.cases[ens.index[i][0]]) for i in range(n))
+        if self.grouped:
+            if store_all:
+                raise ValueError("store_all needs the whole batch in one sweep (no group_size)")
+            stored = ckpt
+        elif stored_steps is not None:
+            if stored_steps != steps and (stored_steps % ckpt or not ckpt <= stored_steps < steps):
+                raise ValueError("stored_steps must be the run length or a multiple of ckpt below it")
+            stored = stored_steps
+        elif store_all is None:
+            free = torch.cuda.mem_get_info()[0] + torch.cuda.memory_reserved() - torch.cuda.memory_allocated()
+            stored = min(steps, max(ckpt, int(memory_fraction * free // per_step) // ckpt * ckpt))
+        else:
+            stored = steps if store_all else ckpt
+        self.stored = stored
+        self.store_all = stored >= steps
+        self.n_slots = stored
+        self.head = steps - stored         # steps before the stored tail
         # record and adjoint buffers for the largest group (reused group after group)
         self.rec: List[torch.Tensor] = []
         self.lam = [[], []]
         for k in range(gmax):
             cgs = [ens.cases[ens.index[g[k]][0]] for g in self.groups if k < len(g)]
-            per_slot = max(4 * cg.ncells if self.kind == L.RECORD_MACROS else
-                           (L.RR3_STATE_VALUES if self.kind == L.RECORD_RR3_STATE else 19) * cg.qs for cg in cgs)
+            per_slot = max(per_slot_of(cg) for cg in cgs)
             lam_len = max(19 * cg.qs for cg in cgs)
-            self.rec.append(torch.empty(ckpt * per_slot, dtype=torch.float32, device="cuda"))
+            self.rec.append(torch.empty(self.n_slots * per_slot, dtype=torch.float32, device="cuda"))
             for b in range(1 if self.inplace else 2):
                 self.lam[b].append(torch.empty(lam_len, dtype=torch.float32, device="cuda"))
         self.grad = torch.zeros(n, 3, dtype=torch.float64, device="cuda")
         self._subplans = {}
 
     # ------------------------------------------------------------------ forward
-    def _advance_with_snapshots(self, plan, fs: Sequence[torch.Tensor]):
+    def _advance_with_snapshots(self, plan, fs: Sequence[torch.Tensor], upto: Optional[int] = None):
+        """Advance to step `upto` (default N), copying the populations at the
+        marks before it."""
+        upto = self.steps if upto is None else upto
         self.snaps = []
         for s0 in self.marks:
+            if s0 >= upto:
+                break
             self.snaps.append([f.clone() for f in fs])
-            L.lbm_collide_stream(plan, min(self.ckpt, self.steps - s0), stream_handle())
+            L.lbm_collide_stream(plan, min(self.ckpt, upto - s0), stream_handle())
 
     def forward(self):
         """Advance the batch from rest to step N; returns the probe averages per instance."""
@@ -92,7 +136,10 @@ class CheckpointedAdjoint:
         if self.grouped:
             ens.advance(self.steps)
         else:
-            self._advance_with_snapshots(ens.plan, ens.f)
+            # snapshots up to the stored tail, then the tail with its records
+            self._advance_with_snapshots(ens.plan, ens.f, upto=self.head)
+            L.lbm_collide_stream_record_qoi(ens.plan, self.stored, self.kind, [t.data_ptr() for t in self.rec],
+                                            self.n_slots, stream_handle())
         out = []
         for i in range(len(ens)):
             cg = ens.cases[ens.index[i][0]]
@@ -123,20 +170,28 @@ class CheckpointedAdjoint:
         fs = [self.ens.f[i] for i in members]
         N = self.steps
         L.lbm_adjoint_init(plan, lam_ptr[0 if self.inplace else N % 2], pw_ptr, s)
-        for m in reversed(range(len(self.marks))):
-            s0 = self.marks[m]
-            s1 = min(s0 + self.ckpt, N)
-            for f, snap in zip(fs, self.snaps[m]):
-                f.copy_(snap)
-            L.lbm_plan_set_step(plan, s0)
-            L.lbm_collide_stream_record(plan, s1 - s0, self.kind, rec_ptr, self.ckpt, s)
+
+        def adjoint_steps(s1, s0):
             for n in range(s1 - 1, s0 - 1, -1):
                 if self.inplace:
-                    L.lbm_adjoint_step_inplace(plan, n, lam_ptr[0], rec_ptr, self.kind, self.ckpt, pw_ptr,
+                    L.lbm_adjoint_step_inplace(plan, n, lam_ptr[0], rec_ptr, self.kind, self.n_slots, pw_ptr,
                                                grad.data_ptr(), s)
                 else:
                     L.lbm_adjoint_step(plan, n, lam_ptr[(n + 1) % 2], lam_ptr[n % 2], rec_ptr,
-                                       self.kind, self.ckpt, pw_ptr, grad.data_ptr(), s)
+                                       self.kind, self.n_slots, pw_ptr, grad.data_ptr(), s)
+
+        # segments of the stored tail still have their records from the
+        # forward run; the earlier ones are re-run from their snapshots
+        tail_from = N if self.grouped else self.head
+        for m in reversed(range(len(self.marks))):
+            s0 = self.marks[m]
+            s1 = min(s0 + self.ckpt, N)
+            if s0 < tail_from:
+                for f, snap in zip(fs, self.snaps[m]):
+                    f.copy_(snap)
+                L.lbm_plan_set_step(plan, s0)
+                L.lbm_collide_stream_record(plan, s1 - s0, self.kind, rec_ptr, self.n_slots, s)
+            adjoint_steps(s1, s0)
 
     def backward(self, pweights: Sequence[Optional[torch.Tensor]]):
         """dJ/dtheta [n_inst, 3] (FP64) of J_i = sum_p pweights[i][p] <u_x(p)>.

@@ -330,8 +330,13 @@ bool pair_plain(const lbm_plan *p, int64_t n)
     return true;
 }
 
-int run_steps(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_d, int32_t n_slots, hipStream_t s)
+// kind > 0 records the state of every step; qoi: the steps also add to the
+// QoI sums (a forward run that records), else recording leaves them alone
+// (the adjoint sweep's segment re-runs)
+int run_steps(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_d, int32_t n_slots, hipStream_t s,
+              bool qoi = false)
 {
+    const bool sums = kind == 0 || qoi;
     int32_t left = n_steps;
     while (left > 0) {
         const int64_t n = p->step;
@@ -351,8 +356,7 @@ int run_steps(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_d, i
         StepArgs a{};
         a.step = n;
         a.tinfo = p->tinfo_d;
-        // recording runs re-play steps for the adjoint and leave the QoI sums alone
-        a.accumulate = (kind == 0 && step_accumulates(p, n)) ? 1 : 0;
+        a.accumulate = (sums && step_accumulates(p, n)) ? 1 : 0;
         a.record = kind;
         a.rec = rec_d;
         a.rec_slot = kind ? (n % n_slots) : 0;
@@ -361,7 +365,7 @@ int run_steps(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_d, i
         p->step = n + 1;
         --left;
         if (a.accumulate) ++p->pending;
-        if (kind == 0 && p->avg_end > p->avg_begin && p->step == p->avg_end && p->step > p->avg_begin) {
+        if (sums && p->avg_end > p->avg_begin && p->step == p->avg_end && p->step > p->avg_begin) {
             // the last state of the window is never collided inside the window
             if (launch_capture(p->v.tile(), (int)(p->step & 1), p->geo_d, p->tiles_d, p->n_tiles, p->step,
                                p->health_d, s))
@@ -813,8 +817,10 @@ int lbm_collide_stream(lbm_plan *p, int32_t n_steps, hipStream_t s)
     return run_steps(p, n_steps, 0, nullptr, 1, s);
 }
 
-int lbm_collide_stream_record(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_host, int32_t n_slots,
-                              hipStream_t s)
+namespace {
+
+int collide_stream_record(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_host, int32_t n_slots,
+                          bool qoi, hipStream_t s)
 {
     int r = check_plan(p);
     if (r) return r;
@@ -827,7 +833,21 @@ int lbm_collide_stream_record(lbm_plan *p, int32_t n_steps, int32_t kind, float 
     float **rec_d = nullptr;
     r = table_of(p, (float *const *)rec_host, &rec_d);
     if (r) return r;
-    return run_steps(p, n_steps, kind, rec_d, n_slots, s);
+    return run_steps(p, n_steps, kind, rec_d, n_slots, s, qoi);
+}
+
+}  // namespace
+
+int lbm_collide_stream_record(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_host, int32_t n_slots,
+                              hipStream_t s)
+{
+    return collide_stream_record(p, n_steps, kind, rec_host, n_slots, false, s);
+}
+
+int lbm_collide_stream_record_qoi(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_host,
+                                  int32_t n_slots, hipStream_t s)
+{
+    return collide_stream_record(p, n_steps, kind, rec_host, n_slots, true, s);
 }
 
 int lbm_read_fields(lbm_plan *p, int32_t i, float *out_dev, hipStream_t s)

@@ -87,6 +87,8 @@ _SIGS = [
     ("lbm_collide_stream", ctypes.c_int, [_P, ctypes.c_int32, _P]),
     ("lbm_collide_stream_record", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P,
                                                  ctypes.c_int32, _P]),
+    ("lbm_collide_stream_record_qoi", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P,
+                                                 ctypes.c_int32, _P]),
     ("lbm_read_fields", ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
     ("lbm_read_populations", ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
     ("lbm_qoi_average", ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
@@ -279,6 +281,11 @@ def lbm_collide_stream(plan, n_steps: int, stream: int):
 def lbm_collide_stream_record(plan, n_steps: int, kind: int, rec_ptrs: Sequence[int], n_slots: int,
                               stream: int):
     _check(lib().lbm_collide_stream_record(plan, n_steps, kind, _ptr_array(rec_ptrs), n_slots, stream))
+
+
+def lbm_collide_stream_record_qoi(plan, n_steps: int, kind: int, rec_ptrs: Sequence[int], n_slots: int,
+                                  stream: int):
+    _check(lib().lbm_collide_stream_record_qoi(plan, n_steps, kind, _ptr_array(rec_ptrs), n_slots, stream))
 
 
 def lbm_read_fields(plan, inst: int, out_dev: int, stream: int):

@@ -281,3 +281,52 @@ def test_record_kinds_rejected_for_other_models():
             L.lbm_collide_stream_record(ens.plan, 1, L.RECORD_RR3_STATE, [rec.data_ptr()], 1, sc.stream_handle())
     finally:
         ens.close()
+
+
+@pytest.mark.parametrize("model", ["bgk", "smagorinsky", "rr3"])
+@pytest.mark.parametrize("inplace", [False, True], ids=["two_buffers", "in_place"])
+def test_store_all_equals_checkpointed(model, inplace):
+    """Forward runs that record one segment, a tail of two or every step
+    (the rest re-run from snapshots with recording) give the same probe
+    averages and gradients, bit for bit: recording runs and plain runs
+    execute the same steps."""
+    w = inputs.scaled(inputs.urban_les(steps=60, avg_len=20), 48, 24, 20, model=model, ramp=20,
+                      tau0=0.56 if model == "bgk" else inputs.LES_TAU0)
+    solid = inputs.solid_mask(w)
+    probes = _plane_probes(w, solid)
+    cg = sc.make_geometry(w, solid, probes)
+    x, a, th = sc.collocation(w)
+    pw = [torch.full((len(probes),), 1.0 / len(probes), dtype=torch.float64, device="cuda")] * 3
+    out = {}
+    for stored in (20, 40, 60):          # one segment, a tail of two, every step
+        ens = sc.Ensemble([cg], [th[:3]], avg_begin=w.avg_start, avg_end=w.steps, use_graph=True)
+        try:
+            run = CheckpointedAdjoint(ens, w.steps, 20, inplace=inplace, stored_steps=stored)
+            assert run.store_all == (stored == w.steps) and run.head == w.steps - stored
+            q = [t.cpu().numpy() for t in run.forward()]
+            g = run.backward(pw).cpu().numpy()
+            # the sweep leaves the batch at rest at step 0 either way
+            assert ens.step == 0 and all(float(f.abs().max()) == 0.0 for f in ens.f)
+            out[stored] = (q, g)
+            run.close()
+        finally:
+            ens.close()
+    assert np.abs(out[20][1]).max() > 0
+    for stored in (40, 60):
+        assert np.array_equal(out[20][1], out[stored][1]), stored
+        for qa, qb in zip(out[20][0], out[stored][0]):
+            assert np.array_equal(qa, qb)
+
+
+def test_store_all_refused_for_grouped_sweeps():
+    w = inputs.scaled(inputs.urban_les(steps=20, avg_len=10), 24, 12, 10)
+    solid = inputs.solid_mask(w)
+    cg = sc.make_geometry(w, solid, _plane_probes(w, solid))
+    x, a, th = sc.collocation(w)
+    ens = sc.Ensemble([cg], [th[:2]], avg_begin=w.avg_start, avg_end=w.steps, use_graph=False)
+    try:
+        with pytest.raises(ValueError):
+            CheckpointedAdjoint(ens, w.steps, 10, group_size=1, store_all=True)
+        assert not CheckpointedAdjoint(ens, w.steps, 10, group_size=1).store_all
+    finally:
+        ens.close()
