@@ -43,7 +43,7 @@ class CheckpointedAdjoint:
     """
 
     def __init__(self, ens: Ensemble, steps: int, ckpt: int = 100, group_size: Optional[int] = None,
-                 inplace: Optional[bool] = None, record_kind: Optional[int] = None,
+                 inplace: bool = False, record_kind: Optional[int] = None,
                  store_all: Optional[bool] = None, memory_fraction: float = 0.6,
                  stored_steps: Optional[int] = None):
         if steps % 2 or ckpt % 2:
@@ -54,12 +54,11 @@ class CheckpointedAdjoint:
         self.steps = steps
         self.ckpt = ckpt
         self.model = ens.instances[0].model
-        # lambda layout by default the faster one measured on the 13 x
-        # 128x64x48 adjoint case (sweeps on one box): one buffer updated in
-        # place (lbm_adjoint_step_inplace, half the memory) for BGK, 2-3 %
-        # faster; two alternating buffers (lbm_adjoint_step) for the
-        # Smagorinsky and regularised models, 1-2 % and 5 % faster
-        self.inplace = (self.model == L.BGK) if inplace is None else bool(inplace)
+        # lambda layout: two alternating buffers (lbm_adjoint_step) by
+        # default, for every model as fast as or faster than one buffer
+        # updated in place (lbm_adjoint_step_inplace, half the lambda memory)
+        # on the 13 x 128x64x48 adjoint case (BGK 4-7 %, regularised 0-3 %)
+        self.inplace = bool(inplace)
         n = len(ens)
         self.groups = [list(range(n))] if not group_size else \
             [list(range(k, min(n, k + group_size))) for k in range(0, n, group_size)]

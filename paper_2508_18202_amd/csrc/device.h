@@ -991,24 +991,27 @@ __device__ __forceinline__ void adjoint_gather(const Geo &G, const Shape &S, con
     };
     double sx = 0.0, sy = 0.0;
     bool inl = false;
+    // Every lane loads its links (a missing one reads the cell's own slot and
+    // is dropped) and the moving-wall terms are selected, not branched on: a
+    // load under a lane condition is waited for inside its branch, one
+    // direction after the other, which took a third of the adjoint step.
     (
         [&] {
             RelLink a, e;
             scatter_rel<Ks>(S, p, sm, a, e);
+            const uint32_t own = (uint32_t)Ks * qs + c;
             float s = 0.0f;
-            if (e.valid) s += ldg(lin, (uint32_t)e.slot * qs + cell(e.delta));
-            if (a.valid) {
-                const float l = ldg(lin, (uint32_t)a.slot * qs + cell(a.delta));
-                s += l;
-                if (a.inlet) {
-                    constexpr int q = opp(Ks);
-                    const double f6 = 6.0 * (double)wgt(q) * (double)l;
-                    sx += (double)cx(q) * f6;
-                    sy += (double)cy(q) * f6;
-                    inl = true;
-                }
+            if constexpr (cx(Ks) == -1) {
+                const float v = ldg(lin, e.valid ? (uint32_t)e.slot * qs + cell(e.delta) : own);
+                s = e.valid ? v : 0.0f;
             }
-            mu[Ks] = s;
+            const float l = ldg(lin, a.valid ? (uint32_t)a.slot * qs + cell(a.delta) : own);
+            mu[Ks] = a.valid ? s + l : s;
+            constexpr int q = opp(Ks);
+            const double f6 = a.inlet ? 6.0 * (double)wgt(q) * (double)l : 0.0;
+            sx += (double)cx(q) * f6;
+            sy += (double)cy(q) * f6;
+            inl = inl || a.inlet;
         }(),
         ...);
     if (inl) inflow_grad(G, z, T, sx, sy, gr0, gr1, gr2);
@@ -1093,15 +1096,16 @@ __device__ __forceinline__ void adjoint_gather_x(const Geo &G, const Shape &S, b
             const uint32_t pn = umin_u32((uint32_t)((int32_t)c + off_of(G, K)), last);
             if constexpr (cx(K) == -1) {
                 float v = ldg(lin, xlo ? (uint32_t)opp(K) * qs + c : (uint32_t)K * qs + pn);
+                // the outlet's second link, loaded by every lane (see adjoint_gather)
+                const float w = ldg(lin, (uint32_t)K * qs +
+                                             umin_u32((uint32_t)((int32_t)c + cy(K) * G.offy + cz(K) * G.offz), last));
                 if (xlo && inl) {
                     constexpr int q = opp(K);
                     const double f6 = 6.0 * (double)wgt(q) * (double)v;
                     sx += (double)cx(q) * f6;
                     sy += (double)cy(q) * f6;
                 }
-                if (xhi && out)
-                    v += ldg(lin, (uint32_t)K * qs +
-                                      umin_u32((uint32_t)((int32_t)c + cy(K) * G.offy + cz(K) * G.offz), last));
+                if (xhi && out) v += w;
                 mu[K] = v;
             } else if constexpr (cx(K) == 1) {
                 const float v = ldg(lin, xhi ? (uint32_t)opp(K) * qs + c : (uint32_t)K * qs + pn);

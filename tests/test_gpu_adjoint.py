@@ -222,8 +222,7 @@ def test_full_size_adjoint_first_steps(model, nodes, inplace):
 @pytest.mark.parametrize("model", ["bgk", "smagorinsky", "rr3"])
 def test_lambda_buffer_count_follows_the_layout(model):
     """One lambda buffer per instance with inplace=True, two with
-    inplace=False, for every collision model; by default one for BGK and two
-    for the other models."""
+    inplace=False (the default), for every collision model."""
     w = inputs.scaled(inputs.adjoint_case(steps=20, avg_len=10), 24, 12, 10, model=model, cs=0.1)
     solid = inputs.solid_mask(w)
     probes = _plane_probes(w, solid)
@@ -231,7 +230,7 @@ def test_lambda_buffer_count_follows_the_layout(model):
     x, a, th = sc.collocation(w)
     ens = sc.Ensemble([cg], [th[:2]], avg_begin=w.avg_start, avg_end=w.steps, fields=False, use_graph=False)
     try:
-        for inplace, n_buf in ((None, 1 if model == "bgk" else 2), (False, 2), (True, 1)):
+        for inplace, n_buf in ((None, 2), (False, 2), (True, 1)):
             kw = {} if inplace is None else {"inplace": inplace}
             run = CheckpointedAdjoint(ens, w.steps, 10, **kw)
             assert [len(b) for b in run.lam] == ([2, 2] if n_buf == 2 else [2, 0]), (inplace, run.lam)
