@@ -122,11 +122,11 @@ def _full_size_nodes(w0, solid, nodes, steps, label, variant=(128, 1, 1, 1)):
 def test_full_size_regularised_urban_first_steps():
     """The regularised-collision leg of the bench (13 Smolyak nodes of the
     256x128x64 urban box, regularised third-order collision with the
-    Smagorinsky tau_eff) in its launch shape: 24 steps, first and last node
-    against the oracle."""
+    Smagorinsky tau_eff) in its launch shape: 24 steps, every node against
+    the oracle."""
     w = inputs.scaled(inputs.urban_les(), 256, 128, 64, model="rr3")
     solid = inputs.solid_mask(w)
-    _full_size_nodes(inputs.scaled(w, w.nx, w.ny, w.nz, ramp=0), solid, (0, 12), 24, "regularised urban")
+    _full_size_nodes(inputs.scaled(w, w.nx, w.ny, w.nz, ramp=0), solid, range(13), 24, "regularised urban")
 
 
 def test_full_size_series_urban_through_an_hour_change():
@@ -144,12 +144,12 @@ def test_full_size_series_urban_through_an_hour_change():
 
 def test_full_size_gauss_hermite_first_steps():
     """The Gauss-Hermite leg of the bench (121 nodes of the 128x64x48 urban
-    box, series inflow) in its launch shape: 24 steps, the first, middle and
-    last node against the oracle."""
+    box, series inflow) in its launch shape: 24 steps, every fifth node (25
+    of 121, both ends of the rule included) against the oracle."""
     w = inputs.scaled(inputs.urban_gpc(hours=4, hour_steps=100, blend_steps=30), 128, 64, 48, ramp=0,
                       ref_height=48.0)
     solid = inputs.solid_mask(w)
-    _full_size_nodes(w, solid, (0, 60, 120), 24, "Gauss-Hermite urban")
+    _full_size_nodes(w, solid, range(0, 121, 5), 24, "Gauss-Hermite urban")
 
 
 def test_full_size_assimilation_real_ramp():
