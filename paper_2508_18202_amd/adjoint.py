@@ -35,6 +35,27 @@ from . import lbmsc as L
 from .sc import Ensemble, stream_handle
 
 
+def stored_tail(steps: int, ckpt: int, grouped: bool, store_all: Optional[bool], stored_steps: Optional[int],
+                per_step: int, free: Optional[int], memory_fraction: float = 0.6) -> int:
+    """Number of last steps the forward run records itself (host logic of
+    CheckpointedAdjoint): stored_steps if given (the run length or a multiple
+    of ckpt below it), every step or one segment for store_all True/False,
+    one segment for grouped sweeps, else as many whole segments as
+    memory_fraction of `free` bytes holds at `per_step` bytes per step (at
+    least one segment, at most the run)."""
+    if grouped:
+        if store_all:
+            raise ValueError("store_all needs the whole batch in one sweep (no group_size)")
+        return ckpt
+    if stored_steps is not None:
+        if stored_steps != steps and (stored_steps % ckpt or not ckpt <= stored_steps < steps):
+            raise ValueError("stored_steps must be the run length or a multiple of ckpt below it")
+        return stored_steps
+    if store_all is not None:
+        return steps if store_all else min(ckpt, steps)
+    return min(steps, max(ckpt, int(memory_fraction * free // per_step) // ckpt * ckpt))
+
+
 class CheckpointedAdjoint:
     """Forward run with snapshots and the reverse sweep over one Ensemble.
 
@@ -86,19 +107,10 @@ class CheckpointedAdjoint:
         # 13 x 128x64x48 adjoint case, 164 GB); store_all=True asks for every
         # step, False for one segment; grouped sweeps store one segment.
         per_step = 4 * sum(per_slot_of(ens.cases[ens.index[i][0]]) for i in range(n))
-        if self.grouped:
-            if store_all:
-                raise ValueError("store_all needs the whole batch in one sweep (no group_size)")
-            stored = ckpt
-        elif stored_steps is not None:
-            if stored_steps != steps and (stored_steps % ckpt or not ckpt <= stored_steps < steps):
-                raise ValueError("stored_steps must be the run length or a multiple of ckpt below it")
-            stored = stored_steps
-        elif store_all is None:
+        free = None
+        if not self.grouped and stored_steps is None and store_all is None:
             free = torch.cuda.mem_get_info()[0] + torch.cuda.memory_reserved() - torch.cuda.memory_allocated()
-            stored = min(steps, max(ckpt, int(memory_fraction * free // per_step) // ckpt * ckpt))
-        else:
-            stored = steps if store_all else ckpt
+        stored = stored_tail(steps, ckpt, self.grouped, store_all, stored_steps, per_step, free, memory_fraction)
         self.stored = stored
         self.store_all = stored >= steps
         self.n_slots = stored
