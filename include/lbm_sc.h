@@ -257,10 +257,11 @@ int lbm_collide_stream_record(lbm_plan *plan, int32_t n_steps, int32_t record_ki
                               float *const *rec_dev_host, int32_t n_slots, hipStream_t stream);
 /* The same recording run that also adds to the QoI sums like
  * lbm_collide_stream (not in the paper): the forward run of an adjoint sweep
- * that keeps the record of every step (n_slots >= the run length, slot n for
- * step n), so that the sweep needs no segment re-runs.  Memory: n_slots
- * records per instance (16, 76 or 64 B per cell and step for kinds 1, 2,
- * 3).  Same arguments and errors as lbm_collide_stream_record. */
+ * records its last steps itself (slot n % n_slots, as above), so that the
+ * sweep re-runs none of the segments those records cover; with n_slots at
+ * least the run length it keeps every step.  Memory: n_slots records per
+ * instance (16, 76 or 64 B per cell and step for kinds 1, 2, 3).  Same
+ * arguments and errors as lbm_collide_stream_record. */
 int lbm_collide_stream_record_qoi(lbm_plan *plan, int32_t n_steps, int32_t record_kind,
                                   float *const *rec_dev_host, int32_t n_slots, hipStream_t stream);
 
