@@ -329,3 +329,51 @@ def test_store_all_refused_for_grouped_sweeps():
         assert not CheckpointedAdjoint(ens, w.steps, 10, group_size=1).store_all
     finally:
         ens.close()
+
+
+def test_recording_run_with_qoi_equals_plain_and_recording_runs():
+    """lbm_collide_stream_record_qoi through the C ABI: the window averages,
+    probe averages and final populations equal those of lbm_collide_stream,
+    and its records (slot n % n_slots, here with a wrap) those of
+    lbm_collide_stream_record, bit for bit; a plain recording run adds
+    nothing to the QoI sums."""
+    w = inputs.scaled(inputs.urban_les(steps=40, avg_len=20), 48, 24, 20, ramp=10)
+    solid = inputs.solid_mask(w)
+    probes = _plane_probes(w, solid)
+    cg = sc.make_geometry(w, solid, probes)
+    x, a, th = sc.collocation(w)
+    s = sc.stream_handle()
+    res = {}
+    for mode in ("plain", "record_qoi", "record"):
+        ens = sc.Ensemble([cg], [th[:2]], avg_begin=w.avg_start, avg_end=w.steps, use_graph=False)
+        try:
+            n_slots = 40 if mode == "record" else 16       # 16: steps 24..39 in slots 8..15, 0..7
+            recs = [torch.zeros(n_slots * 19 * cg.qs, dtype=torch.float32, device="cuda") for _ in range(2)]
+            if mode == "plain":
+                ens.advance(w.steps)
+            elif mode == "record_qoi":
+                L.lbm_collide_stream_record_qoi(ens.plan, w.steps, L.RECORD_POPULATIONS,
+                                                [r.data_ptr() for r in recs], n_slots, s)
+            else:
+                L.lbm_collide_stream_record(ens.plan, w.steps, L.RECORD_POPULATIONS, [r.data_ptr() for r in recs],
+                                            n_slots, s)
+            out = []
+            for i in range(2):
+                q = torch.empty(cg.ncells, 4, dtype=torch.float32, device="cuda")
+                p = torch.empty(len(probes), dtype=torch.float32, device="cuda")
+                ens.averages_into(i, q, p)
+                out.append((q.cpu().numpy(), p.cpu().numpy(), ens.populations(i).cpu().numpy(),
+                            recs[i].view(n_slots, 19, cg.qs).cpu().numpy()))
+            res[mode] = out
+        finally:
+            ens.close()
+    for i in range(2):
+        q0, p0, f0, _ = res["plain"][i]
+        q1, p1, f1, r1 = res["record_qoi"][i]
+        q2, p2, f2, r2 = res["record"][i]
+        assert np.abs(p0).max() > 0 and np.abs(q0).max() > 0
+        assert np.array_equal(q0, q1) and np.array_equal(p0, p1) and np.array_equal(f0, f1)
+        assert np.array_equal(f0, f2)
+        assert not np.any(q2) and not np.any(p2)
+        for n in range(24, 40):
+            assert np.array_equal(r1[n % 16], r2[n]), n
