@@ -834,12 +834,15 @@ def main():
 
     checks = {}
 
-    def sc_pass(timing, check=False):
+    def sc_pass(timing, check=False, phases=None):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record()
         x, a, th = sc.collocation(w)                       # collocation rule + node parameters
         cg = sc.make_geometry(w, solid)
         ens = sc.Ensemble([cg], [th], avg_begin=w.avg_start, avg_end=w.steps,
                           use_graph=True, variant=variant)  # geometry + rest state of all nodes
         try:
+            ev[1].record()
             ens.advance(ramp)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -847,14 +850,21 @@ def main():
             ens.advance(plain)                              # pure collide-and-stream launches
             e1.record()
             ens.advance(w.steps - ramp - plain)             # QoI window
+            ev[2].record()
             q = torch.empty(len(ens), cg.ncells, 4, dtype=torch.float32, device="cuda")
             for j in range(len(ens)):
                 ens.averages_into(j, q[j])
+            ev[3].record()
             mean, var, nneg = sc.moments(q, a, count_negative=True)
+            ev[4].record()
             bad = ens.health()
             if bad >= 0:
                 raise RuntimeError(f"node {bad} went unstable")
             timing.append((e0, e1))
+            if phases is not None:
+                phases.append((ev, e0, e1))
+            if check:
+                last_q.update(q=q, a=a)
             if check:
                 # invariants of the full-length run: finite fields and moments,
                 # the mean density deviation of every node (sum of f - w over the
@@ -875,9 +885,11 @@ def main():
         progress(f"warm-up pass {k + 1}/{args.warmup}")
     torch.cuda.synchronize()
     timing = []
+    phases = []
+    last_q = {}
     t0 = time.perf_counter()
     for k in range(args.steps):
-        mean, var, n_inst = sc_pass(timing, check=(k == args.steps - 1))
+        mean, var, n_inst = sc_pass(timing, check=(k == args.steps - 1), phases=phases)
         progress(f"timed pass {k + 1}/{args.steps}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -892,6 +904,44 @@ def main():
     traffic, traffic_launch = load_traffic(launch_bytes)
     copy_gbs = copy_ceiling()
     props = torch.cuda.get_device_properties(0)
+    # where a pass's time goes (HIP events on the launch stream, mean over the
+    # timed passes): set-up (collocation, geometry, rest state), ramp, plain
+    # steps, the QoI window (each step also reads and writes the FP32 partial
+    # sums, +32 B per fluid cell, and every 64 states a flush into FP64), the
+    # window averages, and the FP64 moments of the 13 x 4 x cells values
+    win = w.steps - ramp - plain
+    ph = np.mean([[ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(e0), e0.elapsed_time(e1),
+                   e1.elapsed_time(ev[2]), ev[2].elapsed_time(ev[3]), ev[3].elapsed_time(ev[4])]
+                  for ev, e0, e1 in phases], axis=0) if phases else np.full(6, float("nan"))
+    n_el = 4 * int(np.prod(solid.shape))
+    breakdown = {
+        "setup_ms": round(float(ph[0]), 2), "ramp_ms": round(float(ph[1]), 2),
+        "plain_ms": round(float(ph[2]), 2), "window_ms": round(float(ph[3]), 2),
+        "averages_ms": round(float(ph[4]), 3), "moments_ms": round(float(ph[5]), 3),
+        "window_launch_us": round(float(ph[3]) * 1e3 / max(1, win), 2),
+        "window_gbs": round((BYTES_PER_CELL_UPDATE + 32) * n_inst * n_fluid / (float(ph[3]) / max(1, win) / 1e3) / 1e9, 1),
+    }
+    if last_q:
+        # the moments kernel alone on the last pass's window averages (the
+        # pass's moments phase also holds the count's copy to the host)
+        qq, aa = last_q["q"], np.ascontiguousarray(last_q["a"], dtype=np.float64)
+        mean_k = torch.empty(qq.shape[1:], dtype=torch.float64, device="cuda")
+        var_k = torch.empty_like(mean_k)
+        neg_k = torch.zeros(1, dtype=torch.int64, device="cuda")
+        n_q, n_e = qq.shape[0], qq[0].numel()
+        for rep_ in range(2):
+            k0 = torch.cuda.Event(enable_timing=True)
+            k1 = torch.cuda.Event(enable_timing=True)
+            k0.record()
+            for _ in range(20):
+                L.lbm_sc_moments(qq.data_ptr(), aa, n_q, n_e, mean_k.data_ptr(), var_k.data_ptr(),
+                                 neg_k.data_ptr(), sc.stream_handle())
+            k1.record()
+            k1.synchronize()
+        t_k = k0.elapsed_time(k1) / 20 / 1e3
+        breakdown["moments_kernel_us"] = round(t_k * 1e6, 1)
+        breakdown["moments_kernel_gbs"] = round((n_q * 4 + 16) * n_e / t_k / 1e9, 1)
+        del last_q["q"]
 
     out = {
         "metric": METRIC,
@@ -936,6 +986,7 @@ def main():
                              "frac": round(achieved / copy_gbs, 4)},
         },
         "kernel_mlups": round(n_inst * n_fluid / avg_launch_s / 1e6, 1),
+        "pass_breakdown": breakdown,
         "invariants": checks,
     }
 

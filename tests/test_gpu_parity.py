@@ -202,6 +202,33 @@ def test_moments_kernel_against_oracle():
         sc.moments(torch.zeros(3, 10, device="cuda"), np.array([0.2, 0.3, 0.6]))
 
 
+def test_moments_kernel_layouts():
+    """The moments kernel's element paths against the oracle: groups of four
+    (the vector path), a count not divisible by 4 (the per-element tail), a
+    4-byte-offset buffer (per-element path only), and more elements than one
+    pass of the grid covers (grid-stride)."""
+    rng = np.random.default_rng(5)
+    _, a13 = orc.smolyak_cc(2, 2)
+    s = sc.stream_handle()
+    for nq, n, offset in ((13, 3003, 0), (5, 4001, 0), (13, 4000, 1), (40, 2002, 1), (13, 4 * 4096 * 256 + 12, 0)):
+        a = a13 if nq == 13 else rng.random(nq)
+        a = a / a.sum()
+        q = (rng.standard_normal((nq, n)) * 0.01 + 0.05).astype(np.float32)
+        buf = torch.zeros(nq * n + offset, dtype=torch.float32, device="cuda")
+        buf[offset:] = torch.from_numpy(q.reshape(-1)).cuda()
+        mean = torch.empty(n + 1, dtype=torch.float64, device="cuda")
+        var = torch.empty(n + 1, dtype=torch.float64, device="cuda")
+        neg = torch.zeros(1, dtype=torch.int64, device="cuda")
+        L.lbm_sc_moments(buf.data_ptr() + 4 * offset, np.ascontiguousarray(a, dtype=np.float64), nq, n,
+                         mean.data_ptr() + 8 * offset, var.data_ptr() + 8 * offset, neg.data_ptr(), s)
+        eo, vo = orc.moments(q.astype(np.float64), a)
+        m = mean.cpu().numpy()[offset:offset + n]
+        v = var.cpu().numpy()[offset:offset + n]
+        assert np.abs(m - eo).max() < 1e-13, (nq, n, offset)
+        assert np.abs(v - vo).max() < 1e-13 * np.abs(vo).max() + 1e-18, (nq, n, offset)
+        assert int(neg.item()) == int((vo < 0).sum()), (nq, n, offset)
+
+
 def test_batched_uneven_matches_one_at_a_time():
     """Three box sizes x three nodes in one plan equal the same instances run
     as separate plans, bit for bit, and each matches the oracle."""
