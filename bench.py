@@ -112,6 +112,8 @@ def parse():
     ap.add_argument("--lbm-steps", type=int, default=20000, help="time steps per pass")
     ap.add_argument("--avg-len", type=int, default=5000, help="QoI averaging window")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0: autotuned shape)")
+    ap.add_argument("--cache-block", type=int, default=-1,
+                    help="MiB per instance block of plain stretches (-1: the library default, 0: off)")
     ap.add_argument("--cells-per-thread", type=int, default=1)
     ap.add_argument("--model", default="smagorinsky", help=argparse.SUPPRESS)
     ap.add_argument("--nontemporal", type=int, default=1, help="mask: 1 even steps, 2 odd steps")
@@ -834,13 +836,16 @@ def main():
 
     checks = {}
 
+    blocks_used = {"n": 0}
+
     def sc_pass(timing, check=False, phases=None):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
         ev[0].record()
         x, a, th = sc.collocation(w)                       # collocation rule + node parameters
         cg = sc.make_geometry(w, solid)
-        ens = sc.Ensemble([cg], [th], avg_begin=w.avg_start, avg_end=w.steps,
-                          use_graph=True, variant=variant)  # geometry + rest state of all nodes
+        ens = sc.Ensemble([cg], [th], avg_begin=w.avg_start, avg_end=w.steps, use_graph=True, variant=variant,
+                          cache_block=None if args.cache_block < 0 else args.cache_block << 20)
+        blocks_used["n"] = L.lbm_plan_cache_blocks(ens.plan)    # geometry + rest state of all nodes
         try:
             ev[1].record()
             ens.advance(ramp)
@@ -965,6 +970,7 @@ def main():
             "fluid_cells_per_instance": n_fluid,
             "launch": {"block": variant[0], "cells_per_thread": variant[1], "nontemporal": variant[2],
                        "xcd_order": variant[3]},
+            "cache_blocks": blocks_used["n"],
             "parallelism": "batched instances, 1 GPU",
             "device": {"name": props.name, "arch": getattr(props, "gcnArchName", ""),
                        "compute_units": props.multi_processor_count,

@@ -213,6 +213,21 @@ int lbm_plan_create(const lbm_instance *inst, int32_t n_inst, const lbm_plan_opt
 void lbm_plan_destroy(lbm_plan *plan);
 int64_t lbm_plan_step(const lbm_plan *plan);
 int lbm_plan_set_step(lbm_plan *plan, int64_t step);   /* even steps only (natural layout) */
+/* Instance blocks for the device's memory-side cache (not in the paper; a
+ * schedule of Sec. 2.4's independent runs): consecutive instances are
+ * grouped while their state (populations, per-cell flags and solid-link
+ * masks) fits `bytes`, and lbm_collide_stream advances stretches of plain
+ * steps (no ramp, series blend, QoI window or recording; captured graphs)
+ * one block at a time through the whole stretch, so that a block's state
+ * stays in the cache from step to step.  The results are bit-identical to
+ * the batched order: plain steps do not depend on the step index and the
+ * instances are independent.  Used when there are at least two blocks and
+ * every instance fits; default 192 MiB; 0 turns it off.  Synchronises the
+ * device.  LBM_E_INVALID for a negative size. */
+int lbm_plan_set_cache_block(lbm_plan *plan, int64_t bytes);
+/* Number of instance blocks in use (0: plain stretches advance the whole
+ * batch per step); -1 for a NULL plan. */
+int32_t lbm_plan_cache_blocks(const lbm_plan *plan);
 int lbm_plan_set_theta(lbm_plan *plan, int32_t inst, const float theta[3]);
 int lbm_plan_reset_qoi(lbm_plan *plan, hipStream_t stream);     /* zero QoI sums and health */
 int lbm_sync(lbm_plan *plan, hipStream_t stream);

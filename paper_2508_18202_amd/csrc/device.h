@@ -592,7 +592,7 @@ template <int BS, int CPT, bool NT, int MODEL, int PARITY>
 __global__ __launch_bounds__(BS) void k_step(const Geo *__restrict__ geo, const int32_t *__restrict__ tile_inst,
                                              int32_t n_tiles, StepArgs a, int32_t *__restrict__ health)
 {
-    const int tile = tile_of(a.xcd_remap);
+    const int tile = a.tile_base + tile_of(a.xcd_remap);
     if (tile >= n_tiles) return;
     const int ii = __builtin_amdgcn_readfirstlane(tile_inst[tile]);
     const Geo &G = geo[ii];

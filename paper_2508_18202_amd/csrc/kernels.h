@@ -48,6 +48,7 @@ struct StepArgs {
     int32_t accumulate;        // add this state's QoIs to the window sums
     int32_t record;            // 0 none, 1 (rho,u), 2 populations, 3 regularised state
     int32_t xcd_remap;         // tile order over the XCDs (set from the variant, see tile_of)
+    int32_t tile_base;         // first tile of this launch (the launch covers tile_base .. n_tiles - 1)
     float *const *rec;         // device array [n_inst] of record buffer bases
     int64_t rec_slot;          // slot index n % n_slots
     const uint64_t *tinfo;     // per tile, two words (see launch_tile_info)

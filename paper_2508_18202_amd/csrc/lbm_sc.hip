@@ -194,12 +194,46 @@ struct lbm_plan {
     bool use_graph = false;
     hipGraphExec_t gexec = nullptr;
     int graph_pairs = 8;
+    // instance blocks for the memory-side cache: consecutive instances whose
+    // state fits block_bytes; plain stretches advance one block at a time
+    // (used when there are two blocks or more and every instance fits)
+    int64_t block_bytes = int64_t(192) << 20;
+    std::vector<std::pair<int32_t, int32_t>> blocks;   // tile ranges [begin, end)
+    std::vector<hipGraphExec_t> bexec;
     std::map<std::vector<uintptr_t>, void *> tables;
     double *gpart_d = nullptr;   // per-tile adjoint gradient partials [gpart_tiles][3]
     int32_t gpart_tiles = 0;
 };
 
 namespace {
+
+// Instance blocks (see lbm_plan::block_bytes): the state one step touches
+// per instance is its populations and per-cell flags and solid-link masks.
+int build_blocks(lbm_plan *p)
+{
+    for (auto e : p->bexec) HIPCHK(hipGraphExecDestroy(e));
+    p->bexec.clear();
+    p->blocks.clear();
+    if (p->block_bytes <= 0) return LBM_OK;
+    std::vector<std::pair<int32_t, int32_t>> b;
+    int64_t used = 0;
+    for (int i = 0; i < p->n_inst; ++i) {
+        const Geo &g = p->geo_h[i];
+        const int64_t bytes = (int64_t)Q * 4 * g.qs + 5 * (int64_t)g.ncells;
+        if (bytes > p->block_bytes) return LBM_OK;          // an instance alone overflows the cache
+        const int32_t t0 = g.tile0;
+        const int32_t t1 = i + 1 < p->n_inst ? p->geo_h[i + 1].tile0 : p->n_tiles;
+        if (b.empty() || used + bytes > p->block_bytes) {
+            b.push_back({t0, t1});
+            used = 0;
+        } else {
+            b.back().second = t1;
+        }
+        used += bytes;
+    }
+    if (b.size() >= 2) p->blocks = b;
+    return LBM_OK;
+}
 
 int build_tiles(lbm_plan *p)
 {
@@ -229,7 +263,7 @@ int build_tiles(lbm_plan *p)
         HIPCHK(hipGraphExecDestroy(p->gexec));
         p->gexec = nullptr;
     }
-    return LBM_OK;
+    return build_blocks(p);
 }
 
 void set_theta(Geo &g, const lbm_instance &in)
@@ -321,6 +355,32 @@ int ensure_graph(lbm_plan *p)
     return LBM_OK;
 }
 
+int ensure_block_graphs(lbm_plan *p)
+{
+    if (!p->bexec.empty()) return LBM_OK;
+    hipStream_t cap;
+    HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    for (auto &bl : p->blocks) {
+        StepArgs a{};
+        a.step = (p->steady_from + 1) / 2 * 2 + 2;
+        a.tinfo = p->tinfo_d;
+        a.tile_base = bl.first;
+        HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < p->graph_pairs; ++k) {
+            launch_step(p->v, p->model, 0, p->geo_d, p->tiles_d, bl.second, a, p->health_d, cap);
+            launch_step(p->v, p->model, 1, p->geo_d, p->tiles_d, bl.second, a, p->health_d, cap);
+        }
+        hipGraph_t g;
+        HIPCHK(hipStreamEndCapture(cap, &g));
+        hipGraphExec_t e;
+        HIPCHK(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
+        HIPCHK(hipGraphDestroy(g));
+        p->bexec.push_back(e);
+    }
+    HIPCHK(hipStreamDestroy(cap));
+    return LBM_OK;
+}
+
 bool pair_plain(const lbm_plan *p, int64_t n)
 {
     for (int64_t m = n; m < n + 2; ++m) {
@@ -344,6 +404,22 @@ int run_steps(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_d, i
         if (p->use_graph && kind == 0 && (n & 1) == 0 && left >= 2 * p->graph_pairs) {
             bool plain = true;
             for (int k = 0; k < p->graph_pairs && plain; ++k) plain = pair_plain(p, n + 2 * k);
+            if (plain && !p->blocks.empty()) {
+                // the whole plain stretch one instance block at a time: the
+                // steps of a stretch do not depend on the step index, so each
+                // instance takes them in order while its state stays in the
+                // memory-side cache
+                int64_t pairs = 0;
+                while (2 * (pairs + 1) <= left && pair_plain(p, n + 2 * pairs)) ++pairs;
+                pairs -= pairs % p->graph_pairs;
+                int r = ensure_block_graphs(p);
+                if (r) return r;
+                for (auto e : p->bexec)
+                    for (int64_t k = 0; k < pairs; k += p->graph_pairs) HIPCHK(hipGraphLaunch(e, s));
+                p->step += 2 * pairs;
+                left -= (int32_t)(2 * pairs);
+                continue;
+            }
             if (plain) {
                 int r = ensure_graph(p);
                 if (r) return r;
@@ -740,6 +816,7 @@ void lbm_plan_destroy(lbm_plan *p)
     if (!p) return;
     (void)hipDeviceSynchronize();
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    for (auto e : p->bexec) (void)hipGraphExecDestroy(e);
     for (auto &kv : p->tables) (void)hipFree(kv.second);
     if (p->geo_d) (void)hipFree(p->geo_d);
     if (p->tiles_d) (void)hipFree(p->tiles_d);
@@ -750,6 +827,18 @@ void lbm_plan_destroy(lbm_plan *p)
 }
 
 int64_t lbm_plan_step(const lbm_plan *p) { return p ? p->step : -1; }
+
+int lbm_plan_set_cache_block(lbm_plan *p, int64_t bytes)
+{
+    int r = check_plan(p);
+    if (r) return r;
+    if (bytes < 0) return fail(LBM_E_INVALID, "negative cache block size");
+    HIPCHK(hipDeviceSynchronize());                 // block graphs may still be in flight
+    p->block_bytes = bytes;
+    return build_blocks(p);
+}
+
+int32_t lbm_plan_cache_blocks(const lbm_plan *p) { return p ? (int32_t)p->blocks.size() : -1; }
 
 int lbm_plan_set_step(lbm_plan *p, int64_t step)
 {

@@ -18,7 +18,7 @@ template <int BS, int CPT, bool NT>
 void step_v(int parity, const Geo *geo, const int32_t *ti, int32_t nt, const StepArgs &a, int32_t *h,
             hipStream_t s)
 {
-    const dim3 grid(grid_of(nt)), block(BS);
+    const dim3 grid(grid_of(nt - a.tile_base)), block(BS);
     if (parity == 0) hipLaunchKernelGGL((k_step<BS, CPT, NT, M, 0>), grid, block, 0, s, geo, ti, nt, a, h);
     else hipLaunchKernelGGL((k_step<BS, CPT, NT, M, 1>), grid, block, 0, s, geo, ti, nt, a, h);
 }

@@ -78,6 +78,8 @@ _SIGS = [
     ("lbm_plan_destroy", None, [_P]),
     ("lbm_plan_step", ctypes.c_int64, [_P]),
     ("lbm_plan_set_step", ctypes.c_int, [_P, ctypes.c_int64]),
+    ("lbm_plan_set_cache_block", ctypes.c_int, [_P, ctypes.c_int64]),
+    ("lbm_plan_cache_blocks", ctypes.c_int32, [_P]),
     ("lbm_plan_set_theta", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_float * 3]),
     ("lbm_plan_reset_qoi", ctypes.c_int, [_P, _P]),
     ("lbm_sync", ctypes.c_int, [_P, _P]),
@@ -272,6 +274,15 @@ def lbm_plan_autotune(plan, stream: int):
     v = (ctypes.c_int32 * 4)()
     _check(lib().lbm_plan_autotune(plan, stream, v))
     return tuple(v)
+
+
+def lbm_plan_set_cache_block(plan, nbytes: int):
+    """Byte budget of the instance blocks that take plain stretches one at a time (0: off)."""
+    _check(lib().lbm_plan_set_cache_block(plan, int(nbytes)))
+
+
+def lbm_plan_cache_blocks(plan) -> int:
+    return int(lib().lbm_plan_cache_blocks(plan))
 
 
 def lbm_collide_stream(plan, n_steps: int, stream: int):

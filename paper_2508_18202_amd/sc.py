@@ -70,7 +70,8 @@ class Ensemble:
 
     def __init__(self, cases: Sequence[CaseGeometry], thetas: Sequence[Sequence[Sequence[float]]],
                  avg_begin: int = 0, avg_end: int = 0, fields: bool = True, probe_sums: bool = True,
-                 use_graph: bool = True, block: int = 0, variant: Optional[Sequence[int]] = None):
+                 use_graph: bool = True, block: int = 0, variant: Optional[Sequence[int]] = None,
+                 cache_block: Optional[int] = None):
         self.cases = list(cases)
         self.index: List[Tuple[int, int]] = []
         self.f: List[torch.Tensor] = []
@@ -127,6 +128,8 @@ class Ensemble:
         v = tuple(variant) if variant is not None else (block, 0, 1, 0)
         v = v + (0,) * (4 - len(v))
         self.plan = L.lbm_plan_create(insts, avg_begin, avg_end, use_graph, *v)
+        if cache_block is not None:          # bytes per instance block (0: the whole batch per step)
+            L.lbm_plan_set_cache_block(self.plan, cache_block)
         L.lbm_plan_reset_qoi(self.plan, stream_handle())
 
     def reset(self):

@@ -229,6 +229,46 @@ def test_moments_kernel_layouts():
         assert int(neg.item()) == int((vo < 0).sum()), (nq, n, offset)
 
 
+def test_cache_blocks_equal_the_batched_order():
+    """Plain stretches advanced one instance block at a time give bitwise the
+    populations and window averages of the whole batch per step (ramp, plain
+    stretch and QoI window; three blocks of five nodes)."""
+    w = inputs.scaled(inputs.urban_les(steps=100, avg_len=20), 48, 24, 20, ramp=10)
+    solid = inputs.solid_mask(w)
+    probes = inputs.probe_cells(w, solid)
+    cg = sc.make_geometry(w, solid, probes)
+    x, a, th = sc.collocation(w)
+    per_inst = 19 * 4 * cg.qs + 5 * cg.ncells
+    out = {}
+    for budget in (0, 2 * per_inst + 1):
+        ens = sc.Ensemble([cg], [th[:5]], avg_begin=w.avg_start, avg_end=w.steps, use_graph=True,
+                          variant=(128, 1, 1, 1), cache_block=budget)
+        try:
+            assert L.lbm_plan_cache_blocks(ens.plan) == (0 if budget == 0 else 3)
+            ens.advance(w.steps)
+            assert ens.health() == -1
+            res = []
+            for i in range(len(ens)):
+                q = torch.empty(cg.ncells, 4, dtype=torch.float32, device="cuda")
+                pq = torch.empty(len(probes), dtype=torch.float32, device="cuda")
+                ens.averages_into(i, q, pq)
+                res.append((ens.populations(i).cpu().numpy(), q.cpu().numpy(), pq.cpu().numpy()))
+            out[budget] = res
+        finally:
+            ens.close()
+    (r0, r1) = out.values()
+    for i in range(5):
+        for u, v in zip(r0[i], r1[i]):
+            assert np.array_equal(u, v), i
+    assert np.abs(r0[0][1]).max() > 0
+    ens = sc.Ensemble([cg], [th[:2]], use_graph=True)
+    try:
+        with pytest.raises(L.LbmError):
+            L.lbm_plan_set_cache_block(ens.plan, -1)
+    finally:
+        ens.close()
+
+
 def test_batched_uneven_matches_one_at_a_time():
     """Three box sizes x three nodes in one plan equal the same instances run
     as separate plans, bit for bit, and each matches the oracle."""
