@@ -217,11 +217,13 @@ int lbm_plan_set_step(lbm_plan *plan, int64_t step);   /* even steps only (natur
  * schedule of Sec. 2.4's independent runs): consecutive instances are
  * grouped while their state (populations, per-cell flags and solid-link
  * masks) fits `bytes`, and lbm_collide_stream advances stretches of plain
- * steps (no ramp, series blend, QoI window or recording; captured graphs)
- * one block at a time through the whole stretch, so that a block's state
- * stays in the cache from step to step.  The results are bit-identical to
- * the batched order: plain steps do not depend on the step index and the
- * instances are independent.  Used when there are at least two blocks and
+ * steps (captured graphs) one block at a time through the whole stretch,
+ * and ramp, blend and QoI-window steps one block at a time in chunks (ending
+ * where the accumulation starts or stops, at the window's last state and
+ * every 64 accumulated states, where the batch-wide flush falls), so that a
+ * block's state stays in the cache from step to step.  The results are
+ * bit-identical to the batched order: the instances are independent and
+ * each cell's sums keep their order.  Recording runs keep the batched order.  Used when there are at least two blocks and
  * every instance fits; default 192 MiB; 0 turns it off.  Synchronises the
  * device.  LBM_E_INVALID for a negative size. */
 int lbm_plan_set_cache_block(lbm_plan *plan, int64_t bytes);

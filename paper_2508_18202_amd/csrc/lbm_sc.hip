@@ -429,6 +429,56 @@ int run_steps(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_d, i
                 continue;
             }
         }
+        if (kind == 0 && !p->blocks.empty()) {
+            // ramp, blend and window steps one instance block at a time too,
+            // in chunks of steps with per-step arguments: a chunk ends where
+            // the QoI accumulation starts or stops, at the window's last
+            // state (captured batch-wide), where the steady inflow begins,
+            // after the states the FP32 partials may hold before the
+            // (batch-wide) flush, so the sums keep their order, and past the
+            // steady inflow's start at the next even step (plain stretches
+            // take the graphs above)
+            const bool acc = step_accumulates(p, n);
+            const bool window = p->avg_end > p->avg_begin;
+            int32_t chunk = 0;
+            for (; chunk < left; ++chunk) {
+                const int64_t m = n + chunk;
+                if (step_accumulates(p, m) != acc) break;
+                if (n < p->steady_from && m >= p->steady_from) break;
+                if (acc && p->pending + chunk >= p->flush_every) break;
+                if (chunk > 0 && window && m == p->avg_end) break;
+                if (chunk > 0 && !acc && m >= p->steady_from && (m & 1) == 0) break;
+            }
+            if (chunk >= 2) {
+                for (auto &bl : p->blocks) {
+                    for (int32_t k = 0; k < chunk; ++k) {
+                        StepArgs a{};
+                        a.step = n + k;
+                        a.tinfo = p->tinfo_d;
+                        a.accumulate = acc ? 1 : 0;
+                        a.tile_base = bl.first;
+                        if (launch_step(p->v, p->model, (int)((n + k) & 1), p->geo_d, p->tiles_d, bl.second, a,
+                                        p->health_d, s))
+                            return fail(LBM_E_HIP, "step launch failed: %s", hipGetErrorString(hipGetLastError()));
+                    }
+                }
+                p->step = n + chunk;
+                left -= chunk;
+                if (acc) p->pending += chunk;
+                if (p->avg_end > p->avg_begin && p->step == p->avg_end && p->step > p->avg_begin) {
+                    if (launch_capture(p->v.tile(), (int)(p->step & 1), p->geo_d, p->tiles_d, p->n_tiles, p->step,
+                                       p->health_d, s))
+                        return fail(LBM_E_HIP, "capture launch failed");
+                    ++p->pending;
+                    int r = flush(p, s);
+                    if (r) return r;
+                } else if (p->pending >= p->flush_every) {
+                    int r = flush(p, s);
+                    if (r) return r;
+                }
+                continue;
+            }
+        }
         StepArgs a{};
         a.step = n;
         a.tinfo = p->tinfo_d;

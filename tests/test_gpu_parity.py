@@ -229,11 +229,17 @@ def test_moments_kernel_layouts():
         assert int(neg.item()) == int((vo < 0).sum()), (nq, n, offset)
 
 
-def test_cache_blocks_equal_the_batched_order():
-    """Plain stretches advanced one instance block at a time give bitwise the
-    populations and window averages of the whole batch per step (ramp, plain
-    stretch and QoI window; three blocks of five nodes)."""
-    w = inputs.scaled(inputs.urban_les(steps=100, avg_len=20), 48, 24, 20, ramp=10)
+@pytest.mark.parametrize("inflow", ["loglaw", "series"])
+def test_cache_blocks_equal_the_batched_order(inflow):
+    """Steps advanced one instance block at a time (plain stretches from
+    graphs, ramp, blend and window steps in chunks) give bitwise the
+    populations and window averages of the whole batch per step (three
+    blocks of five nodes; a window of 150 states, flushed every 64)."""
+    if inflow == "loglaw":
+        w = inputs.scaled(inputs.urban_les(steps=220, avg_len=150), 48, 24, 20, ramp=10)
+    else:
+        w = inputs.scaled(inputs.urban_series(hours=3, hour_steps=40, blend_steps=15), 48, 24, 20, ramp=10,
+                          steps=220, avg_start=70)
     solid = inputs.solid_mask(w)
     probes = inputs.probe_cells(w, solid)
     cg = sc.make_geometry(w, solid, probes)
