@@ -978,7 +978,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "collide_stream (even/odd in-place pair, Smagorinsky)",
+            "kernel": "collide_stream (even/odd in-place pair, Smagorinsky); a launch is one time step of the "
+                      "batch (one dispatch per instance block when the plan uses cache blocks)",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -986,6 +987,7 @@ def main():
             "traffic": traffic,
             "traffic_launch": traffic_launch,
             "avg_launch_us": round(avg_launch_s * 1e6, 2),
+            "dispatches_per_launch": max(1, blocks_used["n"]),
             "algorithmic_bytes_per_launch": launch_bytes,
             "copy_ceiling": {"value": round(copy_gbs, 1), "unit": "GB/s",
                              "kernel": "hipMemcpyAsync device to device, 2 GiB, best of 5",
