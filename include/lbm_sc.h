@@ -238,10 +238,12 @@ int lbm_sync(lbm_plan *plan, hipStream_t stream);
 int lbm_check_health(lbm_plan *plan, hipStream_t stream, int32_t *bad_inst);
 /* Launch shape of the step kernels: variant_out = {block, cells_per_thread,
  * nontemporal, xcd_order}.  lbm_plan_autotune times step pairs of every shape on the
- * batch (populations, step counter and QoI sums are restored afterwards),
- * keeps the fastest and caches it in the JSON file named by LBMSC_TUNE_CACHE
- * (default ~/.cache/lbmsc_tune.json), keyed by architecture, model, instance
- * count and box sizes. */
+ * batch in the order plain stretches run (with instance blocks, each block
+ * through its own pairs in turn; populations, step counter and QoI sums are
+ * restored afterwards), keeps the fastest and caches it in the JSON file named
+ * by LBMSC_TUNE_CACHE (default ~/.cache/lbmsc_tune.json), keyed by
+ * architecture, model, instance count, instance-block count and box sizes.
+ * Call it after lbm_plan_set_cache_block when both are used. */
 int lbm_plan_variant(const lbm_plan *plan, int32_t variant_out[4]);
 int lbm_plan_autotune(lbm_plan *plan, hipStream_t stream, int32_t variant_out[4]);
 

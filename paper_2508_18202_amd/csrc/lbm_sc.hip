@@ -529,7 +529,7 @@ std::string tune_key(const lbm_plan *p)
     std::ostringstream os;
     // the build stamp keeps results of an older kernel build from being reused
     os << std::string(prop.gcnArchName).substr(0, 6) << "|" << __DATE__ << " " << __TIME__ << "|m" << p->model
-       << "|n" << p->n_inst;
+       << "|n" << p->n_inst << "|b" << p->blocks.size();
     // run-length encoded multiset of box sizes
     for (size_t i = 0; i < dims.size();) {
         size_t j = i;
@@ -1211,22 +1211,33 @@ int lbm_plan_autotune(lbm_plan *p, hipStream_t s, int32_t variant_out[4])
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         const Variant saved = p->v;
-        // time `pairs` step pairs (after two untimed ones) of shape v
+        // time `pairs` step pairs (after two untimed ones) of shape v, in the
+        // order plain stretches run: the whole batch per step, or with
+        // instance blocks each block through its own pairs in turn (the
+        // times of the blocks summed)
         auto time_pairs = [&](const Variant &v, int pairs, float &ms) -> int {
             p->v = v;
             int rc = build_tiles(p);
             if (rc) return rc;
+            std::vector<std::pair<int32_t, int32_t>> ranges = p->blocks;
+            if (ranges.empty()) ranges.push_back({0, p->n_tiles});
             StepArgs a{};
             a.step = p->steady_from + 2;
             a.tinfo = p->tinfo_d;
-            for (int w = 0; w < 2 + pairs; ++w) {
-                if (w == 2) HIPCHK(hipEventRecord(e0, s));
-                launch_step(v, p->model, 0, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
-                launch_step(v, p->model, 1, p->geo_d, p->tiles_d, p->n_tiles, a, p->health_d, s);
+            ms = 0.f;
+            for (const auto &rg : ranges) {
+                a.tile_base = rg.first;
+                for (int w = 0; w < 2 + pairs; ++w) {
+                    if (w == 2) HIPCHK(hipEventRecord(e0, s));
+                    launch_step(v, p->model, 0, p->geo_d, p->tiles_d, rg.second, a, p->health_d, s);
+                    launch_step(v, p->model, 1, p->geo_d, p->tiles_d, rg.second, a, p->health_d, s);
+                }
+                HIPCHK(hipEventRecord(e1, s));
+                HIPCHK(hipEventSynchronize(e1));
+                float t = 0.f;
+                HIPCHK(hipEventElapsedTime(&t, e0, e1));
+                ms += t;
             }
-            HIPCHK(hipEventRecord(e1, s));
-            HIPCHK(hipEventSynchronize(e1));
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
             return 0;
         };
         // coarse pass over every shape, then the six fastest re-timed three

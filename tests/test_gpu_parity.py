@@ -314,12 +314,14 @@ def test_batched_uneven_matches_one_at_a_time():
             i += 1
 
 
-def test_autotune_restores_state(tmp_path, monkeypatch):
-    """The launch-shape autotuner times every shape on the live batch and then
-    restores populations and step counter: continuing afterwards gives the
-    same populations bit for bit as a plan that was never tuned; the second
-    call is served from the cache file, written into directories the library
-    creates."""
+@pytest.mark.parametrize("cache_block", [None, 4 << 20])
+def test_autotune_restores_state(tmp_path, monkeypatch, cache_block):
+    """The launch-shape autotuner times every shape on the live batch (with
+    4 MiB instance blocks: one instance per block, each block through its own
+    step pairs) and then restores populations and step counter: continuing
+    afterwards gives the same populations bit for bit as a plan that was
+    never tuned; the second call is served from the cache file, written into
+    directories the library creates."""
     cache = tmp_path / "cache" / "lbmsc" / "tune.json"
     monkeypatch.setenv("LBMSC_TUNE_CACHE", str(cache))
     w = inputs.scaled(inputs.urban_les(), 64, 32, 24, ramp=4)
@@ -327,8 +329,9 @@ def test_autotune_restores_state(tmp_path, monkeypatch):
     _, _, th = sc.collocation(w)
     outs = []
     for tune in (False, True):
-        ens, _ = _ensemble(w, solid, th[:3], variant=(256, 1, 0, 0), use_graph=tune)
+        ens, _ = _ensemble(w, solid, th[:3], variant=(256, 1, 0, 0), use_graph=tune, cache_block=cache_block)
         try:
+            assert L.lbm_plan_cache_blocks(ens.plan) == (0 if cache_block is None else 3)
             ens.advance(6)
             before = [ens.populations(i).cpu().numpy() for i in range(3)]
             if tune:
