@@ -429,25 +429,28 @@ int run_steps(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_d, i
                 continue;
             }
         }
-        if (kind == 0 && !p->blocks.empty()) {
-            // ramp, blend and window steps one instance block at a time too,
-            // in chunks of steps with per-step arguments: a chunk ends where
-            // the QoI accumulation starts or stops, at the window's last
-            // state (captured batch-wide), where the steady inflow begins,
-            // after the states the FP32 partials may hold before the
-            // (batch-wide) flush, so the sums keep their order, and past the
-            // steady inflow's start at the next even step (plain stretches
-            // take the graphs above)
-            const bool acc = step_accumulates(p, n);
-            const bool window = p->avg_end > p->avg_begin;
+        if (!p->blocks.empty()) {
+            // ramp, blend and window steps, and every step of a recording
+            // run, one instance block at a time too, in chunks of steps with
+            // per-step arguments: a chunk ends where the QoI accumulation
+            // starts or stops, at the window's last state (captured
+            // batch-wide), where the steady inflow begins, after the states
+            // the FP32 partials may hold before the (batch-wide) flush, so
+            // the sums keep their order, and, in runs that do not record,
+            // past the steady inflow's start at the next even step (plain
+            // stretches take the graphs above).  Records are per instance
+            // (slot n % n_slots), so each instance writes the same records
+            // in the same order as in the batched order.
+            const bool acc = sums && step_accumulates(p, n);
+            const bool window = sums && p->avg_end > p->avg_begin;
             int32_t chunk = 0;
             for (; chunk < left; ++chunk) {
                 const int64_t m = n + chunk;
-                if (step_accumulates(p, m) != acc) break;
+                if ((sums && step_accumulates(p, m)) != acc) break;
                 if (n < p->steady_from && m >= p->steady_from) break;
                 if (acc && p->pending + chunk >= p->flush_every) break;
                 if (chunk > 0 && window && m == p->avg_end) break;
-                if (chunk > 0 && !acc && m >= p->steady_from && (m & 1) == 0) break;
+                if (kind == 0 && chunk > 0 && !acc && m >= p->steady_from && (m & 1) == 0) break;
             }
             if (chunk >= 2) {
                 for (auto &bl : p->blocks) {
@@ -456,6 +459,9 @@ int run_steps(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_d, i
                         a.step = n + k;
                         a.tinfo = p->tinfo_d;
                         a.accumulate = acc ? 1 : 0;
+                        a.record = kind;
+                        a.rec = rec_d;
+                        a.rec_slot = kind ? (int32_t)((n + k) % n_slots) : 0;
                         a.tile_base = bl.first;
                         if (launch_step(p->v, p->model, (int)((n + k) & 1), p->geo_d, p->tiles_d, bl.second, a,
                                         p->health_d, s))
@@ -465,7 +471,7 @@ int run_steps(lbm_plan *p, int32_t n_steps, int32_t kind, float *const *rec_d, i
                 p->step = n + chunk;
                 left -= chunk;
                 if (acc) p->pending += chunk;
-                if (p->avg_end > p->avg_begin && p->step == p->avg_end && p->step > p->avg_begin) {
+                if (window && p->step == p->avg_end && p->step > p->avg_begin) {
                     if (launch_capture(p->v.tile(), (int)(p->step & 1), p->geo_d, p->tiles_d, p->n_tiles, p->step,
                                        p->health_d, s))
                         return fail(LBM_E_HIP, "capture launch failed");

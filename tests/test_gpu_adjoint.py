@@ -331,12 +331,15 @@ def test_store_all_refused_for_grouped_sweeps():
         ens.close()
 
 
-def test_recording_run_with_qoi_equals_plain_and_recording_runs():
+@pytest.mark.parametrize("cache_block", [None, 2 << 20], ids=["batched", "blocks"])
+def test_recording_run_with_qoi_equals_plain_and_recording_runs(cache_block):
     """lbm_collide_stream_record_qoi through the C ABI: the window averages,
     probe averages and final populations equal those of lbm_collide_stream,
     and its records (slot n % n_slots, here with a wrap) those of
     lbm_collide_stream_record, bit for bit; a plain recording run adds
-    nothing to the QoI sums."""
+    nothing to the QoI sums.  With 2 MiB instance blocks (one instance per
+    block) the recording runs go block by block and still match the plain
+    run in the batched order."""
     w = inputs.scaled(inputs.urban_les(steps=40, avg_len=20), 48, 24, 20, ramp=10)
     solid = inputs.solid_mask(w)
     probes = _plane_probes(w, solid)
@@ -345,8 +348,10 @@ def test_recording_run_with_qoi_equals_plain_and_recording_runs():
     s = sc.stream_handle()
     res = {}
     for mode in ("plain", "record_qoi", "record"):
-        ens = sc.Ensemble([cg], [th[:2]], avg_begin=w.avg_start, avg_end=w.steps, use_graph=False)
+        ens = sc.Ensemble([cg], [th[:2]], avg_begin=w.avg_start, avg_end=w.steps, use_graph=False,
+                          cache_block=None if mode == "plain" else cache_block)
         try:
+            assert L.lbm_plan_cache_blocks(ens.plan) == (2 if mode != "plain" and cache_block else 0)
             n_slots = 40 if mode == "record" else 16       # 16: steps 24..39 in slots 8..15, 0..7
             recs = [torch.zeros(n_slots * 19 * cg.qs, dtype=torch.float32, device="cuda") for _ in range(2)]
             if mode == "plain":
