@@ -227,7 +227,7 @@ int lbm_plan_set_step(lbm_plan *plan, int64_t step);   /* even steps only (natur
  * (lbm_collide_stream_record, lbm_collide_stream_record_qoi) go one block at
  * a time in chunks as well; records are per instance, so each instance
  * writes the same records in the same order.  Used when there are at least
- * two blocks and every instance fits; default 192 MiB; 0 turns it off.
+ * two blocks and every instance fits; default 224 MiB; 0 turns it off.
  * Synchronises the device.  LBM_E_INVALID for a negative size. */
 int lbm_plan_set_cache_block(lbm_plan *plan, int64_t bytes);
 /* Number of instance blocks in use (0: plain stretches advance the whole
